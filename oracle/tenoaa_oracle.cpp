@@ -1,0 +1,884 @@
+// TENO-AA8 / TENO-AA10 compressible-Euler right-hand side: the ORACLE.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is a plain, serial, slow FP64 CPU
+// implementation of L. Fu, "Very-high-order TENO schemes with adaptive
+// accuracy order and adaptive dissipation control" (arXiv 2109.14340), written
+// so that a reader can check every step against the paper by eye.  Only the
+// test suite, the smoke check and the benchmark's CPU-baseline leg load it.
+// It shares no code, header or table with the GPU library; the two are
+// written independently against the same paper and the same written
+// evaluation order (below), and the tests compare them.
+//
+// What it computes (paper section in brackets):
+//   * smoothness indicators beta_{k,r} by their definition: the Jiang-Shu
+//     integral of the squared derivatives of the candidate polynomial over
+//     the cell [x_{i-1/2}, x_{i+1/2}] (Sec. 3.2, eq. for beta_{k,r}), the
+//     polynomial being the one whose cell averages over the stencil equal the
+//     data (Sec. 2, primitive-function definition).  The integral is taken
+//     exactly with Gauss-Legendre quadrature on the Newton form of the
+//     primitive, so constants give exactly zero;
+//   * scale separation gamma_k = 1/(beta_k+eps)^q, q = 7, eps = 1e-40 (Sec. 3.2);
+//   * the ENO-like selection cascade over the groups (S0,S1,S2,Sp) from the
+//     largest large stencil down, the TENO5 fallback with renormalised d_k
+//     (Sec. 3.3), and TENO8-AA = TENO10-AA without S5 (Sec. 4.3);
+//   * the adaptive cut-off C_T from the first-order undivided-difference
+//     measure eta, m, g(m), [beta] (Sec. 3.4);
+//   * the optimised linear schemes and candidate fluxes (Sec. 4.1, 4.2);
+//   * Roe-averaged characteristic projection, LLF or Rusanov splitting,
+//     SSP-RK3, dimension-by-dimension sweeps (Sec. 5 opening paragraph);
+//   * ghost cells for periodic, outflow, slip and no-slip walls (Appendix A;
+//     outflow is the zeroth-order copy reading);
+//   * the positivity-preserving flux limiter of Hu, Adams & Shu 2013 that the
+//     paper applies in its extreme cases (Sec. 5.3 opening paragraph), in
+//     the reading stated at or_limit_face below.
+//
+// Evaluation order.  The GPU path must reproduce, bit for bit, every value
+// that feeds a threshold decision (the split characteristic fluxes), so this
+// file fixes one order for each formula: the order written here, with no
+// contraction (build with -ffp-contract=off) and std::fma only where it is
+// spelled out.  The smoothness indicators, gamma, chi and the C_T bucket are
+// decision-only quantities; the GPU may evaluate them differently and the
+// tests then allow disagreement only where this file reports a decision
+// within a relative 1e-12 of its threshold ("margin").
+//
+// The numerical core is templated on the scalar type so that a complex-step
+// evaluation with frozen decisions gives exact directional derivatives for
+// the adjoint tests.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+typedef std::complex<double> cplx;
+
+inline double re(double x) { return x; }
+inline double re(const cplx& x) { return x.real(); }
+inline double fmaT(double a, double b, double c) { return std::fma(a, b, c); }
+inline cplx fmaT(const cplx& a, const cplx& b, const cplx& c) { return a * b + c; }
+inline double absT(double x) { return std::fabs(x); }
+inline cplx absT(const cplx& x) { return x.real() < 0.0 ? -x : x; }
+inline double sqrtT(double x) { return std::sqrt(x); }
+inline cplx sqrtT(const cplx& x) { return std::sqrt(x); }
+
+// ---------------------------------------------------------------- constants
+// Sec. 3.2: eps and q of the scale-separation formula.
+const double EPS = 1e-40;
+// Sec. 3.4: C_r, alpha_1, alpha_2 and eps of the discontinuity detector.
+const double C_R = 0.265;
+const double ALPHA1 = 14.0;
+const double ALPHA2 = 6.4;
+// Sec. 3.4: C_T = 10^{-[beta]}, [beta] in 7..14, kept as decimal literals.
+const double CT_OF_K[15] = {0, 0, 0, 0, 0, 0, 0, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12, 1e-13, 1e-14};
+// Sec. 4.1: optimal weights of the small stencils.
+const double DK[3] = {0.5065006634, 0.3699651429, 0.1235341937};
+// Sec. 4.1: optimised linear schemes on S3 (6-point), S4 (8-point), S5 (10-point),
+// coefficients from the leftmost stencil cell to the rightmost.
+const double LIN6[6] = {0.02852274270130377, -0.1714015614372447, 0.650378818735941,
+                        0.6253788187359414, -0.1589015614372448, 0.02602274270130375};
+const double LIN8[8] = {-0.006866688980568011, 0.05128582585522106, -0.1968478198727312,
+                        0.6552858258552222,    0.6452858258552218,  -0.1908478198727314,
+                        0.04928582585522098,   -0.006580974694853729};
+const double LIN10[10] = {0.001911786299492748, -0.0170332977472532,  0.07339445614860979,
+                          -0.221228429084247,   0.6657332621611695,   0.6557332621611695,
+                          -0.2145617624175796,  0.07053731329146805,  -0.01631901203296621,
+                          0.001832421220128962};
+
+// Candidate stencils of Sec. 3.1 / 4.2, as (leftmost cell offset from i, width).
+const int ST_LO[6] = {-1, 0, -2, -2, -3, -4};
+const int ST_R[6] = {3, 3, 3, 6, 8, 10};
+
+// ---------------------------------------------- smoothness indicator tables
+// beta_{k,r} = sum_{j=1}^{r-1} dx^{2j-1} int_{cell i} (d^j p_k/dx^j)^2 dx.
+// In units of dx the stencil cell l (0-based) spans [l-1/2, l+1/2]; the
+// primitive P of p_k takes the values P(b-1/2) = sum_{l<b} f_l at the r+1 cell
+// boundaries, so in Newton form over those nodes
+//   P(x) = const + sum_{m=1}^{r-1} Delta^m f_0 / (m+1)! * omega_{m+1}(x) + f_0 x,
+//   omega_{m+1}(x) = prod_{b=0}^{m} (x - (b - 1/2)),
+// and p_k^{(j)} = P^{(j+1)} involves only the forward differences Delta^m f_0,
+// m >= j.  The integral over cell i (local index e = -lo) of the square of a
+// polynomial of degree r-1-j is exact with (r-1)-point Gauss-Legendre.
+struct BetaTable {
+  int r = 0, lo = 0, nq = 0;
+  double w[9];
+  double M[9][9][9];  // M[j-1][q][m-1] = omega_{m+1}^{(j+1)}(x_q) / (m+1)!
+};
+BetaTable g_beta[6];
+bool g_beta_ready = false;
+
+void gauss_legendre(int n, double* x, double* w) {
+  // Newton iteration on the Legendre polynomial P_n from the three-term recurrence.
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 200; ++it) {
+      double pn = 1.0, pm = 0.0;
+      for (int k = 1; k <= n; ++k) {
+        double pk = ((2.0 * k - 1.0) * z * pn - (k - 1.0) * pm) / k;
+        pm = pn;
+        pn = pk;
+      }
+      dp = n * (z * pn - pm) / (z * z - 1.0);
+      double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-17) break;
+    }
+    double pn = 1.0, pm = 0.0;
+    for (int k = 1; k <= n; ++k) {
+      double pk = ((2.0 * k - 1.0) * z * pn - (k - 1.0) * pm) / k;
+      pm = pn;
+      pn = pk;
+    }
+    dp = n * (z * pn - pm) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+void build_beta_tables() {
+  if (g_beta_ready) return;
+  for (int k = 0; k < 6; ++k) {
+    BetaTable& T = g_beta[k];
+    T.r = ST_R[k];
+    T.lo = ST_LO[k];
+    T.nq = T.r - 1;
+    double gx[9], gw[9];
+    gauss_legendre(T.nq, gx, gw);
+    const double e = -T.lo;  // local index of cell i inside the stencil
+    for (int q = 0; q < T.nq; ++q) T.w[q] = 0.5 * gw[q];
+    std::memset(T.M, 0, sizeof(T.M));
+    for (int m = 1; m <= T.r - 1; ++m) {
+      // omega_{m+1}(e + t) as a polynomial in t (coefficients are dyadic, exact).
+      double c[12] = {0};
+      c[0] = 1.0;
+      int deg = 0;
+      for (int b = 0; b <= m; ++b) {
+        const double root = (b - 0.5) - e;  // factor (t - root)
+        double nc[12] = {0};
+        for (int a = 0; a <= deg; ++a) {
+          nc[a + 1] += c[a];
+          nc[a] -= root * c[a];
+        }
+        ++deg;
+        std::memcpy(c, nc, sizeof(c));
+      }
+      double fact = 1.0;
+      for (int a = 2; a <= m + 1; ++a) fact *= a;
+      for (int j = 1; j <= m; ++j) {
+        // (j+1)-th derivative of the t-polynomial
+        double dc[12] = {0};
+        for (int a = j + 1; a <= deg; ++a) {
+          double f = 1.0;
+          for (int s = 0; s <= j; ++s) f *= (a - s);
+          dc[a - j - 1] = c[a] * f;
+        }
+        for (int q = 0; q < T.nq; ++q) {
+          const double t = 0.5 * gx[q];
+          double v = 0.0;
+          for (int a = deg - j - 1; a >= 0; --a) v = v * t + dc[a];
+          T.M[j - 1][q][m - 1] = v / fact;
+        }
+      }
+    }
+  }
+  g_beta_ready = true;
+}
+
+// f points at the stencil's leftmost value; returns beta for candidate k.
+double beta_of(int k, const double* f) {
+  const BetaTable& T = g_beta[k];
+  double tab[10], dif[9];
+  for (int l = 0; l < T.r; ++l) tab[l] = f[l];
+  for (int m = 1; m <= T.r - 1; ++m) {
+    for (int l = 0; l + m < T.r; ++l) tab[l] = tab[l + 1] - tab[l];
+    dif[m - 1] = tab[0];  // Delta^m f_0
+  }
+  double beta = 0.0;
+  for (int j = 1; j <= T.r - 1; ++j) {
+    for (int q = 0; q < T.nq; ++q) {
+      double d = 0.0;
+      for (int m = j; m <= T.r - 1; ++m) d += T.M[j - 1][q][m - 1] * dif[m - 1];
+      beta += T.w[q] * d * d;
+    }
+  }
+  return beta;
+}
+
+// ------------------------------------------------- scalar TENO-AA reconstruction
+// Flag byte: bits 0-1 = chosen large stencil (0 none, 1 S3, 2 S4, 3 S5),
+// bits 2-4 = delta_0..delta_2 of the fallback, bits 5-7 = [beta] - 7.
+struct Decision {
+  uint8_t flag = 0;
+  double margin = INFINITY;  // min relative distance of any decision to its threshold
+};
+
+// Candidate fluxes of Sec. 4.2 at x_{i+1/2}; fk points at f_{i} inside the window.
+template <class T>
+T small_flux(int k, const T* fi) {
+  if (k == 0) return ((-fi[-1] + 5.0 * fi[0]) + 2.0 * fi[1]) / 6.0;
+  if (k == 1) return ((2.0 * fi[0] + 5.0 * fi[1]) - fi[2]) / 6.0;
+  return ((2.0 * fi[-2] - 7.0 * fi[-1]) + 11.0 * fi[0]) / 6.0;
+}
+
+template <class T>
+T large_flux(int k, const T* fi) {
+  const double* c = (k == 3) ? LIN6 : (k == 4) ? LIN8 : LIN10;
+  const int lo = ST_LO[k], r = ST_R[k];
+  T acc = c[0] * fi[lo];
+  for (int m = 1; m < r; ++m) acc = fmaT(T(c[m]), fi[lo + m], acc);
+  return acc;
+}
+
+template <class T>
+T fallback_flux(uint8_t dmask, const T* fi) {
+  const double del[3] = {(dmask & 1) ? 1.0 : 0.0, (dmask & 2) ? 1.0 : 0.0, (dmask & 4) ? 1.0 : 0.0};
+  const double dsum = (DK[0] * del[0] + DK[1] * del[1]) + DK[2] * del[2];
+  const double w0 = (DK[0] * del[0]) / dsum;
+  const double w1 = (DK[1] * del[1]) / dsum;
+  const double w2 = (DK[2] * del[2]) / dsum;
+  return fmaT(T(w2), small_flux(2, fi), fmaT(T(w1), small_flux(1, fi), w0 * small_flux(0, fi)));
+}
+
+double rel_margin(double chi, double ct) { return std::fabs(chi / ct - 1.0); }
+
+// fv = f_{-G+1..G} (r = 2G values); i sits at index G-1.  order is 8 or 10.
+// If frozen is non-null the decisions are taken from *frozen instead.
+template <class T>
+T teno_aa(int order, const T* fv, Decision* dec, const uint8_t* frozen) {
+  const int G = order / 2;
+  const T* fi = fv + (G - 1);
+  if (frozen) {
+    const uint8_t fl = *frozen;
+    const int sel = fl & 3;
+    if (sel) return large_flux(sel + 2, fi);
+    return fallback_flux<T>((fl >> 2) & 7, fi);
+  }
+  double f[10];
+  for (int l = 0; l < order; ++l) f[l] = re(fv[l]);
+  const double* x = f + (G - 1);  // x[k] = f_{i+k}
+
+  // Sec. 3.4: eta_j over j = -1..2, eta_{j+1/2} = min, m, g(m), [beta], C_T.
+  double etabar = 0.0;
+  for (int j = -1; j <= 2; ++j) {
+    const double a = x[j + 1] - x[j];
+    const double b = x[j] - x[j - 1];
+    const double eta = (std::fabs((2.0 * a) * b) + EPS) / ((a * a + b * b) + EPS);
+    if (j == -1 || eta < etabar) etabar = eta;
+  }
+  double ratio = etabar / C_R;
+  if (ratio > 1.0) ratio = 1.0;
+  const double m = 1.0 - ratio;
+  const double om = 1.0 - m;
+  const double om2 = om * om;
+  const double g = (om2 * om2) * (1.0 + 4.0 * m);
+  const double B = ALPHA1 - ALPHA2 * (1.0 - g);
+  int K = (int)std::floor(B);
+  if (K < 7) K = 7;
+  if (K > 14) K = 14;
+  const double CT = CT_OF_K[K];
+  Decision d;
+  if (m > 0.0) d.margin = std::min(d.margin, std::fabs(B - std::nearbyint(B)) / B);
+
+  // Sec. 3.2: scale separation on the three small stencils.
+  double gam[6];
+  for (int k = 0; k < 3; ++k) {
+    const double xb = beta_of(k, x + ST_LO[k]) + EPS;
+    const double x2 = xb * xb, x4 = x2 * x2;
+    gam[k] = 1.0 / ((x4 * x2) * xb);
+  }
+  // Sec. 3.3: groups (S0,S1,S2,Sp), largest p first.
+  const int pmax = (order == 10) ? 5 : 4;
+  for (int p = pmax; p >= 3; --p) {
+    const double xb = beta_of(p, x + ST_LO[p]) + EPS;
+    const double x2 = xb * xb, x4 = x2 * x2;
+    gam[p] = 1.0 / ((x4 * x2) * xb);
+    const double chi = gam[p] / (((gam[0] + gam[1]) + gam[2]) + gam[p]);
+    d.margin = std::min(d.margin, rel_margin(chi, CT));
+    if (chi >= CT) {
+      d.flag = (uint8_t)((p - 2) | ((K - 7) << 5));
+      if (dec) *dec = d;
+      return large_flux(p, fi);
+    }
+  }
+  // Fallback: TENO5 cut-off on the small stencils, normalised among themselves.
+  const double sum3 = (gam[0] + gam[1]) + gam[2];
+  uint8_t dm = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double chi = gam[k] / sum3;
+    d.margin = std::min(d.margin, rel_margin(chi, CT));
+    if (chi >= CT) dm |= (uint8_t)(1 << k);
+  }
+  d.flag = (uint8_t)((dm << 2) | ((K - 7) << 5));
+  if (dec) *dec = d;
+  return fallback_flux<T>(dm, fi);
+}
+
+// ------------------------------------------------------------- Euler system
+struct Grid {
+  int ndim;
+  int64_t n[3];
+  double dx[3];
+  int bc_lo[3], bc_hi[3];
+};
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_SYMMETRY = 2, BC_NOSLIP = 3 };
+
+template <class T>
+struct CellQ {
+  T W[5];  // conserved, axis order (rho, m_x, [m_y], [m_z], E)
+  T F[5];  // physical flux along the sweep direction, axis order
+  T u[3];
+  T p, c, H, sr;
+};
+
+// Sec. 1 (Euler equations, ideal-gas EOS), primitives of one cell.
+template <class T>
+void cell_state(int ndim, double gam, int d, const T* W, CellQ<T>& q) {
+  const int nv = ndim + 2;
+  for (int c = 0; c < nv; ++c) q.W[c] = W[c];
+  const T rho = W[0];
+  T q2 = T(0.0);
+  for (int k = 0; k < ndim; ++k) {
+    q.u[k] = W[1 + k] / rho;
+    q2 = (k == 0) ? q.u[0] * q.u[0] : q2 + q.u[k] * q.u[k];
+  }
+  const T E = W[nv - 1];
+  q.p = (gam - 1.0) * (E - (0.5 * rho) * q2);
+  q.c = sqrtT((gam * q.p) / rho);
+  q.H = (E + q.p) / rho;
+  q.sr = sqrtT(rho);
+  const T un = q.u[d];
+  q.F[0] = W[1 + d];
+  for (int k = 0; k < ndim; ++k) q.F[1 + k] = (k == d) ? W[1 + k] * un + q.p : W[1 + k] * un;
+  q.F[nv - 1] = (E + q.p) * un;
+}
+
+// Pressure of a conserved state, the same arithmetic as in cell_state.
+template <class T>
+T pressure_of(int ndim, double gam, const T* W) {
+  const int nv = ndim + 2;
+  const T rho = W[0];
+  T q2 = T(0.0);
+  for (int k = 0; k < ndim; ++k) {
+    const T uk = W[1 + k] / rho;
+    q2 = (k == 0) ? uk * uk : q2 + uk * uk;
+  }
+  return (gam - 1.0) * (W[nv - 1] - (0.5 * rho) * q2);
+}
+
+// Roe-averaged eigenvectors of the x_d flux Jacobian (Sec. 5, characteristic
+// decomposition at the face).  Local frame: (rho, m_n, m_t1, [m_t2], E) with
+// tangential axes in ascending order; fields (u-c, u, shear..., u+c).
+template <class T>
+struct Eigen {
+  int nv;
+  int perm[5];  // local component -> axis component
+  T L[5][5], R[5][5];
+};
+
+template <class T>
+void roe_eigen(int ndim, double gam, int d, const CellQ<T>& a, const CellQ<T>& b, Eigen<T>& e) {
+  const int nv = ndim + 2;
+  e.nv = nv;
+  e.perm[0] = 0;
+  e.perm[1] = 1 + d;
+  int t = 2;
+  for (int k = 0; k < ndim; ++k)
+    if (k != d) e.perm[t++] = 1 + k;
+  e.perm[nv - 1] = nv - 1;
+
+  const T den = a.sr + b.sr;
+  T ur[3];
+  T q2 = T(0.0);
+  for (int k = 0; k < ndim; ++k) {
+    ur[k] = (a.sr * a.u[k] + b.sr * b.u[k]) / den;
+    q2 = (k == 0) ? ur[0] * ur[0] : q2 + ur[k] * ur[k];
+  }
+  const T H = (a.sr * a.H + b.sr * b.H) / den;
+  const T qq = 0.5 * q2;
+  const T c2 = (gam - 1.0) * (H - qq);
+  const T c = sqrtT(c2);
+  const T b1 = (gam - 1.0) / c2;
+  const T b2 = b1 * qq;
+  const T un = ur[d];
+  T ut[2];
+  int nt = 0;
+  for (int k = 0; k < ndim; ++k)
+    if (k != d) ut[nt++] = ur[k];
+  const T unc = un / c;
+  const T ic = 1.0 / c;
+
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) e.L[i][j] = e.R[i][j] = T(0.0);
+  const int last = nv - 1;
+  // Left eigenvectors (rows).
+  e.L[0][0] = 0.5 * (b2 + unc);
+  e.L[0][1] = 0.5 * (-b1 * un - ic);
+  e.L[1][0] = 1.0 - b2;
+  e.L[1][1] = b1 * un;
+  e.L[last][0] = 0.5 * (b2 - unc);
+  e.L[last][1] = 0.5 * (-b1 * un + ic);
+  for (int k = 0; k < nt; ++k) {
+    e.L[0][2 + k] = 0.5 * (-b1 * ut[k]);
+    e.L[1][2 + k] = b1 * ut[k];
+    e.L[last][2 + k] = 0.5 * (-b1 * ut[k]);
+    e.L[2 + k][0] = -ut[k];
+    e.L[2 + k][2 + k] = T(1.0);
+  }
+  e.L[0][last] = 0.5 * b1;
+  e.L[1][last] = -b1;
+  e.L[last][last] = 0.5 * b1;
+  // Right eigenvectors (columns).
+  e.R[0][0] = T(1.0);
+  e.R[1][0] = un - c;
+  e.R[last][0] = H - un * c;
+  e.R[0][1] = T(1.0);
+  e.R[1][1] = un;
+  e.R[last][1] = qq;
+  e.R[0][last] = T(1.0);
+  e.R[1][last] = un + c;
+  e.R[last][last] = H + un * c;
+  for (int k = 0; k < nt; ++k) {
+    e.R[2 + k][0] = ut[k];
+    e.R[2 + k][1] = ut[k];
+    e.R[2 + k][last] = ut[k];
+    e.R[2 + k][2 + k] = T(1.0);
+    e.R[last][2 + k] = ut[k];
+  }
+}
+
+// Characteristic speed of field s at a cell.
+template <class T>
+T char_speed(int nv, int s, const T& un, const T& c) {
+  if (s == 0) return un - c;
+  if (s == nv - 1) return un + c;
+  return un;
+}
+
+struct Scheme {
+  int order, splitting, positivity;
+};
+
+
+// Positivity limiter: a reading of Hu, Adams & Shu (2013), which the paper
+// applies in its extreme cases (Sec. 5.3, opening paragraph) without restating.
+// With mu = kappa_d * dt/dx_d the face flux F enters the two half-states
+//   X+(F) = U_i - mu F,   X-(F) = U_{i+1} + mu F,
+// whose weighted average is the forward-Euler update.  The first-order
+// Lax-Friedrichs flux FL (alpha = max(|u_n|+c) over the two cells) keeps both
+// half-states admissible when mu * alpha <= 1.  The high-order flux FH is
+// pulled towards FL: first so that the density of both half-states stays
+// >= min(1e-13, rho(X(FL))), then so that their pressure stays
+// >= min(1e-13, p(X(FL))), using that pressure is concave in U.
+template <class T>
+void limit_face(int ndim, double gam, int d, double mu, const CellQ<T>& a, const CellQ<T>& b, T* F) {
+  const int nv = ndim + 2;
+  const T sa = absT(a.u[d]) + a.c;
+  const T sb = absT(b.u[d]) + b.c;
+  const T aL = (re(sa) >= re(sb)) ? sa : sb;
+  T FL[5];
+  for (int c = 0; c < nv; ++c) FL[c] = 0.5 * ((a.F[c] + b.F[c]) - aL * (b.W[c] - a.W[c]));
+  T X[5];
+  // density step
+  double theta_r = 1.0;
+  for (int side = 0; side < 2; ++side) {
+    const CellQ<T>& cq = side == 0 ? a : b;
+    const double sg = side == 0 ? -1.0 : 1.0;
+    const double rL = re(cq.W[0] + (sg * mu) * FL[0]);
+    const double rH = re(cq.W[0] + (sg * mu) * F[0]);
+    const double eps = std::min(1e-13, rL);
+    const double th = (rH < eps) ? (rL - eps) / (rL - rH) : 1.0;
+    theta_r = std::min(theta_r, th);
+  }
+  T Fs[5];
+  for (int c = 0; c < nv; ++c) Fs[c] = (theta_r < 1.0) ? FL[c] + theta_r * (F[c] - FL[c]) : F[c];
+  // pressure step
+  double theta_p = 1.0;
+  for (int side = 0; side < 2; ++side) {
+    const CellQ<T>& cq = side == 0 ? a : b;
+    const double sg = side == 0 ? -1.0 : 1.0;
+    for (int c = 0; c < nv; ++c) X[c] = cq.W[c] + (sg * mu) * FL[c];
+    const double pL = re(pressure_of(ndim, gam, X));
+    for (int c = 0; c < nv; ++c) X[c] = cq.W[c] + (sg * mu) * Fs[c];
+    const double pS = re(pressure_of(ndim, gam, X));
+    const double eps = std::min(1e-13, pL);
+    const double th = (pS < eps) ? (pL - eps) / (pL - pS) : 1.0;
+    theta_p = std::min(theta_p, th);
+  }
+  for (int c = 0; c < nv; ++c) F[c] = (theta_p < 1.0) ? FL[c] + theta_p * (Fs[c] - FL[c]) : Fs[c];
+}
+
+// Number of faces along direction d (face f is the left face of cell f).
+int64_t faces_along(const Grid& g, int d) {
+  return g.bc_lo[d] == BC_PERIODIC ? g.n[d] : g.n[d] + 1;
+}
+int64_t faces_total(const Grid& g, int d) {
+  int64_t t = faces_along(g, d);
+  for (int k = 0; k < g.ndim; ++k)
+    if (k != d) t *= g.n[k];
+  return t;
+}
+int64_t flag_offset(const Grid& g, int d) {
+  int64_t off = 0;
+  for (int k = 0; k < d; ++k) off += (int64_t)(g.ndim + 2) * 2 * faces_total(g, k);
+  return off;
+}
+
+// Ghost cells in conserved variables along one pencil (Appendix A).
+template <class T>
+void fill_ghosts(int ndim, int d, int bc, bool low, int64_t n, int G, std::vector<T>& line) {
+  const int nv = ndim + 2;
+  auto at = [&](int64_t l) -> T* { return &line[(size_t)(l + G) * nv]; };
+  for (int r = 1; r <= G; ++r) {
+    const int64_t dst = low ? -r : n - 1 + r;
+    int64_t src;
+    if (bc == BC_PERIODIC) src = low ? n - r : r - 1;
+    else if (bc == BC_OUTFLOW) src = low ? 0 : n - 1;
+    else src = low ? r - 1 : n - r;  // mirror
+    for (int c = 0; c < nv; ++c) at(dst)[c] = at(src)[c];
+    if (bc == BC_SYMMETRY) at(dst)[1 + d] = -at(dst)[1 + d];
+    if (bc == BC_NOSLIP)
+      for (int k = 0; k < ndim; ++k) at(dst)[1 + k] = -at(dst)[1 + k];
+  }
+}
+
+// a_d = max over cells of |u_d| + c (used for dt and the limiter weights).
+void wave_speeds(const Grid& g, double gam, const double* U, double* amax) {
+  const int nv = g.ndim + 2;
+  const int64_t nc = g.n[0] * g.n[1] * g.n[2];
+  for (int d = 0; d < 3; ++d) amax[d] = 0.0;
+  double W[5];
+  CellQ<double> q;
+  for (int64_t i = 0; i < nc; ++i) {
+    for (int c = 0; c < nv; ++c) W[c] = U[c * nc + i];
+    cell_state(g.ndim, gam, 0, W, q);
+    for (int d = 0; d < g.ndim; ++d) amax[d] = std::max(amax[d], std::fabs(q.u[d]) + q.c);
+  }
+}
+
+// dt = CFL / sum_d a_d/dx_d, once per step from U^n (Sec. 5, CFL 0.4 typical).
+double dt_from(const Grid& g, double cfl, const double* amax) {
+  double s = amax[0] / g.dx[0];
+  for (int d = 1; d < g.ndim; ++d) s = s + amax[d] / g.dx[d];
+  return cfl / s;
+}
+
+// Semi-discrete right-hand side dU/dt = -sum_d (F_{i+1/2} - F_{i-1/2})/dx_d
+// (Sec. 2, conservative finite-difference form), directions in order x, y, z.
+template <class T>
+int rhs_impl(const Grid& g, const Scheme& sc, double gam, const T* U, T* dU, double dt_lim, const double* amax,
+             uint8_t* flags, double* margins, const uint8_t* frozen) {
+  const int nd = g.ndim, nv = nd + 2, G = sc.order / 2;
+  const int64_t nc = g.n[0] * g.n[1] * g.n[2];
+  for (int64_t i = 0; i < nv * nc; ++i) dU[i] = T(0.0);
+  const bool limit = sc.positivity && dt_lim > 0.0;
+  double mu[3] = {0, 0, 0};
+  if (limit) {
+    double S = (dt_lim / g.dx[0]) * amax[0];
+    for (int d = 1; d < nd; ++d) S = S + (dt_lim / g.dx[d]) * amax[d];
+    for (int d = 0; d < nd; ++d) mu[d] = (2.0 * S) / amax[d];
+  }
+  const int64_t stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
+  for (int d = 0; d < nd; ++d) {
+    const int64_t n = g.n[d];
+    const bool periodic = g.bc_lo[d] == BC_PERIODIC;
+    const int64_t nf = faces_along(g, d);
+    const int64_t nft = faces_total(g, d);
+    const int64_t foff = flag_offset(g, d);
+    int oa[2];
+    int no = 0;
+    for (int k = 0; k < 3; ++k)
+      if (k != d) oa[no++] = k;
+    std::vector<T> line((size_t)(n + 2 * G) * nv);
+    std::vector<CellQ<T>> cells((size_t)(n + 2 * G));
+    std::vector<T> Fh((size_t)nf * nv);
+    std::vector<T> v(2 * G), gch(2 * G), gp(2 * G), gm(2 * G), fv(2 * G);
+    for (int64_t o1 = 0; o1 < g.n[oa[1]]; ++o1) {
+      for (int64_t o0 = 0; o0 < g.n[oa[0]]; ++o0) {
+        const int64_t base = o0 * stride[oa[0]] + o1 * stride[oa[1]];
+        for (int64_t l = 0; l < n; ++l)
+          for (int c = 0; c < nv; ++c) line[(size_t)(l + G) * nv + c] = U[c * nc + base + l * stride[d]];
+        fill_ghosts(nd, d, g.bc_lo[d], true, n, G, line);
+        fill_ghosts(nd, d, g.bc_hi[d], false, n, G, line);
+        for (int64_t l = -G; l < n + G; ++l) cell_state(nd, gam, d, &line[(size_t)(l + G) * nv], cells[(size_t)(l + G)]);
+        for (int64_t f = 0; f < nf; ++f) {
+          // face between cells f-1 and f; window of cells f-G .. f+G-1
+          const CellQ<T>* win = &cells[(size_t)(f - G + G)];
+          const CellQ<T>& ca = cells[(size_t)(f - 1 + G)];
+          const CellQ<T>& cb = cells[(size_t)(f + G)];
+          Eigen<T> e;
+          roe_eigen(nd, gam, d, ca, cb, e);
+          // face linear index inside the flag array of direction d
+          int64_t idx[3] = {0, 0, 0};
+          idx[d] = f;
+          idx[oa[0]] = o0;
+          idx[oa[1]] = o1;
+          int64_t m0 = (d == 0) ? nf : g.n[0];
+          int64_t m1 = (d == 1) ? nf : g.n[1];
+          const int64_t flin = (idx[2] * m1 + idx[1]) * m0 + idx[0];
+          T fhat[5];
+          for (int s = 0; s < nv; ++s) {
+            // projection onto field s of the conserved state and physical flux
+            for (int j = 0; j < 2 * G; ++j) {
+              T av = e.L[s][0] * win[j].W[e.perm[0]];
+              T ag = e.L[s][0] * win[j].F[e.perm[0]];
+              for (int c = 1; c < nv; ++c) {
+                av = fmaT(e.L[s][c], win[j].W[e.perm[c]], av);
+                ag = fmaT(e.L[s][c], win[j].F[e.perm[c]], ag);
+              }
+              v[j] = av;
+              gch[j] = ag;
+            }
+            // splitting speed over the window: LLF per field, Rusanov for all fields
+            T alpha = T(-1.0);
+            for (int j = 0; j < 2 * G; ++j) {
+              const T un = win[j].u[d];
+              const T lam = sc.splitting == 0 ? absT(char_speed(nv, s, un, win[j].c)) : absT(un) + win[j].c;
+              if (re(lam) > re(alpha)) alpha = lam;
+            }
+            for (int j = 0; j < 2 * G; ++j) {
+              gp[j] = 0.5 * fmaT(alpha, v[j], gch[j]);
+              gm[j] = 0.5 * fmaT(-alpha, v[j], gch[j]);
+            }
+            T sum = T(0.0);
+            for (int side = 0; side < 2; ++side) {
+              for (int k = 0; k < 2 * G; ++k) fv[k] = side == 0 ? gp[k] : gm[2 * G - 1 - k];
+              const int64_t fi = foff + ((int64_t)s * 2 + side) * nft + flin;
+              Decision dec;
+              const T h = teno_aa(sc.order, fv.data(), &dec, frozen ? frozen + fi : nullptr);
+              if (flags && !frozen) flags[fi] = dec.flag;
+              if (margins && !frozen) margins[fi] = dec.margin;
+              sum = side == 0 ? h : sum + h;
+            }
+            fhat[s] = sum;
+          }
+          // back to conserved components: F = sum_s R[:,s] fhat_s, then axis order
+          T* Fo = &Fh[(size_t)f * nv];
+          for (int c = 0; c < nv; ++c) {
+            T acc = e.R[c][0] * fhat[0];
+            for (int s = 1; s < nv; ++s) acc = fmaT(e.R[c][s], fhat[s], acc);
+            Fo[e.perm[c]] = acc;
+          }
+          if (limit) limit_face(nd, gam, d, mu[d], ca, cb, Fo);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+          const int64_t fr = periodic ? (i + 1) % n : i + 1;
+          for (int c = 0; c < nv; ++c) {
+            const int64_t cell = c * nc + base + i * stride[d];
+            dU[cell] = dU[cell] - (Fh[(size_t)fr * nv + c] - Fh[(size_t)i * nv + c]) / g.dx[d];
+          }
+        }
+      }
+    }
+  }
+  return 0;
+}
+
+// SSP-RK3 in the Shu-Osher form printed in Sec. 5:
+//   u1 = un + dt L(un)
+//   u2 = 3/4 un + 1/4 u1 + 1/4 dt L(u1)
+//   u^{n+1} = 1/3 un + 2/3 u2 + 2/3 dt L(u2)
+// L(stage, in, out) evaluates the right-hand side of stage 0, 1, 2.
+template <class RHS>
+void ssp_rk3(int64_t N, double dt, double* U, RHS&& L) {
+  std::vector<double> Un(U, U + N), U1((size_t)N), U2((size_t)N), dU((size_t)N);
+  L(0, Un.data(), dU.data());
+  for (int64_t i = 0; i < N; ++i) U1[(size_t)i] = Un[(size_t)i] + dt * dU[(size_t)i];
+  L(1, U1.data(), dU.data());
+  for (int64_t i = 0; i < N; ++i)
+    U2[(size_t)i] = 0.75 * Un[(size_t)i] + 0.25 * U1[(size_t)i] + (0.25 * dt) * dU[(size_t)i];
+  L(2, U2.data(), dU.data());
+  for (int64_t i = 0; i < N; ++i)
+    U[i] = (1.0 / 3.0) * Un[(size_t)i] + (2.0 / 3.0) * U2[(size_t)i] + ((2.0 / 3.0) * dt) * dU[(size_t)i];
+}
+
+int check_grid(const Grid& g, const Scheme& s) {
+  if (g.ndim < 1 || g.ndim > 3) return -1;
+  if (s.order != 8 && s.order != 10) return -1;
+  for (int d = 0; d < 3; ++d) {
+    if (g.n[d] < 1) return -1;
+    if (d < g.ndim) {
+      if (g.n[d] < s.order / 2 || g.dx[d] <= 0.0) return -1;
+      if ((g.bc_lo[d] == BC_PERIODIC) != (g.bc_hi[d] == BC_PERIODIC)) return -1;
+      if (g.bc_lo[d] < 0 || g.bc_lo[d] > 3 || g.bc_hi[d] < 0 || g.bc_hi[d] > 3) return -1;
+    } else if (g.n[d] != 1) {
+      return -1;
+    }
+  }
+  return 0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C API
+extern "C" {
+
+struct or_grid {
+  int32_t ndim;
+  int32_t pad;
+  int64_t n[3];
+  double dx[3];
+  int32_t bc_lo[3];
+  int32_t bc_hi[3];
+};
+
+static Grid to_grid(const or_grid* g) {
+  Grid r;
+  r.ndim = g->ndim;
+  for (int d = 0; d < 3; ++d) {
+    r.n[d] = g->n[d];
+    r.dx[d] = g->dx[d];
+    r.bc_lo[d] = g->bc_lo[d];
+    r.bc_hi[d] = g->bc_hi[d];
+  }
+  return r;
+}
+
+// beta of candidate k (0..5) for the values of its stencil, leftmost first.
+double or_beta(int k, const double* f) {
+  build_beta_tables();
+  if (k < 0 || k > 5) return NAN;
+  return beta_of(k, f);
+}
+
+// Scalar TENO-AA reconstruction of f_{i+1/2} from f_{-G+1..G}.
+double or_teno(int order, const double* fv, uint8_t* flag, double* margin) {
+  build_beta_tables();
+  Decision d;
+  const double h = teno_aa(order, fv, &d, nullptr);
+  if (flag) *flag = d.flag;
+  if (margin) *margin = d.margin;
+  return h;
+}
+
+// Candidate flux k (0..5) at i+1/2; fi points at f_i inside a long enough array.
+double or_candidate_flux(int k, const double* fi) {
+  if (k < 3) return small_flux(k, fi);
+  return large_flux(k, fi);
+}
+
+void or_wave_speeds(const or_grid* g, double gam, const double* U, double* amax) {
+  wave_speeds(to_grid(g), gam, U, amax);
+}
+
+double or_dt(const or_grid* g, double gam, double cfl, const double* U) {
+  double a[3];
+  Grid G = to_grid(g);
+  wave_speeds(G, gam, U, a);
+  return dt_from(G, cfl, a);
+}
+
+int64_t or_flags_size(const or_grid* g) {
+  Grid G = to_grid(g);
+  return flag_offset(G, G.ndim);
+}
+
+// One RHS.  The limiter acts only if positivity != 0 and dt_lim > 0; its wave
+// speeds a_d are taken from U.  flags/margins may be null.
+int or_rhs(const or_grid* g, int order, int splitting, int positivity, double gam, const double* U, double* dU,
+           double dt_lim, uint8_t* flags, double* margins) {
+  build_beta_tables();
+  Grid G = to_grid(g);
+  Scheme s{order, splitting, positivity};
+  if (check_grid(G, s)) return -1;
+  double a[3] = {0, 0, 0};
+  if (positivity && dt_lim > 0.0) wave_speeds(G, gam, U, a);
+  return rhs_impl<double>(G, s, gam, U, dU, dt_lim, a, flags, margins, nullptr);
+}
+
+// RHS with every decision frozen to the given flags, evaluated on U + i*h*V.
+// Returns Im(RHS)/h in jvp: the exact directional derivative of the
+// piecewise-smooth map at U along V (complex-step differentiation).
+int or_rhs_jvp(const or_grid* g, int order, int splitting, double gam, const double* U, const double* V,
+               const uint8_t* flags, double* rhs_out, double* jvp) {
+  build_beta_tables();
+  Grid G = to_grid(g);
+  Scheme s{order, splitting, 0};
+  if (check_grid(G, s) || !flags) return -1;
+  const double h = 1e-150;
+  const int64_t N = (int64_t)(G.ndim + 2) * G.n[0] * G.n[1] * G.n[2];
+  std::vector<cplx> Uc((size_t)N), dUc((size_t)N);
+  for (int64_t i = 0; i < N; ++i) Uc[(size_t)i] = cplx(U[i], h * V[i]);
+  double a[3] = {0, 0, 0};
+  rhs_impl<cplx>(G, s, gam, Uc.data(), dUc.data(), 0.0, a, nullptr, nullptr, flags);
+  for (int64_t i = 0; i < N; ++i) {
+    if (rhs_out) rhs_out[i] = dUc[(size_t)i].real();
+    jvp[i] = dUc[(size_t)i].imag() / h;
+  }
+  return 0;
+}
+
+// One SSP-RK3 step (Sec. 5, Shu-Osher form) in place.  *dt > 0 is used as
+// given, otherwise dt = CFL / sum_d a_d/dx_d from U^n and written back.
+// flags3/margins3 (optional) receive the decisions of the three stages.
+int or_step(const or_grid* g, int order, int splitting, int positivity, double gam, double cfl, double* U,
+            double* dt, uint8_t* flags3, double* margins3) {
+  build_beta_tables();
+  Grid G = to_grid(g);
+  Scheme s{order, splitting, positivity};
+  if (check_grid(G, s)) return -1;
+  const int64_t N = (int64_t)(G.ndim + 2) * G.n[0] * G.n[1] * G.n[2];
+  const int64_t nfl = flag_offset(G, G.ndim);
+  double a[3];
+  wave_speeds(G, gam, U, a);
+  if (!(*dt > 0.0)) *dt = dt_from(G, cfl, a);
+  const double h = *dt;
+  ssp_rk3(N, h, U, [&](int st, const double* in, double* out) {
+    rhs_impl<double>(G, s, gam, in, out, h, a, flags3 ? flags3 + st * nfl : nullptr,
+                     margins3 ? margins3 + st * nfl : nullptr, nullptr);
+  });
+  return 0;
+}
+
+// Scalar linear advection u_t + u_x = 0 on a periodic grid (Sec. 5.1): the
+// flux is f = u with positive speed, so only the upwind-biased reconstruction
+// enters.  dudt = -(fhat_{i+1/2} - fhat_{i-1/2})/dx.
+int or_advect_rhs(int order, int64_t n, double dx, const double* u, double* dudt, uint8_t* flags) {
+  build_beta_tables();
+  if ((order != 8 && order != 10) || n < order) return -1;
+  const int G = order / 2;
+  std::vector<double> fh((size_t)n), fv((size_t)(2 * G));
+  for (int64_t i = 0; i < n; ++i) {
+    for (int k = 0; k < 2 * G; ++k) fv[(size_t)k] = u[((i - G + 1 + k) % n + n) % n];
+    Decision d;
+    fh[(size_t)i] = teno_aa(order, fv.data(), &d, nullptr);  // fhat_{i+1/2}
+    if (flags) flags[i] = d.flag;
+  }
+  for (int64_t i = 0; i < n; ++i) dudt[i] = -(fh[(size_t)i] - fh[(size_t)((i - 1 + n) % n)]) / dx;
+  return 0;
+}
+
+// One SSP-RK3 step of the periodic scalar advection problem with time step dt.
+int or_advect_step(int order, int64_t n, double dx, double dt, double* u, uint8_t* flags3) {
+  if ((order != 8 && order != 10) || n < order) return -1;
+  ssp_rk3(n, dt, u, [&](int st, const double* in, double* out) {
+    or_advect_rhs(order, n, dx, in, out, flags3 ? flags3 + st * n : nullptr);
+  });
+  return 0;
+}
+
+// Roe-averaged eigen-system at a face of direction d between states Wa, Wb
+// (axis order).  L and R are nv x nv row-major in the local frame; lam holds
+// the characteristic speeds; perm maps local to axis components.
+void or_eigen(int ndim, double gam, int d, const double* Wa, const double* Wb, double* L, double* R, double* lam,
+              int32_t* perm) {
+  CellQ<double> a, b;
+  cell_state(ndim, gam, d, Wa, a);
+  cell_state(ndim, gam, d, Wb, b);
+  Eigen<double> e;
+  roe_eigen(ndim, gam, d, a, b, e);
+  const int nv = ndim + 2;
+  for (int i = 0; i < nv; ++i) {
+    perm[i] = e.perm[i];
+    for (int j = 0; j < nv; ++j) {
+      L[i * nv + j] = e.L[i][j];
+      R[i * nv + j] = e.R[i][j];
+    }
+  }
+  // speeds at the Roe state: the normal-momentum row of R holds u_n - c, u_n, u_n + c
+  for (int s = 0; s < nv; ++s) lam[s] = (s == 0) ? e.R[1][0] : (s == nv - 1) ? e.R[1][nv - 1] : e.R[1][1];
+}
+
+}  // extern "C"

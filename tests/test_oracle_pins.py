@@ -1,0 +1,509 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check here is independent of the oracle's own formulas: printed values
+of the paper, closed forms, exactness on polynomials, invariants of the Euler
+equations, and the paper's qualitative properties turned into exact tables.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+# ------------------------------------------------------------------ helpers
+
+
+def load_printed_betas():
+    """Paper Sec. 4.2: printed beta_{3,6}, beta_{4,8}, beta_{5,10} quadratic forms."""
+    forms = {}
+    cur = None
+    with open(os.path.join(GOLDEN, "beta_printed.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            t = line.split()
+            if t[0] == "beta":
+                cur = (int(t[1]), int(t[2]), int(t[3]), int(t[4]), [])
+                forms[int(t[1])] = cur
+            else:
+                cur[4].append((int(t[0]), int(t[1]), int(t[2])))
+    return forms
+
+
+def printed_beta_exact(form, f):
+    """Exact rational value of a printed form at the float64 data f (offsets lo..hi)."""
+    r, lo, hi, den, terms = form
+    fr = {lo + j: Fraction(float(f[j])) for j in range(r)}
+    s = sum(Fraction(c) * fr[a] * fr[b] for a, b, c in terms)
+    return s / den
+
+
+def weno_js_beta(k, f):
+    """Paper Sec. 4.2: the printed three-point indicators, in exact arithmetic."""
+    g = [Fraction(float(v)) for v in f]
+    if k == 0:
+        fm1, f0, f1 = g
+        return Fraction(1, 4) * (fm1 - f1) ** 2 + Fraction(13, 12) * (fm1 - 2 * f0 + f1) ** 2
+    if k == 1:
+        f0, f1, f2 = g
+        return Fraction(1, 4) * (3 * f0 - 4 * f1 + f2) ** 2 + Fraction(13, 12) * (f0 - 2 * f1 + f2) ** 2
+    fm2, fm1, f0 = g
+    return Fraction(1, 4) * (fm2 - 4 * fm1 + 3 * f0) ** 2 + Fraction(13, 12) * (fm2 - 2 * fm1 + f0) ** 2
+
+
+ST_LO = [-1, 0, -2, -2, -3, -4]
+ST_R = [3, 3, 3, 6, 8, 10]
+
+
+# ------------------------------------------------- smoothness indicators
+
+
+@pytest.mark.parametrize("k,r", [(3, 6), (4, 8), (5, 10)])
+def test_beta_equals_printed_form(k, r):
+    forms = load_printed_betas()
+    rng = np.random.default_rng(100 + k)
+    for trial in range(40):
+        if trial % 2 == 0:
+            f = rng.standard_normal(r)
+        else:  # smooth data on an offset: the printed form cancels badly here
+            x = np.arange(r) * 0.05 + rng.uniform()
+            f = 2.0 + np.sin(2 * np.pi * x)
+        exact = float(printed_beta_exact(forms[r], f))
+        got = oracle.beta(k, f)
+        assert abs(got - exact) <= 2e-13 * abs(exact), (trial, got, exact)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_small_beta_equals_printed_weno_js(k):
+    rng = np.random.default_rng(7 + k)
+    for _ in range(50):
+        f = rng.standard_normal(3)
+        exact = float(weno_js_beta(k, f))
+        assert abs(oracle.beta(k, f) - exact) <= 1e-14 * max(abs(exact), 1e-300)
+
+
+@pytest.mark.parametrize("k", range(6))
+def test_beta_closed_forms(k):
+    """Jiang-Shu integral for cell averages of 1, x, x^2 (and x^3 where reproduced)."""
+    lo, r = ST_LO[k], ST_R[k]
+    l = np.arange(lo, lo + r, dtype=np.float64)  # cell centres relative to cell i
+    assert oracle.beta(k, np.full(r, 3.7)) == 0.0  # constants: exactly zero
+    # cell averages of h = x over [l-1/2, l+1/2] are l: beta = int 1^2 = 1
+    assert abs(oracle.beta(k, l) - 1.0) <= 4e-15
+    # h = x^2: averages l^2 + 1/12; beta = int (2t)^2 + int 2^2 = 1/3 + 4
+    assert abs(oracle.beta(k, l * l + 1.0 / 12.0) - 13.0 / 3.0) <= 1e-13
+    if r >= 4:
+        # h = x^3: averages l^3 + l/4; beta = int (3t^2)^2 + (6t)^2 + 6^2 = 9/80 + 3 + 36
+        assert abs(oracle.beta(k, l ** 3 + l / 4.0) - (9.0 / 80.0 + 3.0 + 36.0)) <= 1e-12
+    # scaling: beta(c f) = c^2 beta(f); shift invariance beta(f + c) = beta(f)
+    f = np.random.default_rng(k).standard_normal(r)
+    b = oracle.beta(k, f)
+    assert abs(oracle.beta(k, 3.0 * f) - 9.0 * b) <= 1e-13 * b
+    assert abs(oracle.beta(k, f + 1.0) - b) <= 1e-12 * b
+    assert b >= 0.0
+
+
+# ------------------------------------------------------ linear schemes
+
+
+@pytest.mark.parametrize("k,degree", [(3, 4), (4, 6), (5, 8)])
+def test_linear_scheme_exact_derivative(k, degree):
+    """Sec. 4.1: the 6/8/10-point schemes are 4th/6th/8th order: the flux difference is
+    the exact derivative of point values of any polynomial of degree <= 4/6/8."""
+    rng = np.random.default_rng(k)
+    h = 0.37
+    for deg in range(degree + 1):
+        c = rng.standard_normal(deg + 1)
+        x = (np.arange(-6, 7)) * h
+        f = np.polyval(c, x)
+        i = 6  # x_i = 0
+        fp = oracle.candidate_flux(k, f, i)
+        fm = oracle.candidate_flux(k, f, i - 1)
+        d_exact = np.polyval(np.polyder(c), 0.0) if deg > 0 else 0.0
+        scale = np.abs(c).sum() + 1.0
+        assert abs((fp - fm) / h - d_exact) <= 5e-13 * scale / h, deg
+    # one degree higher is not exact (the order is not higher than stated)
+    c = np.zeros(degree + 2)
+    c[0] = 1.0
+    x = (np.arange(-6, 7)) * h
+    f = np.polyval(c, x)
+    fp = oracle.candidate_flux(k, f, 6)
+    fm = oracle.candidate_flux(k, f, 5)
+    assert abs((fp - fm) / h - 0.0) > 1e-8
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_small_candidates_reproduce_quadratics(k):
+    """Sec. 4.2: three-point candidate fluxes recover h(x_{i+1/2}) from cell averages
+    of any quadratic h."""
+    rng = np.random.default_rng(20 + k)
+    c = rng.standard_normal(3)  # h = c0 x^2 + c1 x + c2
+    l = np.arange(-3, 4, dtype=np.float64)
+    avg = c[0] * (l * l + 1.0 / 12.0) + c[1] * l + c[2]
+    got = oracle.candidate_flux(k, avg, 3)
+    assert abs(got - (c[0] * 0.25 + c[1] * 0.5 + c[2])) <= 1e-14 * 10
+
+
+def test_small_weights_give_third_order_scheme():
+    """Sec. 4.1: the d_k combination of the three small candidates is a consistent
+    3rd-order five-point scheme (exact derivative up to cubics, not quartics)."""
+    d = [0.5065006634, 0.3699651429, 0.1235341937]
+    h = 0.1
+
+    def comb(f, i):
+        return sum(d[k] * oracle.candidate_flux(k, f, i) for k in range(3))
+
+    x = (np.arange(-5, 6) + 0.3) * h
+    for deg, exact in [(0, True), (1, True), (2, True), (3, True), (4, False)]:
+        c = np.zeros(deg + 1)
+        c[0] = 1.0
+        f = np.polyval(c, x)
+        err = abs((comb(f, 5) - comb(f, 4)) / h - np.polyval(np.polyder(c), x[5]))
+        if exact:
+            assert err <= 2e-8, (deg, err)  # d_k are printed to 10 digits
+        else:
+            assert err > 1e-5, err
+
+
+# ------------------------------------------------------- TENO-AA scalar
+
+
+@pytest.mark.parametrize("order", [8, 10])
+def test_smooth_data_selects_largest_stencil(order):
+    """Sec. 3.3 remark: on smooth data the largest candidate gives the flux exactly."""
+    G = order // 2
+    big = 5 if order == 10 else 4
+    rng = np.random.default_rng(order)
+    for _ in range(200):
+        ppw = rng.uniform(16, 64)  # points per wavelength
+        x = (np.arange(-G + 1, G + 1)) / ppw
+        f = rng.uniform(-2, 2) + rng.uniform(0.1, 3) * np.sin(2 * np.pi * (x + rng.uniform()))
+        h, flag, _ = oracle.teno(order, f)
+        sel, _, K = oracle.decode_flag(flag)
+        assert sel == big
+        assert h == oracle.candidate_flux(big, f, G - 1)
+
+
+@pytest.mark.parametrize("order", [8, 10])
+@pytest.mark.parametrize("s", list(range(-3, 6)))
+def test_step_flag_table(order, s):
+    """ENO at an isolated step between cells s-1 and s (closed form of Sec. 3.3/3.4):
+    every large stencil containing the step is rejected, the largest one that does
+    not contain it is chosen; if none, delta keeps exactly the small stencils that
+    do not contain it; [beta] = 7 iff the jump lies inside the eta window f_{-2..3}."""
+    G = order // 2
+    if s < -G + 2 or s > G:
+        pytest.skip("step outside the window")
+    k_idx = np.arange(-G + 1, G + 1)
+    f = np.where(k_idx >= s, 1.0, 0.0)
+    h, flag, _ = oracle.teno(order, f)
+    sel, delta, K = oracle.decode_flag(flag)
+
+    def crosses(k):
+        lo, r = ST_LO[k], ST_R[k]
+        return lo <= s - 1 and s <= lo + r - 1
+
+    larges = [5, 4, 3] if order == 10 else [4, 3]
+    expect_sel = next((k for k in larges if not crosses(k)), 0)
+    assert sel == expect_sel
+    if expect_sel == 0:
+        assert delta == tuple(0 if crosses(k) else 1 for k in range(3))
+    else:
+        assert delta == (0, 0, 0)
+    assert K == (7 if -2 <= s - 1 <= 2 else 14)
+    # no new extrema: the flux stays within the data range (up to the printed
+    # coefficients' sums, which differ from 1 by up to 7.6e-15)
+    assert -1e-14 <= h <= 1.0 + 1e-14
+
+
+def _g_of_m(m):
+    return (1 - m) ** 4 * (1 + 4 * m)
+
+
+@pytest.mark.parametrize("K", range(7, 15))
+def test_adaptive_cutoff_buckets(K):
+    """Sec. 3.4: C_T = 10^-[14 - 6.4 (1 - g(m))]; K = 14 at m = 0, 7 at m = 1, and
+    the bucket of K is g in [1 - (14-K)/6.4, 1 - (13-K)/6.4)."""
+    if K == 14:
+        m_target = 0.0
+    else:
+        lo_g = max(0.0, 1 - (14 - K) / 6.4)
+        hi_g = 1 - (13 - K) / 6.4
+        g_target = 0.5 * (lo_g + hi_g)
+        a, b = 0.0, 1.0  # g decreasing in m: bisection
+        for _ in range(200):
+            mid = 0.5 * (a + b)
+            if _g_of_m(mid) > g_target:
+                a = mid
+            else:
+                b = mid
+        m_target = 0.5 * (a + b)
+    etabar = 0.265 * (1 - m_target)
+    # differences alternating 1, t: every eta_j = 2t/(1+t^2) = etabar
+    if etabar >= 1.0:
+        t = 1.0
+    else:
+        t = (1 - math.sqrt(1 - etabar * etabar)) / etabar if etabar > 0 else 0.0
+    if K == 14:
+        t = 1.0  # eta = 1 >= C_r
+    diffs = [1.0, t, 1.0, t, 1.0, t, 1.0, t, 1.0]
+    f = np.concatenate([[0.0], np.cumsum(diffs)])
+    f = f[: 10]
+    _, flag, _ = oracle.teno(10, f)
+    assert oracle.decode_flag(flag)[2] == K
+
+
+# ---------------------------------------------------------- Euler system
+
+
+def euler_flux(W, d, gamma):
+    """Physical flux along axis d of the Euler equations (Sec. 1)."""
+    nd = len(W) - 2
+    rho = W[0]
+    u = W[1:1 + nd] / rho
+    E = W[-1]
+    p = (gamma - 1) * (E - 0.5 * rho * np.dot(u, u))
+    F = np.empty_like(W)
+    F[0] = W[1 + d]
+    for k in range(nd):
+        F[1 + k] = W[1 + k] * u[d] + (p if k == d else 0.0)
+    F[-1] = (E + p) * u[d]
+    return F
+
+
+def rand_state(rng, nd, gamma):
+    rho = rng.uniform(0.2, 3)
+    u = rng.uniform(-1.5, 1.5, nd)
+    p = rng.uniform(0.2, 3)
+    return np.concatenate([[rho], rho * u, [p / (gamma - 1) + 0.5 * rho * np.dot(u, u)]])
+
+
+@pytest.mark.parametrize("nd", [1, 2, 3])
+def test_roe_eigensystem(nd):
+    """Roe property F(U_R) - F(U_L) = R diag(lam) L (U_R - U_L), and L R = I."""
+    rng = np.random.default_rng(nd)
+    for gamma in (1.4, 5.0 / 3.0):
+        for d in range(nd):
+            for _ in range(20):
+                Wa, Wb = rand_state(rng, nd, gamma), rand_state(rng, nd, gamma)
+                L, R, lam, perm = oracle.eigen(nd, gamma, d, Wa, Wb)
+                assert np.abs(L @ R - np.eye(nd + 2)).max() < 1e-13
+                P = np.zeros((nd + 2, nd + 2))
+                for c in range(nd + 2):
+                    P[c, perm[c]] = 1.0  # local = P @ axis
+                dF = P @ (euler_flux(Wb, d, gamma) - euler_flux(Wa, d, gamma))
+                dW = P @ (Wb - Wa)
+                approx = R @ np.diag(lam) @ (L @ dW)
+                assert np.abs(approx - dF).max() <= 1e-12 * (1 + np.abs(dF).max())
+
+
+def _grid(shape, bc=oracle.BC_PERIODIC):
+    return oracle.make_grid(shape, [1.0 / n for n in shape], [bc] * len(shape))
+
+
+@pytest.mark.parametrize("order", [8, 10])
+@pytest.mark.parametrize("shape", [(24,), (12, 10), (10, 8, 6)])
+def test_constant_state_is_steady(order, shape):
+    nd = len(shape)
+    g = _grid(shape)
+    W = np.array([1.3] + [0.4, -0.2, 0.1][:nd] + [3.1])
+    U = np.empty((nd + 2, 1 if nd < 3 else shape[2], 1 if nd < 2 else shape[1], shape[0]))
+    U[:] = W[:, None, None, None]
+    dU, flags, _ = oracle.rhs(g, U, order=order)
+    assert np.all(dU == 0.0)
+    big = 5 if order == 10 else 4
+    assert np.all(flags & 3 == big - 2)
+    assert np.all(flags >> 5 == 7)  # K = 14
+
+
+@pytest.mark.parametrize("order,splitting", [(8, 0), (10, 0), (10, 1)])
+@pytest.mark.parametrize("shape", [(32,), (16, 12), (10, 8, 8)])
+def test_conservation_periodic(order, splitting, shape):
+    """Periodic flux-difference form: the cell sums of dU/dt vanish to round-off."""
+    from paper_2109_14340_amd import inputs
+    U = inputs.random_smooth(shape, seed=len(shape) + order, kmax=3)
+    U[0] *= 1.0  # keep
+    # add a discontinuity so the nonlinear paths are active
+    nd = len(shape)
+    sl = [slice(None)] * 4
+    sl[3] = slice(0, shape[0] // 2)
+    U[tuple(sl)] *= 1.7
+    g = _grid(shape)
+    dU, _, _ = oracle.rhs(g, U, order=order, splitting=splitting)
+    for c in range(nd + 2):
+        scale = np.abs(dU[c]).sum()
+        assert abs(dU[c].sum()) <= 1e-13 * scale
+
+
+def test_multidim_reduces_to_1d():
+    """Data constant along y (and z) gives the 1D result in every such pencil."""
+    from paper_2109_14340_amd import inputs
+    U1 = inputs.shock_tube_1d(32)
+    g1 = _grid((32,), oracle.BC_OUTFLOW)
+    d1, _, _ = oracle.rhs(g1, U1, order=10)
+    for nd, shape in [(2, (32, 6)), (3, (32, 6, 6))]:
+        U = np.zeros((nd + 2,) + ((shape[2],) if nd == 3 else (1,)) + (shape[1], 32))
+        U[0] = U1[0, 0, 0]
+        U[1] = U1[1, 0, 0]
+        U[-1] = U1[2, 0, 0]
+        g = oracle.make_grid(shape, [1 / 32.0] + [0.1] * (nd - 1), [oracle.BC_OUTFLOW] + [oracle.BC_PERIODIC] * (nd - 1))
+        d, _, _ = oracle.rhs(g, U, order=10)
+        assert np.array_equal(d[0], np.broadcast_to(d1[0], d[0].shape))
+        assert np.array_equal(d[1], np.broadcast_to(d1[1], d[1].shape))
+        assert np.array_equal(d[-1], np.broadcast_to(d1[2], d[-1].shape))
+        for k in range(2, nd + 1):
+            assert np.all(d[k] == 0.0)
+
+
+def test_transpose_symmetry_2d():
+    """x <-> y with the momenta swapped maps dU/dt to its transpose exactly."""
+    from paper_2109_14340_amd import inputs
+    U = inputs.grf_2d(16, seed=5)
+    g = _grid((16, 16))
+    d, _, _ = oracle.rhs(g, U, order=10)
+    UT = np.ascontiguousarray(np.transpose(U, (0, 1, 3, 2))[[0, 2, 1, 3]])
+    dT, _, _ = oracle.rhs(g, UT, order=10)
+    assert np.array_equal(dT, np.transpose(d, (0, 1, 3, 2))[[0, 2, 1, 3]])
+
+
+def test_mirror_symmetry_1d():
+    """x -> -x, u -> -u maps dU/dt to its mirror image (to round-off)."""
+    from paper_2109_14340_amd import inputs
+    U = inputs.shock_tube_1d(40)
+    g = _grid((40,), oracle.BC_OUTFLOW)
+    d, _, _ = oracle.rhs(g, U, order=10)
+    M = U[:, :, :, ::-1].copy()
+    M[1] *= -1
+    dm, _, _ = oracle.rhs(g, M, order=10)
+    dmm = dm[:, :, :, ::-1].copy()
+    dmm[1] *= -1
+    assert np.abs(dmm - d).max() <= 1e-12 * np.abs(d).max()
+
+
+@pytest.mark.parametrize("order,expected", [(8, 6.0), (10, 8.0)])
+def test_rhs_convergence_order_entropy_wave(order, expected):
+    """Smooth periodic entropy wave rho = 1 + 0.2 sin 2 pi x, u = 1, p = 1: the RHS
+    truncation error decays at the linear scheme's order (Sec. 4.1 / Sec. 5.1)."""
+    gamma = 1.4
+    errs = []
+    Ns = [16, 24, 32] if order == 10 else [16, 24, 32, 48]
+    for N in Ns:
+        x = (np.arange(N) + 0.5) / N
+        rho = 1 + 0.2 * np.sin(2 * np.pi * x)
+        U = np.stack([rho, rho, 1 / (gamma - 1) + 0.5 * rho])[:, None, None, :]
+        g = _grid((N,))
+        d, flags, _ = oracle.rhs(g, U, order=order, gamma=gamma)
+        drho = -0.4 * np.pi * np.cos(2 * np.pi * x)  # -(rho u)_x exactly
+        exact = np.stack([drho, drho, 0.5 * drho])
+        errs.append(np.abs(d[:, 0, 0, :] - exact).max())
+    rates = [math.log(errs[i] / errs[i + 1]) / math.log(Ns[i + 1] / Ns[i]) for i in range(len(Ns) - 1)]
+    assert min(rates) > expected - 0.6, (errs, rates)
+
+
+@pytest.mark.parametrize("order,expected", [(8, 6.0), (10, 8.0)])
+def test_gaussian_pulse_advection_order(order, expected):
+    """Sec. 5.1: u_0 = exp(-300 (x - 0.5)^2), periodic linear advection; the
+    spatial operator converges at the designed order."""
+    errs = []
+    Ns = [160, 240, 320]
+    for N in Ns:
+        x = (np.arange(N) + 0.5) / N
+        u = np.exp(-300 * (x - 0.5) ** 2)
+        d, flags = oracle.advect_rhs(order, u, 1.0 / N)
+        exact = 600 * (x - 0.5) * u  # -u_x
+        errs.append(np.abs(d - exact).max())
+        # near the pulse the largest stencil is used; far out in the tails the
+        # data decays by a factor ~10 per cell and lower-order candidates take over
+        core = np.abs(x - 0.5) < 0.1
+        assert np.all(flags[core] & 3 == (3 if order == 10 else 2))
+    rates = [math.log(errs[i] / errs[i + 1]) / math.log(Ns[i + 1] / Ns[i]) for i in range(2)]
+    assert min(rates) > expected - 0.7, (errs, rates)
+
+
+@pytest.mark.parametrize("order", [8, 10])
+def test_rk3_stability_polynomial(order):
+    """SSP-RK3 (Sec. 5): on data where the scheme is linear (every flag selects the
+    largest stencil), one step multiplies a Fourier mode by exactly
+    1 + z + z^2/2 + z^3/6, z = dt * lambda_k, with lambda_k read off the spatial
+    operator's action on cos and sin."""
+    N, k = 32, 3
+    dx = 1.0 / N
+    x = (np.arange(N) + 0.5) * dx
+    c, s_ = np.cos(2 * np.pi * k * x), np.sin(2 * np.pi * k * x)
+    Lc, fc = oracle.advect_rhs(order, c + 2.0, dx)
+    Ls, fs = oracle.advect_rhs(order, s_ + 2.0, dx)
+    big = 3 if order == 10 else 2
+    assert np.all(fc & 3 == big) and np.all(fs & 3 == big)
+    lam = (Lc + 1j * Ls) / (c + 1j * s_)  # constant over i for a linear shift-invariant operator
+    assert np.abs(lam - lam[0]).max() < 1e-10 * abs(lam[0])
+    lam = lam.mean()
+    dt = 0.3 * dx
+    z = dt * lam
+    P = 1 + z + z * z / 2 + z ** 3 / 6
+    u1, f3 = oracle.advect_step(order, c + 2.0, dx, dt)
+    assert np.all(f3 & 3 == big)
+    expect = (P * (c + 1j * s_)).real + 2.0
+    assert np.abs(u1 - expect).max() < 1e-13
+    # a wrong stage weight would be visible at this size
+    assert abs(P) < 1.0
+
+
+def test_positivity_limiter_blast_cavity():
+    """With the limiter, density and pressure stay positive through a step of the
+    blast/cavity workload (Sec. 5.3 applies it for this purpose)."""
+    from paper_2109_14340_amd import inputs
+    gamma = 1.4
+    U = inputs.blast_cavity_3d(12)
+    g = _grid((12, 12, 12))
+    U1, dt, _, _ = oracle.step(g, U, order=10, positivity=1, cfl=0.4, gamma=gamma)
+    rho = U1[0]
+    p = (gamma - 1) * (U1[4] - 0.5 * (U1[1] ** 2 + U1[2] ** 2 + U1[3] ** 2) / rho)
+    assert rho.min() > 0 and p.min() > 0
+
+
+def test_positivity_double_rarefaction():
+    """Sec. 5.3.1 double rarefaction (rho,u,p) = (1,-2,0.1) | (1,2,0.1), N = 400,
+    outflow ends, to t = 0.1 with the limiter: rho and p stay positive."""
+    from paper_2109_14340_amd import inputs
+    gamma = 1.4
+    N = 400
+    x = (np.arange(N) + 0.5) / N
+    rho = np.ones(N)
+    u = np.where(x < 0.5, -2.0, 2.0)
+    p = np.full(N, 0.1)
+    U = inputs._as_layout(inputs.conserved_from_primitive(rho, [u], p, gamma), 1)
+    g = _grid((N,), oracle.BC_OUTFLOW)
+    t = 0.0
+    while t < 0.1 - 1e-14:
+        dt = oracle.dt(g, gamma, 0.4, U)
+        dt = min(dt, 0.1 - t)
+        U, dt, _, _ = oracle.step(g, U, order=10, positivity=1, dt=dt, gamma=gamma)
+        t += dt
+        r = U[0, 0, 0]
+        pp = (gamma - 1) * (U[2, 0, 0] - 0.5 * U[1, 0, 0] ** 2 / r)
+        assert r.min() > 0 and pp.min() > 0
+    # the centre approaches vacuum
+    assert U[0, 0, 0, N // 2] < 0.05
+
+
+def test_limiter_inactive_on_smooth_data():
+    """theta = 1 on smooth positive data: the limited RHS equals the unlimited one."""
+    from paper_2109_14340_amd import inputs
+    U = inputs.random_smooth((20, 16), seed=9, kmax=2)
+    g = _grid((20, 16))
+    a, _, _ = oracle.rhs(g, U, order=10)
+    b, _, _ = oracle.rhs(g, U, order=10, positivity=1, dt_lim=1e-3)
+    assert np.array_equal(a, b)
+
+
+def test_margins_report_near_decisions():
+    """The oracle's margin is |chi/C_T - 1| of the closest decision: a data set built to
+    sit on a threshold reports a tiny margin, smooth data a large one."""
+    f = np.sin(np.arange(10) * 0.3)
+    _, _, m = oracle.teno(10, f)
+    assert m > 1e-3
