@@ -1,0 +1,129 @@
+/*
+ * tenoaa.h - C ABI of the MI355X TENO-AA8/10 compressible-Euler library.
+ *
+ * The library evaluates the finite-difference right-hand side of the Euler
+ * equations (arXiv 2109.14340, Sec. 1 for the equations and ideal-gas EOS,
+ * Sec. 2 for the conservative flux-difference form) with the eight- or
+ * ten-point TENO-AA reconstruction (Sec. 3 and 4) applied to Roe-averaged
+ * characteristic fields with LLF or Rusanov flux splitting, optionally the
+ * positivity-preserving flux limiter the paper applies in its extreme cases
+ * (Sec. 5.3), and advances it with the SSP-RK3 scheme of Sec. 5.
+ *
+ * Conventions shared by every entry point
+ *  - Memory: every double/uint8 array argument is DEVICE memory on the
+ *    current HIP device unless stated otherwise.  Grid and scheme structs are
+ *    HOST memory and are read before the call returns.  The caller owns all
+ *    buffers; the library never allocates or frees in these calls.
+ *  - Layout of a state array U: float64, structure of arrays
+ *    U[v][k][j][i] with i (x) fastest, v = 0..nvar-1, nvar = ndim + 2 and
+ *    components (rho, rho*u, [rho*v], [rho*w], E).  Sizes of unused
+ *    dimensions are 1.  No ghost cells: boundaries are applied internally.
+ *  - Faces: along direction d, face f is the left face of cell f; there are
+ *    nf_d = n_d faces for a periodic direction and n_d + 1 otherwise.  A face
+ *    array of direction d has the cell array's shape with axis d of length
+ *    nf_d.
+ *  - Flags (optional output): uint8 per (direction, characteristic field,
+ *    split side, face), laid out [d][field][side][face array of d] with the
+ *    directions concatenated in order x, y, z.  Fields are ordered
+ *    (u-c, u, shear..., u+c); side 0 is the upwind-biased (+) side.  Bits
+ *    0-1: large stencil chosen (0 none, 1 S3, 2 S4, 3 S5); bits 2-4: the
+ *    cut-off deltas of the three small stencils when none was chosen;
+ *    bits 5-7: [beta] - 7 of the adaptive C_T = 10^-[beta] (Sec. 3.4).
+ *  - Streams: `stream` is a hipStream_t passed as void*; NULL is the null
+ *    stream.  Calls enqueue work and return without synchronising, except
+ *    where stated.  Calls on distinct (stream, workspace) pairs are
+ *    independent; calls sharing a workspace must be ordered by the caller.
+ *  - Errors: 0 on success; TENOAA_EINVAL for a bad argument (nothing is
+ *    enqueued); TENOAA_EUNSUPPORTED for a valid but unimplemented option;
+ *    TENOAA_EHIP when a HIP call fails (tenoaa_last_hip_error() returns
+ *    the hipError_t); TENOAA_EWORKSPACE when ws_bytes is too small.
+ *    Physical failures (rho <= 0, p <= 0 or NaN in a state the kernels read)
+ *    are asynchronous: they set a status word inside the workspace that
+ *    tenoaa_get_status() reports.
+ */
+#ifndef TENOAA_H
+#define TENOAA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TENOAA_OK = 0,
+  TENOAA_EINVAL = -1,
+  TENOAA_EUNSUPPORTED = -2,
+  TENOAA_EHIP = -3,
+  TENOAA_ENONPHYSICAL = -4,
+  TENOAA_EWORKSPACE = -5
+};
+
+/* Boundary conditions (Appendix A of the paper; OUTFLOW copies the nearest
+ * interior cell into every ghost layer).  A direction is either periodic on
+ * both sides or on neither. */
+enum { TENOAA_BC_PERIODIC = 0, TENOAA_BC_OUTFLOW = 1, TENOAA_BC_SYMMETRY = 2, TENOAA_BC_NOSLIP = 3 };
+
+/* Flux splitting (Sec. 5): LLF uses, per characteristic field, the largest
+ * |eigenvalue| over the reconstruction window; RUSANOV one max(|u_n| + c)
+ * over the window for every field. */
+enum { TENOAA_LLF = 0, TENOAA_RUSANOV = 1 };
+
+/* Workspace purposes for tenoaa_workspace_bytes. */
+enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1 };
+
+/* Uniform cell-centred grid: cell i of direction d has centre (i + 1/2) dx[d].
+ * n[d] >= order/2 for d < ndim and n[d] == 1 otherwise; dx[d] > 0. */
+typedef struct {
+  int32_t ndim;
+  int32_t pad;
+  int64_t n[3];
+  double dx[3];
+  int32_t bc_lo[3];
+  int32_t bc_hi[3];
+} tenoaa_grid;
+
+/* order: 8 (TENO8-AA) or 10 (TENO10-AA), Sec. 4; splitting: TENOAA_LLF or
+ * TENOAA_RUSANOV; positivity: 1 enables the flux limiter. */
+typedef struct {
+  int32_t order;
+  int32_t splitting;
+  int32_t positivity;
+  int32_t pad;
+} tenoaa_scheme;
+
+/* Bytes of device workspace a call of the given purpose needs for this grid.
+ * Returns 0 for invalid arguments.  The workspace must be 256-byte aligned
+ * and stays owned by the caller. */
+size_t tenoaa_workspace_bytes(const tenoaa_grid* grid, const tenoaa_scheme* scheme, int32_t which);
+
+/* Semi-discrete right-hand side dUdt = -sum_d (F_{f+1} - F_f)/dx_d
+ * (Sec. 2) of the state U, directions in order x, y, z.  dUdt (same layout as
+ * U, must not alias it) is overwritten.  gamma > 1 is the ratio of specific
+ * heats.  The limiter acts only if scheme->positivity and dt_limiter > 0;
+ * its CFL weights use the wave speeds of U.  flags may be NULL. */
+int tenoaa_rhs(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U, double* dUdt,
+               double dt_limiter, uint8_t* flags, void* ws, size_t ws_bytes, void* stream);
+
+/* One SSP-RK3 step (Sec. 5, Shu-Osher form) of U in place.  dt_dev is a
+ * device double: if it holds a value > 0 on entry that dt is used, otherwise
+ * dt = cfl / sum_d (a_d / dx_d) with a_d = max over cells of |u_d| + c is
+ * computed from U^n on the device and stored there.  No host
+ * synchronisation.  0 < cfl <= 1; with the limiter on, cfl <= 0.5. */
+int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,
+                double* dt_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronises `stream`, reads and clears the workspace status word.
+ * *out = 0 if every state read since the last call was physical, else 1.
+ * Returns TENOAA_ENONPHYSICAL if *out != 0, otherwise 0 (or an error). */
+int tenoaa_get_status(void* ws, void* stream, int32_t* out);
+
+/* hipError_t of the last failed HIP call in this thread (0 if none). */
+int tenoaa_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TENOAA_H */

@@ -65,6 +65,9 @@ def lib():
         L.or_rhs.restype = ctypes.c_int
         L.or_rhs.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                              dp, dp, ctypes.c_double, u8, dp]
+        L.or_rhs_cells.restype = ctypes.c_int
+        L.or_rhs_cells.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
+                                   ctypes.c_double, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), dp]
         L.or_rhs_jvp.restype = ctypes.c_int
         L.or_rhs_jvp.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, u8, dp, dp]
         L.or_step.restype = ctypes.c_int
@@ -153,6 +156,21 @@ def rhs(grid, U, order=10, splitting=LLF, positivity=0, gamma=1.4, dt_lim=0.0, w
     if rc:
         raise ValueError("oracle rhs rejected its arguments (rc=%d)" % rc)
     return dU, fl, mg
+
+
+def rhs_cells(grid, U, cells, order=10, splitting=LLF, positivity=0, gamma=1.4, dt_lim=0.0, amax=None):
+    """dU/dt at flat cell indices `cells` only; returns (len(cells), nvar)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    nv = grid.ndim + 2
+    out = np.empty((cells.size, nv))
+    am = np.ascontiguousarray(amax, dtype=np.float64) if amax is not None else None
+    rc = lib().or_rhs_cells(ctypes.byref(grid), order, splitting, positivity, gamma, _dp(U), dt_lim,
+                            _dp(am) if am is not None else None, cells.size,
+                            cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out))
+    if rc:
+        raise ValueError("oracle rhs_cells rejected its arguments (rc=%d)" % rc)
+    return out
 
 
 def rhs_jvp(grid, U, V, flags, order=10, splitting=LLF, gamma=1.4):

@@ -565,6 +565,82 @@ double dt_from(const Grid& g, double cfl, const double* amax) {
   return cfl / s;
 }
 
+// Numerical flux of direction d at face f (between cells f-1 and f) of one
+// pencil; cl[l] is the cell record of pencil cell l, l = -G .. n+G-1.
+// Decisions go to flags/margins at fbase + (2 s + side) * nft when given.
+template <class T>
+void face_flux(const Grid& g, const Scheme& sc, double gam, int d, const CellQ<T>* cl, int64_t f, double mu,
+               bool limit, int64_t fbase, int64_t nft, uint8_t* flags, double* margins, const uint8_t* frozen,
+               T* Fo) {
+  const int nd = g.ndim, nv = nd + 2, G = sc.order / 2;
+  const CellQ<T>* win = cl + (f - G);  // window of cells f-G .. f+G-1
+  const CellQ<T>& ca = cl[f - 1];
+  const CellQ<T>& cb = cl[f];
+  Eigen<T> e;
+  roe_eigen(nd, gam, d, ca, cb, e);
+  T v[10], gch[10], gp[10], gm[10], fv[10];
+  T fhat[5];
+  for (int s = 0; s < nv; ++s) {
+    // projection onto field s of the conserved state and physical flux
+    for (int j = 0; j < 2 * G; ++j) {
+      T av = e.L[s][0] * win[j].W[e.perm[0]];
+      T ag = e.L[s][0] * win[j].F[e.perm[0]];
+      for (int c = 1; c < nv; ++c) {
+        av = fmaT(e.L[s][c], win[j].W[e.perm[c]], av);
+        ag = fmaT(e.L[s][c], win[j].F[e.perm[c]], ag);
+      }
+      v[j] = av;
+      gch[j] = ag;
+    }
+    // splitting speed over the window: LLF per field, Rusanov for all fields
+    T alpha = T(-1.0);
+    for (int j = 0; j < 2 * G; ++j) {
+      const T un = win[j].u[d];
+      const T lam = sc.splitting == 0 ? absT(char_speed(nv, s, un, win[j].c)) : absT(un) + win[j].c;
+      if (re(lam) > re(alpha)) alpha = lam;
+    }
+    for (int j = 0; j < 2 * G; ++j) {
+      gp[j] = 0.5 * fmaT(alpha, v[j], gch[j]);
+      gm[j] = 0.5 * fmaT(-alpha, v[j], gch[j]);
+    }
+    T sum = T(0.0);
+    for (int side = 0; side < 2; ++side) {
+      // + side: f_k = g+_{i+k}; - side mirrored: f_k = g-_{i+1-k}
+      for (int k = 0; k < 2 * G; ++k) fv[k] = side == 0 ? gp[k] : gm[2 * G - 1 - k];
+      const int64_t fi = fbase + ((int64_t)s * 2 + side) * nft;
+      Decision dec;
+      const T h = teno_aa(sc.order, fv, &dec, frozen ? frozen + fi : nullptr);
+      if (flags && !frozen) flags[fi] = dec.flag;
+      if (margins && !frozen) margins[fi] = dec.margin;
+      sum = side == 0 ? h : sum + h;
+    }
+    fhat[s] = sum;
+  }
+  // back to conserved components: F = sum_s R[:,s] fhat_s, then axis order
+  for (int c = 0; c < nv; ++c) {
+    T acc = e.R[c][0] * fhat[0];
+    for (int s = 1; s < nv; ++s) acc = fmaT(e.R[c][s], fhat[s], acc);
+    Fo[e.perm[c]] = acc;
+  }
+  if (limit) limit_face(nd, gam, d, mu, ca, cb, Fo);
+}
+
+// Conserved pencil of direction d through (o0, o1) with G ghost cells per
+// side, and its cell records (cells[l + G] for l = -G .. n+G-1).
+template <class T>
+void load_pencil(const Grid& g, double gam, int d, int G, const T* U, int64_t base, std::vector<T>& line,
+                 std::vector<CellQ<T>>& cells) {
+  const int nd = g.ndim, nv = nd + 2;
+  const int64_t n = g.n[d];
+  const int64_t nc = g.n[0] * g.n[1] * g.n[2];
+  const int64_t stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
+  for (int64_t l = 0; l < n; ++l)
+    for (int c = 0; c < nv; ++c) line[(size_t)(l + G) * nv + c] = U[c * nc + base + l * stride[d]];
+  fill_ghosts(nd, d, g.bc_lo[d], true, n, G, line);
+  fill_ghosts(nd, d, g.bc_hi[d], false, n, G, line);
+  for (int64_t l = -G; l < n + G; ++l) cell_state(nd, gam, d, &line[(size_t)(l + G) * nv], cells[(size_t)(l + G)]);
+}
+
 // Semi-discrete right-hand side dU/dt = -sum_d (F_{i+1/2} - F_{i-1/2})/dx_d
 // (Sec. 2, conservative finite-difference form), directions in order x, y, z.
 template <class T>
@@ -594,74 +670,21 @@ int rhs_impl(const Grid& g, const Scheme& sc, double gam, const T* U, T* dU, dou
     std::vector<T> line((size_t)(n + 2 * G) * nv);
     std::vector<CellQ<T>> cells((size_t)(n + 2 * G));
     std::vector<T> Fh((size_t)nf * nv);
-    std::vector<T> v(2 * G), gch(2 * G), gp(2 * G), gm(2 * G), fv(2 * G);
     for (int64_t o1 = 0; o1 < g.n[oa[1]]; ++o1) {
       for (int64_t o0 = 0; o0 < g.n[oa[0]]; ++o0) {
         const int64_t base = o0 * stride[oa[0]] + o1 * stride[oa[1]];
-        for (int64_t l = 0; l < n; ++l)
-          for (int c = 0; c < nv; ++c) line[(size_t)(l + G) * nv + c] = U[c * nc + base + l * stride[d]];
-        fill_ghosts(nd, d, g.bc_lo[d], true, n, G, line);
-        fill_ghosts(nd, d, g.bc_hi[d], false, n, G, line);
-        for (int64_t l = -G; l < n + G; ++l) cell_state(nd, gam, d, &line[(size_t)(l + G) * nv], cells[(size_t)(l + G)]);
+        load_pencil(g, gam, d, G, U, base, line, cells);
         for (int64_t f = 0; f < nf; ++f) {
-          // face between cells f-1 and f; window of cells f-G .. f+G-1
-          const CellQ<T>* win = &cells[(size_t)(f - G + G)];
-          const CellQ<T>& ca = cells[(size_t)(f - 1 + G)];
-          const CellQ<T>& cb = cells[(size_t)(f + G)];
-          Eigen<T> e;
-          roe_eigen(nd, gam, d, ca, cb, e);
           // face linear index inside the flag array of direction d
           int64_t idx[3] = {0, 0, 0};
           idx[d] = f;
           idx[oa[0]] = o0;
           idx[oa[1]] = o1;
-          int64_t m0 = (d == 0) ? nf : g.n[0];
-          int64_t m1 = (d == 1) ? nf : g.n[1];
+          const int64_t m0 = (d == 0) ? nf : g.n[0];
+          const int64_t m1 = (d == 1) ? nf : g.n[1];
           const int64_t flin = (idx[2] * m1 + idx[1]) * m0 + idx[0];
-          T fhat[5];
-          for (int s = 0; s < nv; ++s) {
-            // projection onto field s of the conserved state and physical flux
-            for (int j = 0; j < 2 * G; ++j) {
-              T av = e.L[s][0] * win[j].W[e.perm[0]];
-              T ag = e.L[s][0] * win[j].F[e.perm[0]];
-              for (int c = 1; c < nv; ++c) {
-                av = fmaT(e.L[s][c], win[j].W[e.perm[c]], av);
-                ag = fmaT(e.L[s][c], win[j].F[e.perm[c]], ag);
-              }
-              v[j] = av;
-              gch[j] = ag;
-            }
-            // splitting speed over the window: LLF per field, Rusanov for all fields
-            T alpha = T(-1.0);
-            for (int j = 0; j < 2 * G; ++j) {
-              const T un = win[j].u[d];
-              const T lam = sc.splitting == 0 ? absT(char_speed(nv, s, un, win[j].c)) : absT(un) + win[j].c;
-              if (re(lam) > re(alpha)) alpha = lam;
-            }
-            for (int j = 0; j < 2 * G; ++j) {
-              gp[j] = 0.5 * fmaT(alpha, v[j], gch[j]);
-              gm[j] = 0.5 * fmaT(-alpha, v[j], gch[j]);
-            }
-            T sum = T(0.0);
-            for (int side = 0; side < 2; ++side) {
-              for (int k = 0; k < 2 * G; ++k) fv[k] = side == 0 ? gp[k] : gm[2 * G - 1 - k];
-              const int64_t fi = foff + ((int64_t)s * 2 + side) * nft + flin;
-              Decision dec;
-              const T h = teno_aa(sc.order, fv.data(), &dec, frozen ? frozen + fi : nullptr);
-              if (flags && !frozen) flags[fi] = dec.flag;
-              if (margins && !frozen) margins[fi] = dec.margin;
-              sum = side == 0 ? h : sum + h;
-            }
-            fhat[s] = sum;
-          }
-          // back to conserved components: F = sum_s R[:,s] fhat_s, then axis order
-          T* Fo = &Fh[(size_t)f * nv];
-          for (int c = 0; c < nv; ++c) {
-            T acc = e.R[c][0] * fhat[0];
-            for (int s = 1; s < nv; ++s) acc = fmaT(e.R[c][s], fhat[s], acc);
-            Fo[e.perm[c]] = acc;
-          }
-          if (limit) limit_face(nd, gam, d, mu[d], ca, cb, Fo);
+          face_flux<T>(g, sc, gam, d, cells.data() + G, f, limit ? mu[d] : 0.0, limit, foff + flin, nft, flags,
+                       margins, frozen, &Fh[(size_t)f * nv]);
         }
         for (int64_t i = 0; i < n; ++i) {
           const int64_t fr = periodic ? (i + 1) % n : i + 1;
@@ -786,6 +809,48 @@ int or_rhs(const or_grid* g, int order, int splitting, int positivity, double ga
   double a[3] = {0, 0, 0};
   if (positivity && dt_lim > 0.0) wave_speeds(G, gam, U, a);
   return rhs_impl<double>(G, s, gam, U, dU, dt_lim, a, flags, margins, nullptr);
+}
+
+// dU/dt at the listed cells only (flat cell indices), written to out[k*nv + c].
+// amax (wave speeds of the whole state, for the limiter) may be null when the
+// limiter is off.  Used to check full-size results at sampled cells.
+int or_rhs_cells(const or_grid* g, int order, int splitting, int positivity, double gam, const double* U,
+                 double dt_lim, const double* amax, int64_t ncells, const int64_t* cells, double* out) {
+  build_beta_tables();
+  Grid G = to_grid(g);
+  Scheme s{order, splitting, positivity};
+  if (check_grid(G, s)) return -1;
+  const int nd = G.ndim, nv = nd + 2, Gh = order / 2;
+  const bool limit = positivity && dt_lim > 0.0;
+  double mu[3] = {0, 0, 0};
+  if (limit) {
+    if (!amax) return -1;
+    double S = (dt_lim / G.dx[0]) * amax[0];
+    for (int d = 1; d < nd; ++d) S = S + (dt_lim / G.dx[d]) * amax[d];
+    for (int d = 0; d < nd; ++d) mu[d] = (2.0 * S) / amax[d];
+  }
+  const int64_t stride[3] = {1, G.n[0], G.n[0] * G.n[1]};
+  for (int64_t k = 0; k < ncells; ++k) {
+    const int64_t cell = cells[k];
+    const int64_t co[3] = {cell % G.n[0], (cell / G.n[0]) % G.n[1], cell / (G.n[0] * G.n[1])};
+    double du[5] = {0, 0, 0, 0, 0};
+    for (int d = 0; d < nd; ++d) {
+      const int64_t n = G.n[d];
+      const bool periodic = G.bc_lo[d] == BC_PERIODIC;
+      std::vector<double> line((size_t)(n + 2 * Gh) * nv);
+      std::vector<CellQ<double>> cq((size_t)(n + 2 * Gh));
+      const int64_t base = cell - co[d] * stride[d];
+      load_pencil(G, gam, d, Gh, U, base, line, cq);
+      double Fl[5], Fr[5];
+      const int64_t i = co[d];
+      const int64_t fr = periodic ? (i + 1) % n : i + 1;
+      face_flux<double>(G, s, gam, d, cq.data() + Gh, i, mu[d], limit, 0, 0, nullptr, nullptr, nullptr, Fl);
+      face_flux<double>(G, s, gam, d, cq.data() + Gh, fr, mu[d], limit, 0, 0, nullptr, nullptr, nullptr, Fr);
+      for (int c = 0; c < nv; ++c) du[c] = du[c] - (Fr[c] - Fl[c]) / G.dx[d];
+    }
+    for (int c = 0; c < nv; ++c) out[k * nv + c] = du[c];
+  }
+  return 0;
 }
 
 // RHS with every decision frozen to the given flags, evaluated on U + i*h*V.

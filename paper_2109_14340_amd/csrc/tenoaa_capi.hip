@@ -1,0 +1,229 @@
+// C ABI of libtenoaa (declared in include/tenoaa.h): argument validation,
+// workspace layout and the launch sequence of one right-hand side or one
+// SSP-RK3 step.  Nothing here allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "tenoaa.h"
+#include "tenoaa_internal.h"
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip_error = (int)e;
+  return TENOAA_EHIP;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+bool valid_grid(const tenoaa_grid* g, const tenoaa_scheme* s) {
+  if (!g || !s) return false;
+  if (g->ndim < 1 || g->ndim > 3) return false;
+  if (s->order != 8 && s->order != 10) return false;
+  if (s->splitting != TENOAA_LLF && s->splitting != TENOAA_RUSANOV) return false;
+  if (s->positivity != 0 && s->positivity != 1) return false;
+  for (int d = 0; d < 3; ++d) {
+    if (d < g->ndim) {
+      if (g->n[d] < s->order / 2 || !(g->dx[d] > 0.0)) return false;
+      if (g->bc_lo[d] < 0 || g->bc_lo[d] > 3 || g->bc_hi[d] < 0 || g->bc_hi[d] > 3) return false;
+      if ((g->bc_lo[d] == TENOAA_BC_PERIODIC) != (g->bc_hi[d] == TENOAA_BC_PERIODIC)) return false;
+    } else if (g->n[d] != 1) {
+      return false;
+    }
+  }
+  // flat indices stay within int64 and the grid within a launch's z extent
+  const double cells = (double)g->n[0] * (double)g->n[1] * (double)g->n[2];
+  if (cells * (g->ndim + 2) > 9.0e15) return false;
+  return true;
+}
+
+int64_t faces_along(const tenoaa_grid* g, int d) {
+  return g->bc_lo[d] == TENOAA_BC_PERIODIC ? g->n[d] : g->n[d] + 1;
+}
+
+int64_t faces_total(const tenoaa_grid* g, int d) {
+  int64_t t = faces_along(g, d);
+  for (int k = 0; k < 3; ++k)
+    if (k != d) t *= g->n[k];
+  return t;
+}
+
+struct Layout {
+  size_t scalars;       // offset of tenoaa::Scalars
+  size_t fbuf[3];       // face flux arrays per direction
+  size_t stage;         // RK stage state (step only)
+  size_t total;
+};
+
+Layout layout(const tenoaa_grid* g, int which) {
+  Layout L;
+  const int nv = g->ndim + 2;
+  const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
+  size_t off = 0;
+  L.scalars = off;
+  off += align256(sizeof(tenoaa::Scalars));
+  for (int d = 0; d < 3; ++d) {
+    L.fbuf[d] = off;
+    if (d < g->ndim) off += align256((size_t)nv * (size_t)faces_total(g, d) * sizeof(double));
+  }
+  L.stage = off;
+  if (which == TENOAA_WS_STEP) off += align256((size_t)nv * (size_t)ncell * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+struct Ctx {
+  const tenoaa_grid* g;
+  const tenoaa_scheme* s;
+  double gamma;
+  char* ws;
+  Layout L;
+  tenoaa::Scalars* S;
+  hipStream_t st;
+};
+
+// Face fluxes of every direction for state U; flags optional.
+int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags) {
+  const tenoaa_grid* g = c.g;
+  const int nv = g->ndim + 2;
+  int64_t flag_off = 0;
+  for (int d = 0; d < g->ndim; ++d) {
+    tenoaa::SweepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.U = U;
+    a.F = reinterpret_cast<double*>(c.ws + c.L.fbuf[d]);
+    a.flags = flags ? flags + flag_off : nullptr;
+    for (int k = 0; k < 3; ++k) a.n[k] = g->n[k];
+    a.nf = faces_along(g, d);
+    a.nft = faces_total(g, d);
+    a.bc_lo = g->bc_lo[d];
+    a.bc_hi = g->bc_hi[d];
+    a.splitting = c.s->splitting;
+    a.gamma = c.gamma;
+    a.mu = c.S->mu;
+    a.status = &c.S->status;
+    hipError_t e = tenoaa::launch_sweep(c.s->order, g->ndim, d, a, limit, flags != nullptr, c.st);
+    if (e != hipSuccess) return hip_fail(e);
+    flag_off += (int64_t)nv * 2 * a.nft;
+  }
+  return TENOAA_OK;
+}
+
+int update(const Ctx& c, int mode, const double* Un, const double* Us, double* out) {
+  const tenoaa_grid* g = c.g;
+  tenoaa::UpdateArgs a;
+  std::memset(&a, 0, sizeof(a));
+  for (int d = 0; d < 3; ++d) {
+    a.F[d] = reinterpret_cast<const double*>(c.ws + c.L.fbuf[d]);
+    a.nft[d] = d < g->ndim ? faces_total(g, d) : 0;
+    a.nf[d] = d < g->ndim ? faces_along(g, d) : 1;
+    a.n[d] = g->n[d];
+    a.dx[d] = g->dx[d];
+  }
+  a.Un = Un;
+  a.Us = Us;
+  a.out = out;
+  a.dt = &c.S->dt;
+  hipError_t e = tenoaa::launch_update(g->ndim, mode, a, c.st);
+  return e == hipSuccess ? TENOAA_OK : hip_fail(e);
+}
+
+int prepare(Ctx& c, const tenoaa_grid* g, const tenoaa_scheme* s, double gamma, void* ws, size_t ws_bytes,
+            void* stream, int which) {
+  if (!valid_grid(g, s) || !(gamma > 1.0) || !ws) return TENOAA_EINVAL;
+  if (((uintptr_t)ws & 255) != 0) return TENOAA_EINVAL;
+  c.g = g;
+  c.s = s;
+  c.gamma = gamma;
+  c.ws = static_cast<char*>(ws);
+  c.L = layout(g, which);
+  if (ws_bytes < c.L.total) return TENOAA_EWORKSPACE;
+  c.S = reinterpret_cast<tenoaa::Scalars*>(c.ws + c.L.scalars);
+  c.st = static_cast<hipStream_t>(stream);
+  return TENOAA_OK;
+}
+
+// First device work of an entry point, after every argument check passed.
+int begin(const Ctx&) {
+  hipError_t e = tenoaa::upload_constants();
+  return e == hipSuccess ? TENOAA_OK : hip_fail(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tenoaa_workspace_bytes(const tenoaa_grid* grid, const tenoaa_scheme* scheme, int32_t which) {
+  if (!valid_grid(grid, scheme)) return 0;
+  if (which != TENOAA_WS_RHS && which != TENOAA_WS_STEP) return 0;
+  return layout(grid, which).total;
+}
+
+int tenoaa_rhs(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U, double* dUdt,
+               double dt_limiter, uint8_t* flags, void* ws, size_t ws_bytes, void* stream) {
+  Ctx c;
+  int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_RHS);
+  if (rc) return rc;
+  if (!U || !dUdt || U == dUdt) return TENOAA_EINVAL;
+  if ((rc = begin(c))) return rc;
+  const bool limit = scheme->positivity && dt_limiter > 0.0;
+  const int64_t ncell = grid->n[0] * grid->n[1] * grid->n[2];
+  if (limit) {
+    hipError_t e = tenoaa::launch_wave_speeds(grid->ndim, U, ncell, gamma, c.S, &c.S->status, c.st);
+    if (e == hipSuccess) e = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, 1.0, nullptr, dt_limiter, c.st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  rc = sweeps(c, U, limit, flags);
+  if (rc) return rc;
+  return update(c, 0, nullptr, nullptr, dUdt);
+}
+
+int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,
+                double* dt_dev, void* ws, size_t ws_bytes, void* stream) {
+  Ctx c;
+  int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP);
+  if (rc) return rc;
+  if (!U || !dt_dev) return TENOAA_EINVAL;
+  if (!(cfl > 0.0) || cfl > 1.0) return TENOAA_EINVAL;
+  if (scheme->positivity && cfl > 0.5) return TENOAA_EINVAL;
+  if ((rc = begin(c))) return rc;
+  const int64_t ncell = grid->n[0] * grid->n[1] * grid->n[2];
+  double* Us = reinterpret_cast<double*>(c.ws + c.L.stage);
+  const bool limit = scheme->positivity != 0;
+  hipError_t e = tenoaa::launch_wave_speeds(grid->ndim, U, ncell, gamma, c.S, &c.S->status, c.st);
+  if (e == hipSuccess) e = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, cfl, dt_dev, 0.0, c.st);
+  if (e != hipSuccess) return hip_fail(e);
+  // stage 1: U1 = Un + dt L(Un)            -> Us
+  if ((rc = sweeps(c, U, limit, nullptr))) return rc;
+  if ((rc = update(c, 1, U, nullptr, Us))) return rc;
+  // stage 2: U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1)   -> Us (in place)
+  if ((rc = sweeps(c, Us, limit, nullptr))) return rc;
+  if ((rc = update(c, 2, U, Us, Us))) return rc;
+  // stage 3: U = 1/3 Un + 2/3 U2 + 2/3 dt L(U2)    -> U (in place)
+  if ((rc = sweeps(c, Us, limit, nullptr))) return rc;
+  return update(c, 3, U, Us, U);
+}
+
+int tenoaa_get_status(void* ws, void* stream, int32_t* out) {
+  if (!ws || !out) return TENOAA_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  tenoaa::Scalars* S = reinterpret_cast<tenoaa::Scalars*>(ws);
+  int v = 0;
+  hipError_t e = hipMemcpyAsync(&v, &S->status, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  const int zero = 0;
+  e = hipMemcpyAsync(&S->status, &zero, sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  *out = v ? 1 : 0;
+  return v ? TENOAA_ENONPHYSICAL : TENOAA_OK;
+}
+
+int tenoaa_last_hip_error(void) { return g_last_hip_error; }
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// Internal interface between the C ABI layer and the kernels of libtenoaa.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "tenoaa.h"
+
+namespace tenoaa {
+
+// Device-resident scalars at the head of every workspace.
+struct Scalars {
+  unsigned long long amax_bits[3];  // max_cells |u_d| + c, as bit patterns
+  double dt;
+  double mu[3];  // limiter factors kappa_d * dt / dx_d
+  int status;    // 0 = ok, 1 = a non-physical state was read
+  int pad;
+};
+
+struct SweepArgs {
+  const double* U;
+  double* F;        // face fluxes of this direction, [nvar][nft]
+  uint8_t* flags;   // flags of this direction, [nvar][2][nft], or null
+  int64_t n[3];
+  int64_t nf;       // faces along the direction
+  int64_t nft;      // faces of the direction in total
+  int bc_lo, bc_hi;
+  int splitting;
+  int pad;
+  double gamma;
+  const double* mu; // device: limiter factors
+  int* status;      // device: status word
+};
+
+struct UpdateArgs {
+  const double* F[3];
+  int64_t nft[3];
+  int64_t nf[3];
+  int64_t n[3];
+  double dx[3];
+  const double* Un;
+  const double* Us;
+  double* out;
+  const double* dt;  // device
+};
+
+hipError_t upload_constants();
+hipError_t launch_sweep(int order, int ndim, int dir, const SweepArgs& a, bool limit, bool flags, hipStream_t st);
+hipError_t launch_update(int ndim, int mode, const UpdateArgs& a, hipStream_t st);
+hipError_t launch_wave_speeds(int ndim, const double* U, int64_t ncell, double gam, Scalars* S, int* status,
+                              hipStream_t st);
+hipError_t launch_finalize_dt(Scalars* S, int ndim, const double* dx, double cfl, double* dt_dev, double dt_fixed,
+                              hipStream_t st);
+
+}  // namespace tenoaa

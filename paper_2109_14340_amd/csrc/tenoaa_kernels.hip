@@ -1,0 +1,712 @@
+// TENO-AA8/10 Euler right-hand side: HIP kernels for gfx950 (FP64 VALU).
+//
+// One sweep kernel per direction evaluates every face flux of that direction:
+// a block stages a tile of cells (plus the reconstruction halo, with the
+// boundary conditions applied by index mapping) in LDS as per-cell records
+// (conserved state and physical flux in the face's local frame, normal and
+// tangential velocity, sound speed, sqrt(rho), enthalpy), then each thread
+// takes one face: Roe average and eigenvectors (Sec. 5 of the paper),
+// projection of the window onto one characteristic field at a time, LLF or
+// Rusanov splitting, the scalar TENO-AA reconstruction of both split sides
+// (Sec. 3, 4), back-projection and the optional positivity limiter.  Face
+// fluxes go to a face array; a separate element-wise kernel forms the flux
+// difference and the SSP-RK3 stage.
+//
+// Bit-for-bit agreement with the reference evaluation.  Every value that
+// feeds a threshold decision (the split characteristic fluxes) is computed
+// with one fixed order of IEEE operations: no contraction (this file is built
+// with -ffp-contract=off), fma only where written, correctly rounded division
+// and square root.  The smoothness indicators, the scale-separation test and
+// the C_T bucket may differ from a reference evaluation by a few ulps, which
+// can only move a decision that lies within ~1e-14 of its threshold.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "tenoaa_internal.h"
+#include "tenoaa_sos.h"
+
+namespace tenoaa {
+namespace {
+
+// ---------------------------------------------------------------- constants
+// Sec. 3.2: eps of the scale-separation formula, q = 7.
+constexpr double EPS = 1e-40;
+// Sec. 3.4: C_r, alpha_1, alpha_2; C_T = 10^{-K}, K = 7..14.
+constexpr double C_R = 0.265;
+constexpr double ALPHA1 = 14.0;
+constexpr double ALPHA2 = 6.4;
+__constant__ double c_ct[8] = {1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12, 1e-13, 1e-14};
+// Sec. 4.1 / 4.2: linear schemes on S3, S4, S5, leftmost coefficient first.
+constexpr double LIN6[6] = {0.02852274270130377, -0.1714015614372447, 0.650378818735941,
+                            0.6253788187359414, -0.1589015614372448, 0.02602274270130375};
+constexpr double LIN8[8] = {-0.006866688980568011, 0.05128582585522106, -0.1968478198727312,
+                            0.6552858258552222,    0.6452858258552218,  -0.1908478198727314,
+                            0.04928582585522098,   -0.006580974694853729};
+constexpr double LIN10[10] = {0.001911786299492748, -0.0170332977472532, 0.07339445614860979,
+                              -0.221228429084247,   0.6657332621611695,  0.6557332621611695,
+                              -0.2145617624175796,  0.07053731329146805, -0.01631901203296621,
+                              0.001832421220128962};
+// Fallback weights w_k = d_k delta_k / sum_l d_l delta_l for the 8 delta masks
+// (d_k of Sec. 4.1), filled by the host with the same IEEE expressions.
+__constant__ double c_wfall[8][3];
+
+// -------------------------------------------------------------- small math
+// Compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1, so
+// every index into a register array or constant table is a constant.
+template <int N, class F>
+__device__ __forceinline__ void unroll(F&& f) {
+  if constexpr (N > 0) {
+    unroll<N - 1>(f);
+    f(std::integral_constant<int, N - 1>{});
+  }
+}
+
+__device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
+
+// Reciprocal for decision-only quantities: hardware estimate + two Newton steps.
+__device__ __forceinline__ double rcp_dec(double x) { return 1.0 / x; }
+
+// ------------------------------------------------- scalar TENO-AA (Sec. 3-4)
+// v[0..W-1] = f_{i-G+1..i+G}.  Returns fhat_{i+1/2}; *flag gets the decision
+// byte (bits 0-1 large stencil, 2-4 deltas, 5-7 K-7).
+template <int ORDER>
+__device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& flag) {
+  constexpr int G = ORDER / 2;
+  constexpr int I = G - 1;  // index of f_i
+
+  // forward difference table along the window: d1[q] = f_{q+1} - f_q, ...
+  double d1[ORDER - 1];
+  unroll<ORDER - 1>([&](auto q) { d1[q] = v[q + 1] - v[q]; });
+
+  // Sec. 3.4: eta_j, j = -1..2 (a = f_{j+1} - f_j, b = f_j - f_{j-1}).
+  double etabar = 0.0;
+  unroll<4>([&](auto jj) {
+    const int j = jj - 1;
+    const double a = d1[I + j];
+    const double b = d1[I + j - 1];
+    const double eta = (fabs((2.0 * a) * b) + EPS) / ((a * a + b * b) + EPS);
+    if (jj == 0 || eta < etabar) etabar = eta;
+  });
+  double ratio = etabar / C_R;
+  if (ratio > 1.0) ratio = 1.0;
+  const double m = 1.0 - ratio;
+  const double om = 1.0 - m;
+  const double om2 = om * om;
+  const double g = (om2 * om2) * (1.0 + 4.0 * m);
+  const double B = ALPHA1 - ALPHA2 * (1.0 - g);
+  int K = (int)floor(B);
+  K = K < 7 ? 7 : (K > 14 ? 14 : K);
+  const double CT = c_ct[K - 7];
+
+  // small stencils (Sec. 4.2, printed WENO-JS indicators) in difference form
+  const double b0a = d1[I - 1] + d1[I];          // f_{i+1} - f_{i-1}
+  const double b0b = d1[I] - d1[I - 1];          // second difference at i
+  const double b1a = (d1[I + 1] - d1[I]) - 2.0 * d1[I];  // 3f_i - 4f_{i+1} + f_{i+2}, negated
+  const double b1b = d1[I + 1] - d1[I];
+  const double b2a = (d1[I - 1] - d1[I - 2]) + 2.0 * d1[I - 1];  // f_{i-2} - 4f_{i-1} + 3f_i
+  const double b2b = d1[I - 1] - d1[I - 2];
+  constexpr double C13 = 13.0 / 12.0;
+  const double beta0 = fma(C13, b0b * b0b, 0.25 * (b0a * b0a));
+  const double beta1 = fma(C13, b1b * b1b, 0.25 * (b1a * b1a));
+  const double beta2 = fma(C13, b2b * b2b, 0.25 * (b2a * b2a));
+  auto gam7 = [](double beta) {
+    const double r = rcp_dec(beta + EPS);
+    const double r2 = r * r;
+    const double r4 = r2 * r2;
+    return (r4 * r2) * r;
+  };
+  const double g0 = gam7(beta0), g1 = gam7(beta1), g2 = gam7(beta2);
+  const double S = (g0 + g1) + g2;
+  const uint8_t kbits = (uint8_t)((K - 7) << 5);
+
+  // large stencils, largest first (Sec. 3.3)
+  // full difference table of the window, needed for the sums of squares
+  double tab[ORDER - 1][ORDER - 1];
+  unroll<ORDER - 1>([&](auto q) { tab[0][q] = d1[q]; });
+  unroll<ORDER - 2>([&](auto mm) {
+    constexpr int m1 = decltype(mm)::value + 1;
+    unroll<ORDER - 1 - m1>([&](auto q) { tab[m1][q] = tab[m1 - 1][q + 1] - tab[m1 - 1][q]; });
+  });
+
+  auto accept = [&](double beta) {
+    const double gp = gam7(beta);
+    return gp >= CT * (S + gp);
+  };
+  if constexpr (ORDER == 10) {
+    // S5 = cells i-4..i+5 = whole window, differences from position 0
+    double beta = 0.0;
+    unroll<9>([&](auto k) {
+      double y = 0.0;
+      unroll<9>([&](auto m) {
+        if (m >= k && SOS_S5_L[m][k] != 0.0) y = fma(SOS_S5_L[m][k], tab[m][0], y);
+      });
+      beta = fma(SOS_S5_D[k], y * y, beta);
+    });
+    if (accept(beta)) {
+      flag = (uint8_t)(3 | kbits);
+      double acc = LIN10[0] * v[0];
+      unroll<9>([&](auto q) { acc = fma(LIN10[q + 1], v[q + 1], acc); });
+      return acc;
+    }
+  }
+  {
+    // S4 = cells i-3..i+4
+    constexpr int P = (ORDER == 10) ? 1 : 0;
+    double beta = 0.0;
+    unroll<7>([&](auto k) {
+      double y = 0.0;
+      unroll<7>([&](auto m) {
+        if (m >= k && SOS_S4_L[m][k] != 0.0) y = fma(SOS_S4_L[m][k], tab[m][P], y);
+      });
+      beta = fma(SOS_S4_D[k], y * y, beta);
+    });
+    if (accept(beta)) {
+      flag = (uint8_t)(2 | kbits);
+      double acc = LIN8[0] * v[P];
+      unroll<7>([&](auto q) { acc = fma(LIN8[q + 1], v[P + q + 1], acc); });
+      return acc;
+    }
+  }
+  {
+    // S3 = cells i-2..i+3
+    constexpr int P = (ORDER == 10) ? 2 : 1;
+    double beta = 0.0;
+    unroll<5>([&](auto k) {
+      double y = 0.0;
+      unroll<5>([&](auto m) {
+        if (m >= k && SOS_S3_L[m][k] != 0.0) y = fma(SOS_S3_L[m][k], tab[m][P], y);
+      });
+      beta = fma(SOS_S3_D[k], y * y, beta);
+    });
+    if (accept(beta)) {
+      flag = (uint8_t)(1 | kbits);
+      double acc = LIN6[0] * v[P];
+      unroll<5>([&](auto q) { acc = fma(LIN6[q + 1], v[P + q + 1], acc); });
+      return acc;
+    }
+  }
+  // fallback: TENO5 cut-off among the small stencils (Sec. 3.3)
+  const int dm = (g0 >= CT * S ? 1 : 0) | (g1 >= CT * S ? 2 : 0) | (g2 >= CT * S ? 4 : 0);
+  flag = (uint8_t)((dm << 2) | kbits);
+  const double fm1 = v[I - 1], f0 = v[I], f1 = v[I + 1];
+  const double h0 = ((-fm1 + 5.0 * f0) + 2.0 * f1) / 6.0;
+  const double h1 = ((2.0 * f0 + 5.0 * f1) - v[I + 2]) / 6.0;
+  const double h2 = ((2.0 * v[I - 2] - 7.0 * fm1) + 11.0 * f0) / 6.0;
+  return fma(c_wfall[dm][2], h2, fma(c_wfall[dm][1], h1, c_wfall[dm][0] * h0));
+}
+
+// ------------------------------------------------------------ sweep kernel
+// Local frame of direction DIR: component 0 = rho, 1 = normal momentum,
+// 2.. = tangential momenta in ascending axis order, last = E.
+template <int NDIM, int DIR>
+struct Frame {
+  static constexpr int NV = NDIM + 2;
+  // axis index of tangential k (k = 0 .. NDIM-2)
+  static __host__ __device__ constexpr int tan_axis(int k) { return (k < DIR) ? k : k + 1; }
+  // local velocity slot (0 = normal, 1 + k = tangential k) of axis a
+  static __host__ __device__ constexpr int slot_of_axis(int a) {
+    return a == DIR ? 0 : (a < DIR ? 1 + a : a);
+  }
+};
+
+template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT, bool FLAGS>
+__global__ __launch_bounds__(TT* TN) void sweep_kernel(SweepArgs A) {
+  constexpr int G = ORDER / 2;
+  constexpr int W = ORDER;
+  constexpr int NV = NDIM + 2;
+  constexpr int NT = (NDIM > 1) ? NDIM - 1 : 1;
+  constexpr int NC = TN + W - 1;  // cells along the normal in the tile
+  constexpr int NCT = TT * NC;
+  constexpr int AX_A = (DIR == 0) ? 1 : 0;  // transverse axis mapped to threadIdx (x unless DIR == 0)
+  constexpr int AX_B = (DIR == 2) ? 1 : 2;  // remaining axis (blockIdx.z)
+  using Fr = Frame<NDIM, DIR>;
+
+  __shared__ double sW[NV][NCT];
+  __shared__ double sF[NV][NCT];
+  __shared__ double sUn[NCT], sC[NCT], sSr[NCT], sH[NCT];
+  __shared__ double sUt[NT][NCT];
+
+  const int64_t nN = A.n[DIR];
+  const int64_t nA = A.n[AX_A];
+  const int64_t stride[3] = {1, A.n[0], A.n[0] * A.n[1]};
+  const int64_t ncell = A.n[0] * A.n[1] * A.n[2];
+  const int64_t f0 = (int64_t)blockIdx.x * TN;
+  const int64_t t0 = (int64_t)blockIdx.y * TT;
+  const int64_t bcoord = blockIdx.z;
+  const double gam = A.gamma;
+  const double gm1 = gam - 1.0;
+
+  // ---- stage the tile: cells f0-G .. f0+TN+G-2 along the normal
+  for (int ct = threadIdx.x; ct < NCT; ct += TT * TN) {
+    int tt, nn;
+    if (DIR == 0) {
+      tt = ct / NC;
+      nn = ct % NC;
+    } else {
+      tt = ct % TT;
+      nn = ct / TT;
+    }
+    int64_t t = t0 + tt;
+    if (t >= nA) t = nA - 1;
+    int64_t l = f0 - G + nn;
+    bool mirror = false;
+    int bc = -1;
+    if (l < 0 || l >= nN) {
+      bc = (l < 0) ? A.bc_lo : A.bc_hi;
+      if (bc == TENOAA_BC_PERIODIC) {
+        l = ((l % nN) + nN) % nN;
+      } else if (bc == TENOAA_BC_OUTFLOW) {
+        l = (l < 0) ? 0 : nN - 1;
+      } else {
+        l = (l < 0) ? -l - 1 : 2 * nN - 1 - l;
+        mirror = true;
+      }
+      if (l < 0) l = 0;
+      if (l >= nN) l = nN - 1;
+    }
+    const int64_t off = l * stride[DIR] + t * stride[AX_A] + bcoord * stride[AX_B];
+    double Wc[NV];
+    unroll<NV>([&](auto c) { Wc[c] = A.U[c * ncell + off]; });
+    if (mirror) {
+      if (bc == TENOAA_BC_SYMMETRY) {
+        Wc[1 + DIR] = -Wc[1 + DIR];
+      } else {
+        unroll<NDIM>([&](auto k) { Wc[1 + k] = -Wc[1 + k]; });
+      }
+    }
+    // cell primitives (Sec. 1), axis order
+    const double rho = Wc[0];
+    double u[NDIM];
+    double q2 = 0.0;
+    unroll<NDIM>([&](auto k) {
+      u[k] = Wc[1 + k] / rho;
+      q2 = (k == 0) ? u[0] * u[0] : q2 + u[k] * u[k];
+    });
+    const double E = Wc[NV - 1];
+    const double p = gm1 * (E - (0.5 * rho) * q2);
+    const double c = sqrt((gam * p) / rho);
+    const double H = (E + p) / rho;
+    const double sr = sqrt(rho);
+    const double un = u[DIR];
+    if (!(rho > 0.0) || !(p > 0.0)) atomicOr(A.status, 1);
+    // physical flux along DIR, written in the local frame
+    sW[0][ct] = rho;
+    sF[0][ct] = Wc[1 + DIR];
+    unroll<NDIM>([&](auto k) {
+      const int slot = Fr::slot_of_axis(k);
+      sW[1 + slot][ct] = Wc[1 + k];
+      sF[1 + slot][ct] = (k == DIR) ? Wc[1 + k] * un + p : Wc[1 + k] * un;
+      if (slot > 0) sUt[slot - 1][ct] = u[k];
+    });
+    sW[NV - 1][ct] = E;
+    sF[NV - 1][ct] = (E + p) * un;
+    sUn[ct] = un;
+    sC[ct] = c;
+    sSr[ct] = sr;
+    sH[ct] = H;
+  }
+  __syncthreads();
+
+  // ---- one face per thread
+  int tt, fn;
+  if (DIR == 0) {
+    tt = threadIdx.x / TN;
+    fn = threadIdx.x % TN;
+  } else {
+    tt = threadIdx.x % TT;
+    fn = threadIdx.x / TT;
+  }
+  const int64_t f = f0 + fn;
+  const int64_t t = t0 + tt;
+  if (f >= A.nf || t >= nA) return;
+  auto lidx = [&](int j) { return (DIR == 0) ? tt * NC + fn + j : (fn + j) * TT + tt; };
+  const int ia = lidx(G - 1), ib = lidx(G);
+
+  // Roe average (Sec. 5: characteristic decomposition at the face)
+  const double sa = sSr[ia], sb = sSr[ib];
+  const double den = sa + sb;
+  const double un = (sa * sUn[ia] + sb * sUn[ib]) / den;
+  double ut[NT];
+  unroll<NDIM - 1>([&](auto k) { ut[k] = (sa * sUt[k][ia] + sb * sUt[k][ib]) / den; });
+  // |u|^2 summed in axis order
+  double q2 = 0.0;
+  unroll<NDIM>([&](auto a) {
+    const int slot = Fr::slot_of_axis(a);
+    const double ua = (slot == 0) ? un : ut[slot - 1];
+    q2 = (a == 0) ? ua * ua : q2 + ua * ua;
+  });
+  const double Hr = (sa * sH[ia] + sb * sH[ib]) / den;
+  const double qq = 0.5 * q2;
+  const double c2 = gm1 * (Hr - qq);
+  const double cr = sqrt(c2);
+  const double b1 = gm1 / c2;
+  const double b2 = b1 * qq;
+  const double unc = un / cr;
+  const double ic = 1.0 / cr;
+
+  // splitting speeds over the window
+  double am = 0.0, a0 = 0.0, ap = 0.0, ar = 0.0;
+  unroll<W>([&](auto j) {
+    const int li = lidx(j);
+    const double u = sUn[li], c = sC[li];
+    if (A.splitting == TENOAA_LLF) {
+      am = dmax(am, fabs(u - c));
+      a0 = dmax(a0, fabs(u));
+      ap = dmax(ap, fabs(u + c));
+    } else {
+      ar = dmax(ar, fabs(u) + c);
+    }
+  });
+  if (A.splitting != TENOAA_LLF) am = a0 = ap = ar;
+
+  double Fh[NV];  // back-projected flux, local frame
+  uint8_t* flag_out = nullptr;
+  int64_t flin = 0;
+  {
+    int64_t fs_n = 1, fs_a = 1, fs_b = 1;  // face-array strides
+    int64_t m[3] = {A.n[0], A.n[1], A.n[2]};
+    m[DIR] = A.nf;
+    const int64_t fstr[3] = {1, m[0], m[0] * m[1]};
+    fs_n = fstr[DIR];
+    fs_a = fstr[AX_A];
+    fs_b = fstr[AX_B];
+    flin = f * fs_n + t * fs_a + bcoord * fs_b;
+    if (FLAGS) flag_out = A.flags + flin;
+  }
+
+  unroll<NV>([&](auto s) {
+    // left eigenvector row s (local frame)
+    double L[NV];
+    unroll<NV>([&](auto c) { L[c] = 0.0; });
+    if (s == 0 || s == NV - 1) {
+      const double sg = (s == 0) ? 1.0 : -1.0;
+      L[0] = (s == 0) ? 0.5 * (b2 + unc) : 0.5 * (b2 - unc);
+      L[1] = (s == 0) ? 0.5 * (-b1 * un - ic) : 0.5 * (-b1 * un + ic);
+      unroll<NDIM - 1>([&](auto k) { L[2 + k] = 0.5 * (-b1 * ut[k]); });
+      L[NV - 1] = 0.5 * b1;
+      (void)sg;
+    } else if (s == 1) {
+      L[0] = 1.0 - b2;
+      L[1] = b1 * un;
+      unroll<NDIM - 1>([&](auto k) { L[2 + k] = b1 * ut[k]; });
+      L[NV - 1] = -b1;
+    }
+    // projection of the window's state and flux on field s
+    double gp[W], gm[W];
+    const double alpha = (s == 0) ? am : (s == NV - 1 ? ap : a0);
+    unroll<W>([&](auto j) {
+      const int li = lidx(j);
+      double v, g;
+      if (s == 0 || s == 1 || s == NV - 1) {
+        v = L[0] * sW[0][li];
+        g = L[0] * sF[0][li];
+        unroll<NV - 1>([&](auto cc) {
+          v = fma(L[cc + 1], sW[cc + 1][li], v);
+          g = fma(L[cc + 1], sF[cc + 1][li], g);
+        });
+      } else {
+        const double mu_t = -ut[s - 2];
+        v = mu_t * sW[0][li] + sW[s][li];
+        g = mu_t * sF[0][li] + sF[s][li];
+      }
+      gp[j] = 0.5 * fma(alpha, v, g);
+      gm[j] = 0.5 * fma(-alpha, v, g);
+    });
+    uint8_t flp = 0, flm = 0;
+    const double hp = teno_aa<ORDER>(gp, flp);
+    double gr[W];
+    unroll<W>([&](auto j) { gr[j] = gm[W - 1 - j]; });
+    const double hm = teno_aa<ORDER>(gr, flm);
+    if (FLAGS) {
+      flag_out[(int64_t)(s * 2 + 0) * A.nft] = flp;
+      flag_out[(int64_t)(s * 2 + 1) * A.nft] = flm;
+    }
+    const double fh = hp + hm;
+    // back-projection: F += R[:, s] * fh, accumulated over s in order
+    if (s == 0) {
+      Fh[0] = fh;
+      Fh[1] = (un - cr) * fh;
+      unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = ut[k] * fh; });
+      Fh[NV - 1] = (Hr - un * cr) * fh;
+    } else if (s == 1) {
+      Fh[0] = Fh[0] + fh;
+      Fh[1] = fma(un, fh, Fh[1]);
+      unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = fma(ut[k], fh, Fh[2 + k]); });
+      Fh[NV - 1] = fma(qq, fh, Fh[NV - 1]);
+    } else if (s == NV - 1) {
+      Fh[0] = Fh[0] + fh;
+      Fh[1] = fma(un + cr, fh, Fh[1]);
+      unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = fma(ut[k], fh, Fh[2 + k]); });
+      Fh[NV - 1] = fma(Hr + un * cr, fh, Fh[NV - 1]);
+    } else {
+      Fh[s] = Fh[s] + fh;
+      Fh[NV - 1] = fma(ut[s - 2], fh, Fh[NV - 1]);
+    }
+  });
+
+  if (LIMIT) {
+    // Positivity limiter (reading of Hu, Adams & Shu 2013, applied in Sec. 5.3).
+    const double mu = A.mu[DIR];
+    const double sA = fabs(sUn[ia]) + sC[ia];
+    const double sB = fabs(sUn[ib]) + sC[ib];
+    const double aL = (sA >= sB) ? sA : sB;
+    double FL[NV];
+    unroll<NV>([&](auto c) { FL[c] = 0.5 * ((sF[c][ia] + sF[c][ib]) - aL * (sW[c][ib] - sW[c][ia])); });
+    auto pressure = [&](const double (&X)[NV]) {
+      const double rho = X[0];
+      double q = 0.0;
+      unroll<NDIM>([&](auto a) {
+        const double ua = X[1 + Fr::slot_of_axis(a)] / rho;
+        q = (a == 0) ? ua * ua : q + ua * ua;
+      });
+      return gm1 * (X[NV - 1] - (0.5 * rho) * q);
+    };
+    double th_r = 1.0;
+    unroll<2>([&](auto side) {
+      const int li = side == 0 ? ia : ib;
+      const double sg = side == 0 ? -1.0 : 1.0;
+      const double rL = sW[0][li] + (sg * mu) * FL[0];
+      const double rH = sW[0][li] + (sg * mu) * Fh[0];
+      const double eps = rL < 1e-13 ? rL : 1e-13;
+      const double th = (rH < eps) ? (rL - eps) / (rL - rH) : 1.0;
+      th_r = th < th_r ? th : th_r;
+    });
+    double Fs[NV];
+    unroll<NV>([&](auto c) { Fs[c] = (th_r < 1.0) ? FL[c] + th_r * (Fh[c] - FL[c]) : Fh[c]; });
+    double th_p = 1.0;
+    unroll<2>([&](auto side) {
+      const int li = side == 0 ? ia : ib;
+      const double sg = side == 0 ? -1.0 : 1.0;
+      double X[NV];
+      unroll<NV>([&](auto c) { X[c] = sW[c][li] + (sg * mu) * FL[c]; });
+      const double pL = pressure(X);
+      unroll<NV>([&](auto c) { X[c] = sW[c][li] + (sg * mu) * Fs[c]; });
+      const double pS = pressure(X);
+      const double eps = pL < 1e-13 ? pL : 1e-13;
+      const double th = (pS < eps) ? (pL - eps) / (pL - pS) : 1.0;
+      th_p = th < th_p ? th : th_p;
+    });
+    unroll<NV>([&](auto c) { Fh[c] = (th_p < 1.0) ? FL[c] + th_p * (Fs[c] - FL[c]) : Fs[c]; });
+  }
+
+  // store in axis order
+  A.F[0 * A.nft + flin] = Fh[0];
+  A.F[(int64_t)(NV - 1) * A.nft + flin] = Fh[NV - 1];
+  unroll<NDIM>([&](auto a) { A.F[(int64_t)(1 + a) * A.nft + flin] = Fh[1 + Fr::slot_of_axis(a)]; });
+}
+
+// --------------------------------------------------- flux difference / RK
+template <int NDIM, int MODE>
+__global__ __launch_bounds__(256) void update_kernel(UpdateArgs A) {
+  constexpr int NV = NDIM + 2;
+  const int64_t ncell = A.n[0] * A.n[1] * A.n[2];
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ncell;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t co[3];
+    co[0] = idx % A.n[0];
+    co[1] = (idx / A.n[0]) % A.n[1];
+    co[2] = idx / (A.n[0] * A.n[1]);
+    int64_t fl[3], fr[3];
+    unroll<NDIM>([&](auto d) {
+      int64_t m[3] = {A.n[0], A.n[1], A.n[2]};
+      m[d] = A.nf[d];
+      const int64_t fs[3] = {1, m[0], m[0] * m[1]};
+      int64_t c2[3] = {co[0], co[1], co[2]};
+      fl[d] = c2[0] * fs[0] + c2[1] * fs[1] + c2[2] * fs[2];
+      int64_t r = co[d] + 1;
+      if (r == A.nf[d]) r = 0;  // periodic wrap (nf == n)
+      c2[d] = r;
+      fr[d] = c2[0] * fs[0] + c2[1] * fs[1] + c2[2] * fs[2];
+    });
+    const double dt = (MODE == 0) ? 0.0 : *A.dt;
+    unroll<NV>([&](auto c) {
+      double du = 0.0;
+      unroll<NDIM>([&](auto d) {
+        const double* F = A.F[d] + (int64_t)c * A.nft[d];
+        du = du - (F[fr[d]] - F[fl[d]]) / A.dx[d];
+      });
+      const int64_t e = (int64_t)c * ncell + idx;
+      if (MODE == 0) {
+        A.out[e] = du;
+      } else if (MODE == 1) {
+        A.out[e] = A.Un[e] + dt * du;
+      } else if (MODE == 2) {
+        A.out[e] = 0.75 * A.Un[e] + 0.25 * A.Us[e] + (0.25 * dt) * du;
+      } else {
+        A.out[e] = (1.0 / 3.0) * A.Un[e] + (2.0 / 3.0) * A.Us[e] + ((2.0 / 3.0) * dt) * du;
+      }
+    });
+  }
+}
+
+// ---------------------------------------------------------- wave speeds / dt
+__global__ void init_scalars_kernel(Scalars* S) {
+  if (threadIdx.x == 0) {
+    S->amax_bits[0] = S->amax_bits[1] = S->amax_bits[2] = 0ull;
+  }
+}
+
+template <int NDIM>
+__global__ __launch_bounds__(256) void wave_speed_kernel(const double* U, int64_t ncell, double gam, Scalars* S,
+                                                         int* status) {
+  constexpr int NV = NDIM + 2;
+  double amax[NDIM];
+  unroll<NDIM>([&](auto d) { amax[d] = 0.0; });
+  bool bad = false;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ncell;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double Wc[NV];
+    unroll<NV>([&](auto c) { Wc[c] = U[c * ncell + idx]; });
+    const double rho = Wc[0];
+    double u[NDIM];
+    double q2 = 0.0;
+    unroll<NDIM>([&](auto k) {
+      u[k] = Wc[1 + k] / rho;
+      q2 = (k == 0) ? u[0] * u[0] : q2 + u[k] * u[k];
+    });
+    const double p = (gam - 1.0) * (Wc[NV - 1] - (0.5 * rho) * q2);
+    const double c = sqrt((gam * p) / rho);
+    if (!(rho > 0.0) || !(p > 0.0)) bad = true;
+    unroll<NDIM>([&](auto d) { amax[d] = dmax(amax[d], fabs(u[d]) + c); });
+  }
+  if (bad) atomicOr(status, 1);
+  __shared__ double red[NDIM][256];
+  unroll<NDIM>([&](auto d) { red[d][threadIdx.x] = amax[d]; });
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      unroll<NDIM>([&](auto d) { red[d][threadIdx.x] = dmax(red[d][threadIdx.x], red[d][threadIdx.x + s]); });
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    unroll<NDIM>([&](auto d) {
+      // non-negative doubles order like their bit patterns
+      atomicMax(&S->amax_bits[d], (unsigned long long)__double_as_longlong(red[d][0]));
+    });
+  }
+}
+
+// dt = cfl / sum_d a_d/dx_d unless *dt_dev > 0; limiter mu_d = 2 S / a_d with
+// S = sum_d (dt/dx_d) a_d.
+__global__ void finalize_dt_kernel(Scalars* S, int ndim, double dx0, double dx1, double dx2, double cfl,
+                                   double* dt_dev, double dt_fixed) {
+  if (threadIdx.x != 0) return;
+  const double dx[3] = {dx0, dx1, dx2};
+  double a[3];
+  for (int d = 0; d < 3; ++d) a[d] = __longlong_as_double((long long)S->amax_bits[d]);
+  double dt = dt_fixed;
+  if (!(dt > 0.0) && dt_dev) dt = *dt_dev;
+  if (!(dt > 0.0)) {
+    double s = a[0] / dx[0];
+    for (int d = 1; d < ndim; ++d) s = s + a[d] / dx[d];
+    dt = cfl / s;
+  }
+  if (dt_dev) *dt_dev = dt;
+  S->dt = dt;
+  double Ssum = (dt / dx[0]) * a[0];
+  for (int d = 1; d < ndim; ++d) Ssum = Ssum + (dt / dx[d]) * a[d];
+  for (int d = 0; d < 3; ++d) S->mu[d] = (d < ndim) ? (2.0 * Ssum) / a[d] : 0.0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ host launchers
+hipError_t upload_constants() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  const double DK[3] = {0.5065006634, 0.3699651429, 0.1235341937};
+  double w[8][3];
+  for (int mask = 0; mask < 8; ++mask) {
+    const double del[3] = {(mask & 1) ? 1.0 : 0.0, (mask & 2) ? 1.0 : 0.0, (mask & 4) ? 1.0 : 0.0};
+    volatile double t0 = DK[0] * del[0], t1 = DK[1] * del[1], t2 = DK[2] * del[2];
+    volatile double dsum = (t0 + t1) + t2;
+    for (int k = 0; k < 3; ++k) {
+      volatile double num = DK[k] * del[k];
+      w[mask][k] = num / dsum;
+    }
+  }
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_wfall), w, sizeof(w));
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+template <int ORDER, int NDIM, int DIR, bool LIMIT, bool FLAGS>
+static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
+  constexpr int TT = (NDIM == 1) ? 1 : (DIR == 0 ? 4 : 16);
+  constexpr int TN = (DIR == 0) ? 64 : 16;
+  constexpr int AX_A = (DIR == 0) ? 1 : 0;
+  constexpr int AX_B = (DIR == 2) ? 1 : 2;
+  dim3 grid((unsigned)((a.nf + TN - 1) / TN), (unsigned)((a.n[AX_A] + TT - 1) / TT), (unsigned)a.n[AX_B]);
+  hipLaunchKernelGGL((sweep_kernel<ORDER, NDIM, DIR, TT, TN, LIMIT, FLAGS>), grid, dim3(TT * TN), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int ORDER, int NDIM, int DIR>
+static hipError_t launch_sweep_o(const SweepArgs& a, bool limit, bool flags, hipStream_t st) {
+  if (limit) {
+    return flags ? launch_sweep_t<ORDER, NDIM, DIR, true, true>(a, st)
+                 : launch_sweep_t<ORDER, NDIM, DIR, true, false>(a, st);
+  }
+  return flags ? launch_sweep_t<ORDER, NDIM, DIR, false, true>(a, st)
+               : launch_sweep_t<ORDER, NDIM, DIR, false, false>(a, st);
+}
+
+template <int ORDER>
+static hipError_t launch_sweep_ord(int ndim, int dir, const SweepArgs& a, bool limit, bool flags, hipStream_t st) {
+  if (ndim == 1) return launch_sweep_o<ORDER, 1, 0>(a, limit, flags, st);
+  if (ndim == 2) {
+    return dir == 0 ? launch_sweep_o<ORDER, 2, 0>(a, limit, flags, st) : launch_sweep_o<ORDER, 2, 1>(a, limit, flags, st);
+  }
+  if (dir == 0) return launch_sweep_o<ORDER, 3, 0>(a, limit, flags, st);
+  if (dir == 1) return launch_sweep_o<ORDER, 3, 1>(a, limit, flags, st);
+  return launch_sweep_o<ORDER, 3, 2>(a, limit, flags, st);
+}
+
+hipError_t launch_sweep(int order, int ndim, int dir, const SweepArgs& a, bool limit, bool flags, hipStream_t st) {
+  return order == 10 ? launch_sweep_ord<10>(ndim, dir, a, limit, flags, st)
+                     : launch_sweep_ord<8>(ndim, dir, a, limit, flags, st);
+}
+
+template <int NDIM>
+static hipError_t launch_update_n(int mode, const UpdateArgs& a, hipStream_t st) {
+  const int64_t ncell = a.n[0] * a.n[1] * a.n[2];
+  int64_t blocks = (ncell + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  dim3 g((unsigned)blocks);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL((update_kernel<NDIM, 0>), g, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((update_kernel<NDIM, 1>), g, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((update_kernel<NDIM, 2>), g, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((update_kernel<NDIM, 3>), g, dim3(256), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_update(int ndim, int mode, const UpdateArgs& a, hipStream_t st) {
+  if (ndim == 1) return launch_update_n<1>(mode, a, st);
+  if (ndim == 2) return launch_update_n<2>(mode, a, st);
+  return launch_update_n<3>(mode, a, st);
+}
+
+hipError_t launch_wave_speeds(int ndim, const double* U, int64_t ncell, double gam, Scalars* S, int* status,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, st, S);
+  int64_t blocks = (ncell + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (ndim == 1) hipLaunchKernelGGL(wave_speed_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, U, ncell, gam, S, status);
+  if (ndim == 2) hipLaunchKernelGGL(wave_speed_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, st, U, ncell, gam, S, status);
+  if (ndim == 3) hipLaunchKernelGGL(wave_speed_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, st, U, ncell, gam, S, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_dt(Scalars* S, int ndim, const double* dx, double cfl, double* dt_dev, double dt_fixed,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(64), 0, st, S, ndim, dx[0], dx[1], dx[2], cfl, dt_dev,
+                     dt_fixed);
+  return hipGetLastError();
+}
+
+}  // namespace tenoaa

@@ -1,0 +1,182 @@
+"""Python binding of libtenoaa (include/tenoaa.h): argument marshalling only.
+
+Tensors are torch float64 tensors on the current HIP device in the library
+layout (nvar, nz, ny, nx); the work is enqueued on torch's current stream.
+Every step of the computation runs in the HIP library; if the library is not
+built this module raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtenoaa.so")
+
+BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP = 0, 1, 2, 3
+LLF, RUSANOV = 0, 1
+WS_RHS, WS_STEP = 0, 1
+ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENONPHYSICAL", -5: "EWORKSPACE"}
+
+EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_get_status", "tenoaa_last_hip_error"]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("pad", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+                ("dx", ctypes.c_double * 3), ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3)]
+
+
+class Scheme(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("splitting", ctypes.c_int32), ("positivity", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class TenoaaError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """ctypes handle of libtenoaa.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TenoaaError("libtenoaa.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        gp, sp = ctypes.POINTER(Grid), ctypes.POINTER(Scheme)
+        vp = ctypes.c_void_p
+        L.tenoaa_workspace_bytes.restype = ctypes.c_size_t
+        L.tenoaa_workspace_bytes.argtypes = [gp, sp, ctypes.c_int32]
+        L.tenoaa_rhs.restype = ctypes.c_int
+        L.tenoaa_rhs.argtypes = [gp, sp, ctypes.c_double, vp, vp, ctypes.c_double, vp, vp, ctypes.c_size_t, vp]
+        L.tenoaa_step.restype = ctypes.c_int
+        L.tenoaa_step.argtypes = [gp, sp, ctypes.c_double, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tenoaa_get_status.restype = ctypes.c_int
+        L.tenoaa_get_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
+        L.tenoaa_last_hip_error.restype = ctypes.c_int
+        L.tenoaa_last_hip_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def make_grid(shape, dx=None, bc_lo=None, bc_hi=None):
+    """shape = (nx,), (nx, ny) or (nx, ny, nz) in axis order; bc per axis (default periodic)."""
+    nd = len(shape)
+    g = Grid()
+    g.ndim = nd
+    dx = dx if dx is not None else [1.0 / n for n in shape]
+    bc_lo = bc_lo if bc_lo is not None else [BC_PERIODIC] * nd
+    bc_hi = bc_hi if bc_hi is not None else bc_lo
+    for d in range(3):
+        g.n[d] = shape[d] if d < nd else 1
+        g.dx[d] = dx[d] if d < nd else 1.0
+        g.bc_lo[d] = bc_lo[d] if d < nd else 0
+        g.bc_hi[d] = bc_hi[d] if d < nd else 0
+    return g
+
+
+def make_scheme(order=10, splitting=LLF, positivity=0):
+    s = Scheme()
+    s.order, s.splitting, s.positivity = order, splitting, positivity
+    return s
+
+
+def flags_size(grid):
+    nd = grid.ndim
+    tot = 0
+    for d in range(nd):
+        nf = grid.n[d] if grid.bc_lo[d] == BC_PERIODIC else grid.n[d] + 1
+        t = nf
+        for k in range(3):
+            if k != d:
+                t *= grid.n[k]
+        tot += (nd + 2) * 2 * t
+    return tot
+
+
+def _check(rc, what):
+    if rc != 0:
+        hip = load().tenoaa_last_hip_error()
+        raise TenoaaError("%s failed: %s (hip error %d)" % (what, ERRORS.get(rc, rc), hip))
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def workspace_bytes(grid, scheme, which):
+    b = load().tenoaa_workspace_bytes(ctypes.byref(grid), ctypes.byref(scheme), which)
+    if b == 0:
+        raise TenoaaError("invalid grid/scheme")
+    return int(b)
+
+
+def workspace(grid, scheme, which, device="cuda"):
+    """A zero-filled device workspace (the status word starts cleared)."""
+    import torch
+    return torch.zeros(workspace_bytes(grid, scheme, which), dtype=torch.uint8, device=device)
+
+
+def _check_state(U, grid):
+    import torch
+    if U.dtype != torch.float64 or not U.is_cuda or not U.is_contiguous():
+        raise TenoaaError("state must be a contiguous float64 device tensor")
+    want = (grid.ndim + 2, grid.n[2], grid.n[1], grid.n[0])
+    if tuple(U.shape) != want:
+        raise TenoaaError("state shape %s, grid wants %s" % (tuple(U.shape), want))
+
+
+def rhs(grid, scheme, U, gamma=1.4, dt_limiter=0.0, flags=None, out=None, ws=None):
+    """dU/dt of U (device tensors); flags: optional uint8 device tensor of flags_size(grid)."""
+    import torch
+    _check_state(U, grid)
+    if out is None:
+        out = torch.empty_like(U)
+    if ws is None:
+        ws = workspace(grid, scheme, WS_RHS, U.device)
+    if flags is not None and (flags.dtype != torch.uint8 or flags.numel() < flags_size(grid)):
+        raise TenoaaError("flags must be uint8 with flags_size(grid) elements")
+    rc = load().tenoaa_rhs(ctypes.byref(grid), ctypes.byref(scheme), gamma, _ptr(U), _ptr(out), dt_limiter,
+                           _ptr(flags), _ptr(ws), ws.numel(), _stream())
+    _check(rc, "tenoaa_rhs")
+    return out
+
+
+def step(grid, scheme, U, dt_dev, gamma=1.4, cfl=0.4, ws=None):
+    """One SSP-RK3 step of U in place; dt_dev is a 1-element float64 device tensor."""
+    _check_state(U, grid)
+    if ws is None:
+        ws = workspace(grid, scheme, WS_STEP, U.device)
+    rc = load().tenoaa_step(ctypes.byref(grid), ctypes.byref(scheme), gamma, cfl, _ptr(U), _ptr(dt_dev),
+                            _ptr(ws), ws.numel(), _stream())
+    _check(rc, "tenoaa_step")
+    return U
+
+
+def get_status(ws):
+    """Synchronises the current stream; 0 if every state read was physical."""
+    out = ctypes.c_int32(0)
+    rc = load().tenoaa_get_status(_ptr(ws), _stream(), ctypes.byref(out))
+    if rc not in (0, -4):
+        _check(rc, "tenoaa_get_status")
+    return int(out.value)
+
+
+def grid_for(U, bc=None, dx=None):
+    """Grid of a layout array/tensor (nvar, nz, ny, nx)."""
+    nv, nz, ny, nx = tuple(U.shape)
+    nd = nv - 2
+    shape = (nx, ny, nz)[:nd]
+    bcs = [bc if bc is not None else BC_PERIODIC] * nd if not isinstance(bc, (list, tuple)) else list(bc)
+    return make_grid(shape, dx, bcs)
+
+
+def to_numpy(t):
+    return np.ascontiguousarray(t.detach().cpu().numpy())
