@@ -1,0 +1,146 @@
+"""Throughput of the TENO10-AA Euler step on one MI355X.
+
+Workload: 3D Euler on a 256^3 periodic grid (gamma = 1.4), Gaussian-random-field
+state with a high-pressure blast sphere and a near-vacuum cavity, TENO10-AA
+with LLF splitting and the positivity limiter, one SSP-RK3 step at CFL 0.4
+per timed step (dt recomputed on the device every step).  Input is resident in
+HBM before timing starts.
+
+Prints one JSON line.  `value` is face reconstructions per second
+(one face of one sweep direction, all five characteristic fields, both split
+sides): 3 stages x 3 directions x 256^3 per step.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gface-recon/s (RHS) FP64 3D 256^3 TENO-AA10 fwd & fwd+adj; % of FP64/HBM roofline"
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+PEAK_HBM_GBS = 8000.0
+
+
+def cpu_baseline(n=64):
+    """The oracle, single-threaded, on one step of the same recipe at n^3."""
+    import numpy as np  # noqa: F401
+    import oracle
+    from paper_2109_14340_amd import inputs
+
+    oracle.lib()
+    U = inputs.blast_cavity_3d(n)
+    g = oracle.make_grid((n, n, n), [1.0 / n] * 3, [0, 0, 0])
+    t = time.perf_counter()
+    oracle.step(g, U, order=10, splitting=0, positivity=1, gamma=1.4, cfl=0.4)
+    el = time.perf_counter() - t
+    work = 9 * n ** 3
+    return {"value": work / el / 1e9, "unit": "Gface-recon/s", "cores": 1, "kind": "oracle",
+            "sample": "one SSP-RK3 step (TENO10-AA, LLF, limiter, CFL 0.4) of the same recipe on a "
+                      "%d^3 periodic grid: %d face reconstructions in %.2f s" % (n, work, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2109_14340_amd import flops, inputs, tenoaa
+
+    n = args.n
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    grid = tenoaa.make_grid((n, n, n))
+    sch = tenoaa.make_scheme(10, tenoaa.LLF, 1)
+    U = torch.from_numpy(inputs.grf_3d(n)).to(dev)
+    ws = tenoaa.workspace(grid, sch, tenoaa.WS_STEP, dev)
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def one_step():
+        dt.zero_()
+        tenoaa.step(grid, sch, U, dt, gamma=1.4, cfl=0.4, ws=ws)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    if tenoaa.get_status(ws) != 0:
+        raise RuntimeError("non-physical state during the benchmark")
+    ms = el / args.steps * 1e3
+    work = 9 * n ** 3
+    value = work / (ms * 1e-3) / 1e9
+
+    # per-kernel durations (HIP events on the library's stream) over a few steps
+    tenoaa.timing_enable(True)
+    ksteps = 3
+    for _ in range(ksteps):
+        one_step()
+    per = {}
+    for k, name in enumerate(["sweep_x", "sweep_y", "sweep_z", "update", "wave_speeds"]):
+        cnt, tot = tenoaa.timing_read(k)
+        per[name] = (cnt, tot)
+    tenoaa.timing_enable(False)
+    dom = max(["sweep_x", "sweep_y", "sweep_z"], key=lambda k: per[k][1])
+    dom_dir = ["sweep_x", "sweep_y", "sweep_z"].index(dom)
+    avg_ms = per[dom][1] / per[dom][0]
+
+    # algorithmic flops of that sweep: path counts from the decision flags of
+    # one right-hand side of the current state
+    fl = torch.zeros(tenoaa.flags_size(grid), dtype=torch.uint8, device=dev)
+    tenoaa.rhs(grid, sch, U, gamma=1.4, dt_limiter=float(dt.item()), flags=fl)
+    nft = n ** 3
+    seg = fl[dom_dir * 10 * nft:(dom_dir + 1) * 10 * nft]
+    hist = torch.bincount((seg & 3).to(torch.int64), minlength=4).cpu().tolist()
+    sel_counts = {5: hist[3], 4: hist[2], 3: hist[1], 0: hist[0]}
+    fl_total = flops.sweep_flops(3, 10, sel_counts, nft, 0, True)
+    achieved = fl_total / (avg_ms * 1e-3) / 1e12
+    del fl, seg
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "Gface-recon/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D Euler %d^3 periodic, GRF + blast sphere + cavity, TENO10-AA, LLF, "
+                               "positivity limiter, one SSP-RK3 step at CFL 0.4" % n,
+                   "grid": [n, n, n], "order": 10, "splitting": "LLF", "limiter": True,
+                   "face_recons_per_step": work},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "kernel": dom, "kernel_avg_ms": round(avg_ms, 4),
+                     "algorithmic_flops_per_launch": fl_total,
+                     "path_counts": {"S5": hist[3], "S4": hist[2], "S3": hist[1], "fallback": hist[0]},
+                     "per_kernel_avg_ms": {k: round(v[1] / max(v[0], 1), 4) for k, v in per.items()}},
+        "fwd_adj": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

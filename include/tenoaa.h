@@ -122,6 +122,28 @@ int tenoaa_get_status(void* ws, void* stream, int32_t* out);
 /* hipError_t of the last failed HIP call in this thread (0 if none). */
 int tenoaa_last_hip_error(void);
 
+/* Kernel classes for per-kernel timing. */
+enum {
+  TENOAA_KCLASS_SWEEP_X = 0,
+  TENOAA_KCLASS_SWEEP_Y = 1,
+  TENOAA_KCLASS_SWEEP_Z = 2,
+  TENOAA_KCLASS_UPDATE = 3,
+  TENOAA_KCLASS_WAVESPEED = 4,
+  TENOAA_KCLASS_COUNT = 5
+};
+
+/* Measurement aid (host state shared by all threads, guarded by a mutex).
+ * While enabled (on != 0), every kernel launch of the library is bracketed by
+ * HIP events recorded on the launch's own stream; this adds two event records
+ * per launch and should stay off outside measurements. */
+int tenoaa_timing_enable(int32_t on);
+
+/* Waits for every bracketed launch so far, then returns for one kernel class
+ * the number of launches and their summed duration in milliseconds since the
+ * previous read of that class, and resets that class.  TENOAA_EINVAL for a
+ * bad class or null pointers. */
+int tenoaa_timing_read(int32_t kclass, int64_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

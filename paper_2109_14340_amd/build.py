@@ -19,14 +19,16 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
-    cmd = ["hipcc"] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES] + ["-o", LIB + ".tmp"]
+def build(verbose=False, out=None, defines=()):
+    """Compile the library; `out`/`defines` build a variant elsewhere (tuning)."""
+    target = out or LIB
+    cmd = ["hipcc"] + FLAGS + ["-D%s" % d for d in defines] + ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    cmd += [os.path.join(CSRC, s) for s in SOURCES] + ["-o", target + ".tmp"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(target + ".tmp", target)
+    return target
 
 
 def sources():

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "tenoaa.h"
 #include "tenoaa_internal.h"
@@ -19,6 +21,58 @@ int hip_fail(hipError_t e) {
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// ---- optional per-kernel timing (measurement aid)
+struct TimedLaunch {
+  int cls;
+  hipEvent_t a, b;
+};
+std::mutex g_timing_mu;
+bool g_timing_on = false;
+std::vector<TimedLaunch> g_timed;
+int64_t g_launches[TENOAA_KCLASS_COUNT];
+double g_total_ms[TENOAA_KCLASS_COUNT];
+
+// Brackets one launch with events on `st` when timing is enabled.
+template <class F>
+hipError_t timed(int cls, hipStream_t st, F&& launch) {
+  bool on;
+  {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    on = g_timing_on;
+  }
+  if (!on) return launch();
+  TimedLaunch t{cls, nullptr, nullptr};
+  hipError_t e = hipEventCreate(&t.a);
+  if (e == hipSuccess) e = hipEventCreate(&t.b);
+  if (e == hipSuccess) e = hipEventRecord(t.a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(t.b, st);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  g_timed.push_back(t);
+  return hipSuccess;
+}
+
+// Folds completed timed launches into the per-class totals (waits for them).
+hipError_t collect_timing() {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  for (const TimedLaunch& t : g_timed) {
+    hipError_t e = hipEventSynchronize(t.b);
+    if (e != hipSuccess) return e;
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, t.a, t.b);
+    if (e != hipSuccess) return e;
+    g_launches[t.cls] += 1;
+    g_total_ms[t.cls] += ms;
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  g_timed.clear();
+  return hipSuccess;
+}
 
 bool valid_grid(const tenoaa_grid* g, const tenoaa_scheme* s) {
   if (!g || !s) return false;
@@ -106,7 +160,8 @@ int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags) {
     a.gamma = c.gamma;
     a.mu = c.S->mu;
     a.status = &c.S->status;
-    hipError_t e = tenoaa::launch_sweep(c.s->order, g->ndim, d, a, limit, flags != nullptr, c.st);
+    hipError_t e = timed(TENOAA_KCLASS_SWEEP_X + d, c.st,
+                         [&] { return tenoaa::launch_sweep(c.s->order, g->ndim, d, a, limit, c.st); });
     if (e != hipSuccess) return hip_fail(e);
     flag_off += (int64_t)nv * 2 * a.nft;
   }
@@ -128,7 +183,7 @@ int update(const Ctx& c, int mode, const double* Un, const double* Us, double* o
   a.Us = Us;
   a.out = out;
   a.dt = &c.S->dt;
-  hipError_t e = tenoaa::launch_update(g->ndim, mode, a, c.st);
+  hipError_t e = timed(TENOAA_KCLASS_UPDATE, c.st, [&] { return tenoaa::launch_update(g->ndim, mode, a, c.st); });
   return e == hipSuccess ? TENOAA_OK : hip_fail(e);
 }
 
@@ -173,8 +228,11 @@ int tenoaa_rhs(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamm
   const bool limit = scheme->positivity && dt_limiter > 0.0;
   const int64_t ncell = grid->n[0] * grid->n[1] * grid->n[2];
   if (limit) {
-    hipError_t e = tenoaa::launch_wave_speeds(grid->ndim, U, ncell, gamma, c.S, &c.S->status, c.st);
-    if (e == hipSuccess) e = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, 1.0, nullptr, dt_limiter, c.st);
+    hipError_t e = timed(TENOAA_KCLASS_WAVESPEED, c.st, [&] {
+      hipError_t r = tenoaa::launch_wave_speeds(grid->ndim, U, ncell, gamma, c.S, &c.S->status, c.st);
+      if (r == hipSuccess) r = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, 1.0, nullptr, dt_limiter, c.st);
+      return r;
+    });
     if (e != hipSuccess) return hip_fail(e);
   }
   rc = sweeps(c, U, limit, flags);
@@ -194,8 +252,11 @@ int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gam
   const int64_t ncell = grid->n[0] * grid->n[1] * grid->n[2];
   double* Us = reinterpret_cast<double*>(c.ws + c.L.stage);
   const bool limit = scheme->positivity != 0;
-  hipError_t e = tenoaa::launch_wave_speeds(grid->ndim, U, ncell, gamma, c.S, &c.S->status, c.st);
-  if (e == hipSuccess) e = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, cfl, dt_dev, 0.0, c.st);
+  hipError_t e = timed(TENOAA_KCLASS_WAVESPEED, c.st, [&] {
+    hipError_t r = tenoaa::launch_wave_speeds(grid->ndim, U, ncell, gamma, c.S, &c.S->status, c.st);
+    if (r == hipSuccess) r = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, cfl, dt_dev, 0.0, c.st);
+    return r;
+  });
   if (e != hipSuccess) return hip_fail(e);
   // stage 1: U1 = Un + dt L(Un)            -> Us
   if ((rc = sweeps(c, U, limit, nullptr))) return rc;
@@ -225,5 +286,25 @@ int tenoaa_get_status(void* ws, void* stream, int32_t* out) {
 }
 
 int tenoaa_last_hip_error(void) { return g_last_hip_error; }
+
+int tenoaa_timing_enable(int32_t on) {
+  {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timing_on = on != 0;
+  }
+  return TENOAA_OK;
+}
+
+int tenoaa_timing_read(int32_t kclass, int64_t* launches, double* total_ms) {
+  if (kclass < 0 || kclass >= TENOAA_KCLASS_COUNT || !launches || !total_ms) return TENOAA_EINVAL;
+  hipError_t e = collect_timing();
+  if (e != hipSuccess) return hip_fail(e);
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  *launches = g_launches[kclass];
+  *total_ms = g_total_ms[kclass];
+  g_launches[kclass] = 0;
+  g_total_ms[kclass] = 0.0;
+  return TENOAA_OK;
+}
 
 }  // extern "C"

@@ -45,7 +45,7 @@ struct UpdateArgs {
 };
 
 hipError_t upload_constants();
-hipError_t launch_sweep(int order, int ndim, int dir, const SweepArgs& a, bool limit, bool flags, hipStream_t st);
+hipError_t launch_sweep(int order, int ndim, int dir, const SweepArgs& a, bool limit, hipStream_t st);
 hipError_t launch_update(int ndim, int mode, const UpdateArgs& a, hipStream_t st);
 hipError_t launch_wave_speeds(int ndim, const double* U, int64_t ncell, double gam, Scalars* S, int* status,
                               hipStream_t st);

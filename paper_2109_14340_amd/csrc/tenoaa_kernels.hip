@@ -27,6 +27,26 @@
 #include "tenoaa_internal.h"
 #include "tenoaa_sos.h"
 
+// Launch-shape tunables (overridable at build time).
+#ifndef TENOAA_WAVES_PER_EU
+#define TENOAA_WAVES_PER_EU 0
+#endif
+#ifndef TENOAA_TN_X
+#define TENOAA_TN_X 64
+#endif
+#ifndef TENOAA_TT_X
+#define TENOAA_TT_X 4
+#endif
+#ifndef TENOAA_TN_YZ
+#define TENOAA_TN_YZ 16
+#endif
+#ifndef TENOAA_TT_YZ
+#define TENOAA_TT_YZ 16
+#endif
+#ifndef TENOAA_CELL_BARRIER
+#define TENOAA_CELL_BARRIER 0
+#endif
+
 namespace tenoaa {
 namespace {
 
@@ -65,31 +85,96 @@ __device__ __forceinline__ void unroll(F&& f) {
 
 __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
 
-// Reciprocal for decision-only quantities: hardware estimate + two Newton steps.
-__device__ __forceinline__ double rcp_dec(double x) { return 1.0 / x; }
+// Reciprocal for decision-only quantities: the hardware estimate refined by
+// one Newton step (relative error below 3e-15 for finite non-zero x).
+__device__ __forceinline__ double rcp_dec(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// gamma = 1/(beta + eps)^7 (Sec. 3.2, q = 7), decision-only.
+__device__ __forceinline__ double gamma7(double beta) {
+  const double r = rcp_dec(beta + EPS);
+  const double r2 = r * r;
+  const double r4 = r2 * r2;
+  return (r4 * r2) * r;
+}
+
+// Smoothness indicator of a large stencil of width R whose leftmost value is
+// v[P]: the exact sum of squares in the forward-difference basis.
+template <int R, int P, int W>
+__device__ __forceinline__ double sos_beta(const double (&v)[W]) {
+  static_assert(R == 6 || R == 8 || R == 10, "large stencils only");
+  double lev[R];
+  unroll<R>([&](auto q) { lev[q] = v[P + q]; });
+  double dif[R - 1];  // Delta^{m+1} f_P
+  unroll<R - 1>([&](auto mm) {
+    constexpr int m = decltype(mm)::value;
+    unroll<R - 1 - m>([&](auto q) { lev[q] = lev[q + 1] - lev[q]; });
+    dif[m] = lev[0];
+  });
+  double beta = 0.0;
+  unroll<R - 1>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    double y = 0.0;
+    unroll<R - 1>([&](auto mm) {
+      constexpr int m = decltype(mm)::value;
+      if constexpr (m >= k) {
+        constexpr double l = (R == 10) ? SOS_S5_L[m][k] : (R == 8) ? SOS_S4_L[m][k] : SOS_S3_L[m][k];
+        if constexpr (l != 0.0) y = fma(l, dif[m], y);
+      }
+    });
+    constexpr double dk = (R == 10) ? SOS_S5_D[k] : (R == 8) ? SOS_S4_D[k] : SOS_S3_D[k];
+    beta = fma(dk, y * y, beta);
+  });
+  return beta;
+}
+
+template <int R>
+__device__ __host__ constexpr double lin_coef(int q) {
+  return (R == 10) ? LIN10[q] : (R == 8) ? LIN8[q] : LIN6[q];
+}
+
+// Linear scheme of width R on the values starting at v[P] (Sec. 4.1).
+template <int R, int P, int W>
+__device__ __forceinline__ double linear_flux(const double (&v)[W]) {
+  constexpr double c0 = lin_coef<R>(0);
+  double acc = c0 * v[P];
+  unroll<R - 1>([&](auto qq) {
+    constexpr int q = decltype(qq)::value;
+    constexpr double c = lin_coef<R>(q + 1);
+    acc = fma(c, v[P + q + 1], acc);
+  });
+  return acc;
+}
 
 // ------------------------------------------------- scalar TENO-AA (Sec. 3-4)
-// v[0..W-1] = f_{i-G+1..i+G}.  Returns fhat_{i+1/2}; *flag gets the decision
+// v[0..W-1] = f_{i-G+1..i+G}.  Returns fhat_{i+1/2}; flag gets the decision
 // byte (bits 0-1 large stencil, 2-4 deltas, 5-7 K-7).
 template <int ORDER>
 __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& flag) {
   constexpr int G = ORDER / 2;
   constexpr int I = G - 1;  // index of f_i
 
-  // forward difference table along the window: d1[q] = f_{q+1} - f_q, ...
-  double d1[ORDER - 1];
-  unroll<ORDER - 1>([&](auto q) { d1[q] = v[q + 1] - v[q]; });
-
-  // Sec. 3.4: eta_j, j = -1..2 (a = f_{j+1} - f_j, b = f_j - f_{j-1}).
-  double etabar = 0.0;
+  // Sec. 3.4: eta_j = (|2 a b| + eps) / (a^2 + b^2 + eps), j = -1..2, with
+  // a = f_{j+1} - f_j, b = f_j - f_{j-1}; the minimum is located by cross
+  // multiplication and divided out once.
+  double dd[5];  // f_{k+1} - f_k for k = -2..2
+  unroll<5>([&](auto q) { dd[q] = v[I - 2 + q + 1] - v[I - 2 + q]; });
+  double nb = 0.0, db = 1.0;
   unroll<4>([&](auto jj) {
-    const int j = jj - 1;
-    const double a = d1[I + j];
-    const double b = d1[I + j - 1];
-    const double eta = (fabs((2.0 * a) * b) + EPS) / ((a * a + b * b) + EPS);
-    if (jj == 0 || eta < etabar) etabar = eta;
+    const double a = dd[jj + 1];
+    const double b = dd[jj];
+    const double num = fabs((2.0 * a) * b) + EPS;
+    const double den = (a * a + b * b) + EPS;
+    if (jj == 0 || num * db < nb * den) {
+      nb = num;
+      db = den;
+    }
   });
-  double ratio = etabar / C_R;
+  const double etabar = nb / db;
+  double ratio = etabar * (1.0 / C_R);
   if (ratio > 1.0) ratio = 1.0;
   const double m = 1.0 - ratio;
   const double om = 1.0 - m;
@@ -99,96 +184,49 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   int K = (int)floor(B);
   K = K < 7 ? 7 : (K > 14 ? 14 : K);
   const double CT = c_ct[K - 7];
-
-  // small stencils (Sec. 4.2, printed WENO-JS indicators) in difference form
-  const double b0a = d1[I - 1] + d1[I];          // f_{i+1} - f_{i-1}
-  const double b0b = d1[I] - d1[I - 1];          // second difference at i
-  const double b1a = (d1[I + 1] - d1[I]) - 2.0 * d1[I];  // 3f_i - 4f_{i+1} + f_{i+2}, negated
-  const double b1b = d1[I + 1] - d1[I];
-  const double b2a = (d1[I - 1] - d1[I - 2]) + 2.0 * d1[I - 1];  // f_{i-2} - 4f_{i-1} + 3f_i
-  const double b2b = d1[I - 1] - d1[I - 2];
-  constexpr double C13 = 13.0 / 12.0;
-  const double beta0 = fma(C13, b0b * b0b, 0.25 * (b0a * b0a));
-  const double beta1 = fma(C13, b1b * b1b, 0.25 * (b1a * b1a));
-  const double beta2 = fma(C13, b2b * b2b, 0.25 * (b2a * b2a));
-  auto gam7 = [](double beta) {
-    const double r = rcp_dec(beta + EPS);
-    const double r2 = r * r;
-    const double r4 = r2 * r2;
-    return (r4 * r2) * r;
-  };
-  const double g0 = gam7(beta0), g1 = gam7(beta1), g2 = gam7(beta2);
-  const double S = (g0 + g1) + g2;
   const uint8_t kbits = (uint8_t)((K - 7) << 5);
 
-  // large stencils, largest first (Sec. 3.3)
-  // full difference table of the window, needed for the sums of squares
-  double tab[ORDER - 1][ORDER - 1];
-  unroll<ORDER - 1>([&](auto q) { tab[0][q] = d1[q]; });
-  unroll<ORDER - 2>([&](auto mm) {
-    constexpr int m1 = decltype(mm)::value + 1;
-    unroll<ORDER - 1 - m1>([&](auto q) { tab[m1][q] = tab[m1 - 1][q + 1] - tab[m1 - 1][q]; });
-  });
+  // small stencils (Sec. 4.2, printed WENO-JS indicators) in difference form
+  const double b0a = dd[1] + dd[2];                // f_{i+1} - f_{i-1}
+  const double b0b = dd[2] - dd[1];                // f_{i-1} - 2 f_i + f_{i+1}
+  const double b1a = (dd[3] - dd[2]) - 2.0 * dd[2];  // f_{i+2} - 4 f_{i+1} + 3 f_i
+  const double b1b = dd[3] - dd[2];
+  const double b2a = (dd[1] - dd[0]) + 2.0 * dd[1];  // f_{i-2} - 4 f_{i-1} + 3 f_i
+  const double b2b = dd[1] - dd[0];
+  constexpr double C13 = 13.0 / 12.0;
+  const double g0 = gamma7(fma(C13, b0b * b0b, 0.25 * (b0a * b0a)));
+  const double g1 = gamma7(fma(C13, b1b * b1b, 0.25 * (b1a * b1a)));
+  const double g2 = gamma7(fma(C13, b2b * b2b, 0.25 * (b2a * b2a)));
+  const double S = (g0 + g1) + g2;
 
-  auto accept = [&](double beta) {
-    const double gp = gam7(beta);
-    return gp >= CT * (S + gp);
-  };
+  // Sec. 3.3: the groups (S0,S1,S2,Sp), largest p first; Sp is taken when
+  // chi_p = gamma_p / (S + gamma_p) >= C_T.
   if constexpr (ORDER == 10) {
-    // S5 = cells i-4..i+5 = whole window, differences from position 0
-    double beta = 0.0;
-    unroll<9>([&](auto k) {
-      double y = 0.0;
-      unroll<9>([&](auto m) {
-        if (m >= k && SOS_S5_L[m][k] != 0.0) y = fma(SOS_S5_L[m][k], tab[m][0], y);
-      });
-      beta = fma(SOS_S5_D[k], y * y, beta);
-    });
-    if (accept(beta)) {
+    const double gp = gamma7(sos_beta<10, 0>(v));
+    if (gp >= CT * (S + gp)) {
       flag = (uint8_t)(3 | kbits);
-      double acc = LIN10[0] * v[0];
-      unroll<9>([&](auto q) { acc = fma(LIN10[q + 1], v[q + 1], acc); });
-      return acc;
+      return linear_flux<10, 0>(v);
     }
   }
   {
-    // S4 = cells i-3..i+4
     constexpr int P = (ORDER == 10) ? 1 : 0;
-    double beta = 0.0;
-    unroll<7>([&](auto k) {
-      double y = 0.0;
-      unroll<7>([&](auto m) {
-        if (m >= k && SOS_S4_L[m][k] != 0.0) y = fma(SOS_S4_L[m][k], tab[m][P], y);
-      });
-      beta = fma(SOS_S4_D[k], y * y, beta);
-    });
-    if (accept(beta)) {
+    const double gp = gamma7(sos_beta<8, P>(v));
+    if (gp >= CT * (S + gp)) {
       flag = (uint8_t)(2 | kbits);
-      double acc = LIN8[0] * v[P];
-      unroll<7>([&](auto q) { acc = fma(LIN8[q + 1], v[P + q + 1], acc); });
-      return acc;
+      return linear_flux<8, P>(v);
     }
   }
   {
-    // S3 = cells i-2..i+3
     constexpr int P = (ORDER == 10) ? 2 : 1;
-    double beta = 0.0;
-    unroll<5>([&](auto k) {
-      double y = 0.0;
-      unroll<5>([&](auto m) {
-        if (m >= k && SOS_S3_L[m][k] != 0.0) y = fma(SOS_S3_L[m][k], tab[m][P], y);
-      });
-      beta = fma(SOS_S3_D[k], y * y, beta);
-    });
-    if (accept(beta)) {
+    const double gp = gamma7(sos_beta<6, P>(v));
+    if (gp >= CT * (S + gp)) {
       flag = (uint8_t)(1 | kbits);
-      double acc = LIN6[0] * v[P];
-      unroll<5>([&](auto q) { acc = fma(LIN6[q + 1], v[P + q + 1], acc); });
-      return acc;
+      return linear_flux<6, P>(v);
     }
   }
   // fallback: TENO5 cut-off among the small stencils (Sec. 3.3)
-  const int dm = (g0 >= CT * S ? 1 : 0) | (g1 >= CT * S ? 2 : 0) | (g2 >= CT * S ? 4 : 0);
+  const double cs = CT * S;
+  const int dm = (g0 >= cs ? 1 : 0) | (g1 >= cs ? 2 : 0) | (g2 >= cs ? 4 : 0);
   flag = (uint8_t)((dm << 2) | kbits);
   const double fm1 = v[I - 1], f0 = v[I], f1 = v[I + 1];
   const double h0 = ((-fm1 + 5.0 * f0) + 2.0 * f1) / 6.0;
@@ -211,20 +249,25 @@ struct Frame {
   }
 };
 
-template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT, bool FLAGS>
-__global__ __launch_bounds__(TT* TN) void sweep_kernel(SweepArgs A) {
+template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT>
+__global__ __launch_bounds__(TT* TN)
+#if TENOAA_WAVES_PER_EU > 0
+__attribute__((amdgpu_waves_per_eu(TENOAA_WAVES_PER_EU)))
+#endif
+void sweep_kernel(SweepArgs A) {
   constexpr int G = ORDER / 2;
   constexpr int W = ORDER;
   constexpr int NV = NDIM + 2;
   constexpr int NT = (NDIM > 1) ? NDIM - 1 : 1;
   constexpr int NC = TN + W - 1;  // cells along the normal in the tile
   constexpr int NCT = TT * NC;
-  constexpr int AX_A = (DIR == 0) ? 1 : 0;  // transverse axis mapped to threadIdx (x unless DIR == 0)
+  constexpr int AX_A = (DIR == 0) ? 1 : 0;  // transverse axis spread over threads
   constexpr int AX_B = (DIR == 2) ? 1 : 2;  // remaining axis (blockIdx.z)
   using Fr = Frame<NDIM, DIR>;
 
-  __shared__ double sW[NV][NCT];
-  __shared__ double sF[NV][NCT];
+  // per-cell records: (conserved, flux) pairs in the local frame, then
+  // normal velocity, sound speed, sqrt(rho), enthalpy, tangential velocities
+  __shared__ double2 sWF[NV][NCT];
   __shared__ double sUn[NCT], sC[NCT], sSr[NCT], sH[NCT];
   __shared__ double sUt[NT][NCT];
 
@@ -291,17 +334,14 @@ __global__ __launch_bounds__(TT* TN) void sweep_kernel(SweepArgs A) {
     const double sr = sqrt(rho);
     const double un = u[DIR];
     if (!(rho > 0.0) || !(p > 0.0)) atomicOr(A.status, 1);
-    // physical flux along DIR, written in the local frame
-    sW[0][ct] = rho;
-    sF[0][ct] = Wc[1 + DIR];
+    // conserved state and physical flux along DIR in the local frame
+    sWF[0][ct] = make_double2(rho, Wc[1 + DIR]);
     unroll<NDIM>([&](auto k) {
-      const int slot = Fr::slot_of_axis(k);
-      sW[1 + slot][ct] = Wc[1 + k];
-      sF[1 + slot][ct] = (k == DIR) ? Wc[1 + k] * un + p : Wc[1 + k] * un;
-      if (slot > 0) sUt[slot - 1][ct] = u[k];
+      constexpr int slot = Fr::slot_of_axis(decltype(k)::value);
+      sWF[1 + slot][ct] = make_double2(Wc[1 + k], (k == DIR) ? Wc[1 + k] * un + p : Wc[1 + k] * un);
+      if constexpr (slot > 0) sUt[slot - 1][ct] = u[k];
     });
-    sW[NV - 1][ct] = E;
-    sF[NV - 1][ct] = (E + p) * un;
+    sWF[NV - 1][ct] = make_double2(E, (E + p) * un);
     sUn[ct] = un;
     sC[ct] = c;
     sSr[ct] = sr;
@@ -321,8 +361,10 @@ __global__ __launch_bounds__(TT* TN) void sweep_kernel(SweepArgs A) {
   const int64_t f = f0 + fn;
   const int64_t t = t0 + tt;
   if (f >= A.nf || t >= nA) return;
-  auto lidx = [&](int j) { return (DIR == 0) ? tt * NC + fn + j : (fn + j) * TT + tt; };
-  const int ia = lidx(G - 1), ib = lidx(G);
+  // LDS index of window cell j (cells f-G .. f+G-1)
+  const int lbase = (DIR == 0) ? tt * NC + fn : fn * TT + tt;
+  constexpr int LSTEP = (DIR == 0) ? 1 : TT;
+  const int ia = lbase + (G - 1) * LSTEP, ib = lbase + G * LSTEP;
 
   // Roe average (Sec. 5: characteristic decomposition at the face)
   const double sa = sSr[ia], sb = sSr[ib];
@@ -330,11 +372,12 @@ __global__ __launch_bounds__(TT* TN) void sweep_kernel(SweepArgs A) {
   const double un = (sa * sUn[ia] + sb * sUn[ib]) / den;
   double ut[NT];
   unroll<NDIM - 1>([&](auto k) { ut[k] = (sa * sUt[k][ia] + sb * sUt[k][ib]) / den; });
-  // |u|^2 summed in axis order
-  double q2 = 0.0;
+  double q2 = 0.0;  // |u|^2 summed in axis order
   unroll<NDIM>([&](auto a) {
-    const int slot = Fr::slot_of_axis(a);
-    const double ua = (slot == 0) ? un : ut[slot - 1];
+    constexpr int slot = Fr::slot_of_axis(decltype(a)::value);
+    double ua;
+    if constexpr (slot == 0) ua = un;
+    else ua = ut[slot - 1];
     q2 = (a == 0) ? ua * ua : q2 + ua * ua;
   });
   const double Hr = (sa * sH[ia] + sb * sH[ib]) / den;
@@ -345,106 +388,127 @@ __global__ __launch_bounds__(TT* TN) void sweep_kernel(SweepArgs A) {
   const double b2 = b1 * qq;
   const double unc = un / cr;
   const double ic = 1.0 / cr;
-
   // splitting speeds over the window
-  double am = 0.0, a0 = 0.0, ap = 0.0, ar = 0.0;
+  double am = 0.0, a0 = 0.0, ap = 0.0;
   unroll<W>([&](auto j) {
-    const int li = lidx(j);
+    const int li = lbase + j * LSTEP;
     const double u = sUn[li], c = sC[li];
     if (A.splitting == TENOAA_LLF) {
       am = dmax(am, fabs(u - c));
       a0 = dmax(a0, fabs(u));
       ap = dmax(ap, fabs(u + c));
     } else {
-      ar = dmax(ar, fabs(u) + c);
+      a0 = dmax(a0, fabs(u) + c);
     }
   });
-  if (A.splitting != TENOAA_LLF) am = a0 = ap = ar;
+  if (A.splitting != TENOAA_LLF) am = ap = a0;
 
-  double Fh[NV];  // back-projected flux, local frame
-  uint8_t* flag_out = nullptr;
-  int64_t flin = 0;
+  int64_t flin;
   {
-    int64_t fs_n = 1, fs_a = 1, fs_b = 1;  // face-array strides
     int64_t m[3] = {A.n[0], A.n[1], A.n[2]};
     m[DIR] = A.nf;
     const int64_t fstr[3] = {1, m[0], m[0] * m[1]};
-    fs_n = fstr[DIR];
-    fs_a = fstr[AX_A];
-    fs_b = fstr[AX_B];
-    flin = f * fs_n + t * fs_a + bcoord * fs_b;
-    if (FLAGS) flag_out = A.flags + flin;
+    flin = f * fstr[DIR] + t * fstr[AX_A] + bcoord * fstr[AX_B];
   }
+  uint8_t* const flag_out = A.flags ? A.flags + flin : nullptr;
 
-  unroll<NV>([&](auto s) {
-    // left eigenvector row s (local frame)
+  double Fh[NV];  // back-projected flux, local frame
+  unroll<NV>([&](auto c) { Fh[c] = 0.0; });
+#pragma unroll 1
+  for (int s = 0; s < NV; ++s) {
+    const bool shear = (s >= 2 && s <= NV - 2);
+    const bool acoustic = (s == 0 || s == NV - 1);
+    const double sgn = (s == 0) ? 1.0 : -1.0;  // u - c field: +, u + c field: -
+    // left eigenvector row s (local frame), the reading of the Roe eigenvectors
     double L[NV];
-    unroll<NV>([&](auto c) { L[c] = 0.0; });
-    if (s == 0 || s == NV - 1) {
-      const double sg = (s == 0) ? 1.0 : -1.0;
+    if (acoustic) {
       L[0] = (s == 0) ? 0.5 * (b2 + unc) : 0.5 * (b2 - unc);
       L[1] = (s == 0) ? 0.5 * (-b1 * un - ic) : 0.5 * (-b1 * un + ic);
       unroll<NDIM - 1>([&](auto k) { L[2 + k] = 0.5 * (-b1 * ut[k]); });
       L[NV - 1] = 0.5 * b1;
-      (void)sg;
-    } else if (s == 1) {
+    } else {
       L[0] = 1.0 - b2;
       L[1] = b1 * un;
       unroll<NDIM - 1>([&](auto k) { L[2 + k] = b1 * ut[k]; });
       L[NV - 1] = -b1;
     }
-    // projection of the window's state and flux on field s
-    double gp[W], gm[W];
+    (void)sgn;
+    double mut = 0.0;
+    int sl = 2;
+    if constexpr (NDIM == 3) {
+      mut = (s == 3) ? -ut[1] : -ut[0];
+      sl = s;
+    } else if constexpr (NDIM == 2) {
+      mut = -ut[0];
+    }
     const double alpha = (s == 0) ? am : (s == NV - 1 ? ap : a0);
+    // projection of the window's state and flux on field s, then the split
+    double gp[W], gm[W];
     unroll<W>([&](auto j) {
-      const int li = lidx(j);
+      const int li = lbase + j * LSTEP;
       double v, g;
-      if (s == 0 || s == 1 || s == NV - 1) {
-        v = L[0] * sW[0][li];
-        g = L[0] * sF[0][li];
+      if (!shear) {
+        const double2 w0 = sWF[0][li];
+        v = L[0] * w0.x;
+        g = L[0] * w0.y;
         unroll<NV - 1>([&](auto cc) {
-          v = fma(L[cc + 1], sW[cc + 1][li], v);
-          g = fma(L[cc + 1], sF[cc + 1][li], g);
+          const double2 w = sWF[cc + 1][li];
+          v = fma(L[cc + 1], w.x, v);
+          g = fma(L[cc + 1], w.y, g);
         });
       } else {
-        const double mu_t = -ut[s - 2];
-        v = mu_t * sW[0][li] + sW[s][li];
-        g = mu_t * sF[0][li] + sF[s][li];
+        const double2 w0 = sWF[0][li];
+        const double2 ws = sWF[sl][li];
+        v = mut * w0.x + ws.x;
+        g = mut * w0.y + ws.y;
       }
       gp[j] = 0.5 * fma(alpha, v, g);
-      gm[j] = 0.5 * fma(-alpha, v, g);
+      gm[W - 1 - j] = 0.5 * fma(-alpha, v, g);  // mirrored for the - side
+#if TENOAA_CELL_BARRIER
+      __builtin_amdgcn_sched_barrier(0);
+#endif
     });
     uint8_t flp = 0, flm = 0;
     const double hp = teno_aa<ORDER>(gp, flp);
-    double gr[W];
-    unroll<W>([&](auto j) { gr[j] = gm[W - 1 - j]; });
-    const double hm = teno_aa<ORDER>(gr, flm);
-    if (FLAGS) {
+    // keep the two reconstructions from being interleaved (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
+    const double hm = teno_aa<ORDER>(gm, flm);
+    if (flag_out) {
       flag_out[(int64_t)(s * 2 + 0) * A.nft] = flp;
       flag_out[(int64_t)(s * 2 + 1) * A.nft] = flm;
     }
     const double fh = hp + hm;
-    // back-projection: F += R[:, s] * fh, accumulated over s in order
+    // back-projection F = sum_s R[:, s] fh_s, accumulated over s in order
+    double r1 = 0.0, re = 0.0;
     if (s == 0) {
-      Fh[0] = fh;
-      Fh[1] = (un - cr) * fh;
-      unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = ut[k] * fh; });
-      Fh[NV - 1] = (Hr - un * cr) * fh;
-    } else if (s == 1) {
-      Fh[0] = Fh[0] + fh;
-      Fh[1] = fma(un, fh, Fh[1]);
-      unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = fma(ut[k], fh, Fh[2 + k]); });
-      Fh[NV - 1] = fma(qq, fh, Fh[NV - 1]);
+      r1 = un - cr;
+      re = Hr - un * cr;
     } else if (s == NV - 1) {
-      Fh[0] = Fh[0] + fh;
-      Fh[1] = fma(un + cr, fh, Fh[1]);
-      unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = fma(ut[k], fh, Fh[2 + k]); });
-      Fh[NV - 1] = fma(Hr + un * cr, fh, Fh[NV - 1]);
+      r1 = un + cr;
+      re = Hr + un * cr;
+    } else if (s == 1) {
+      r1 = un;
+      re = qq;
     } else {
-      Fh[s] = Fh[s] + fh;
-      Fh[NV - 1] = fma(ut[s - 2], fh, Fh[NV - 1]);
+      if constexpr (NDIM == 3) re = (s == 3) ? ut[1] : ut[0];
+      else if constexpr (NDIM == 2) re = ut[0];
     }
-  });
+    const double r0 = shear ? 0.0 : 1.0;
+    if (s == 0) {
+      Fh[0] = r0 * fh;
+      Fh[1] = r1 * fh;
+      unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = ut[k] * fh; });
+      Fh[NV - 1] = re * fh;
+    } else {
+      Fh[0] = fma(r0, fh, Fh[0]);
+      Fh[1] = fma(r1, fh, Fh[1]);
+      unroll<NDIM - 1>([&](auto k) {
+        const double rk = shear ? (s == 2 + (int)k ? 1.0 : 0.0) : ut[k];
+        Fh[2 + k] = fma(rk, fh, Fh[2 + k]);
+      });
+      Fh[NV - 1] = fma(re, fh, Fh[NV - 1]);
+    }
+  }
 
   if (LIMIT) {
     // Positivity limiter (reading of Hu, Adams & Shu 2013, applied in Sec. 5.3).
@@ -453,12 +517,15 @@ __global__ __launch_bounds__(TT* TN) void sweep_kernel(SweepArgs A) {
     const double sB = fabs(sUn[ib]) + sC[ib];
     const double aL = (sA >= sB) ? sA : sB;
     double FL[NV];
-    unroll<NV>([&](auto c) { FL[c] = 0.5 * ((sF[c][ia] + sF[c][ib]) - aL * (sW[c][ib] - sW[c][ia])); });
+    unroll<NV>([&](auto c) {
+      const double2 wa = sWF[c][ia], wb = sWF[c][ib];
+      FL[c] = 0.5 * ((wa.y + wb.y) - aL * (wb.x - wa.x));
+    });
     auto pressure = [&](const double (&X)[NV]) {
       const double rho = X[0];
       double q = 0.0;
       unroll<NDIM>([&](auto a) {
-        const double ua = X[1 + Fr::slot_of_axis(a)] / rho;
+        const double ua = X[1 + Fr::slot_of_axis(decltype(a)::value)] / rho;
         q = (a == 0) ? ua * ua : q + ua * ua;
       });
       return gm1 * (X[NV - 1] - (0.5 * rho) * q);
@@ -467,8 +534,9 @@ __global__ __launch_bounds__(TT* TN) void sweep_kernel(SweepArgs A) {
     unroll<2>([&](auto side) {
       const int li = side == 0 ? ia : ib;
       const double sg = side == 0 ? -1.0 : 1.0;
-      const double rL = sW[0][li] + (sg * mu) * FL[0];
-      const double rH = sW[0][li] + (sg * mu) * Fh[0];
+      const double r = sWF[0][li].x;
+      const double rL = r + (sg * mu) * FL[0];
+      const double rH = r + (sg * mu) * Fh[0];
       const double eps = rL < 1e-13 ? rL : 1e-13;
       const double th = (rH < eps) ? (rL - eps) / (rL - rH) : 1.0;
       th_r = th < th_r ? th : th_r;
@@ -480,9 +548,9 @@ __global__ __launch_bounds__(TT* TN) void sweep_kernel(SweepArgs A) {
       const int li = side == 0 ? ia : ib;
       const double sg = side == 0 ? -1.0 : 1.0;
       double X[NV];
-      unroll<NV>([&](auto c) { X[c] = sW[c][li] + (sg * mu) * FL[c]; });
+      unroll<NV>([&](auto c) { X[c] = sWF[c][li].x + (sg * mu) * FL[c]; });
       const double pL = pressure(X);
-      unroll<NV>([&](auto c) { X[c] = sW[c][li] + (sg * mu) * Fs[c]; });
+      unroll<NV>([&](auto c) { X[c] = sWF[c][li].x + (sg * mu) * Fs[c]; });
       const double pS = pressure(X);
       const double eps = pL < 1e-13 ? pL : 1e-13;
       const double th = (pS < eps) ? (pL - eps) / (pL - pS) : 1.0;
@@ -492,9 +560,12 @@ __global__ __launch_bounds__(TT* TN) void sweep_kernel(SweepArgs A) {
   }
 
   // store in axis order
-  A.F[0 * A.nft + flin] = Fh[0];
+  A.F[flin] = Fh[0];
   A.F[(int64_t)(NV - 1) * A.nft + flin] = Fh[NV - 1];
-  unroll<NDIM>([&](auto a) { A.F[(int64_t)(1 + a) * A.nft + flin] = Fh[1 + Fr::slot_of_axis(a)]; });
+  unroll<NDIM>([&](auto a) {
+    constexpr int slot = Fr::slot_of_axis(decltype(a)::value);
+    A.F[(int64_t)(1 + a) * A.nft + flin] = Fh[1 + slot];
+  });
 }
 
 // --------------------------------------------------- flux difference / RK
@@ -633,41 +704,35 @@ hipError_t upload_constants() {
   return e;
 }
 
-template <int ORDER, int NDIM, int DIR, bool LIMIT, bool FLAGS>
+template <int ORDER, int NDIM, int DIR, bool LIMIT>
 static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
-  constexpr int TT = (NDIM == 1) ? 1 : (DIR == 0 ? 4 : 16);
-  constexpr int TN = (DIR == 0) ? 64 : 16;
+  constexpr int TT = (NDIM == 1) ? 1 : (DIR == 0 ? TENOAA_TT_X : TENOAA_TT_YZ);
+  constexpr int TN = (DIR == 0) ? TENOAA_TN_X : TENOAA_TN_YZ;
   constexpr int AX_A = (DIR == 0) ? 1 : 0;
   constexpr int AX_B = (DIR == 2) ? 1 : 2;
   dim3 grid((unsigned)((a.nf + TN - 1) / TN), (unsigned)((a.n[AX_A] + TT - 1) / TT), (unsigned)a.n[AX_B]);
-  hipLaunchKernelGGL((sweep_kernel<ORDER, NDIM, DIR, TT, TN, LIMIT, FLAGS>), grid, dim3(TT * TN), 0, st, a);
+  hipLaunchKernelGGL((sweep_kernel<ORDER, NDIM, DIR, TT, TN, LIMIT>), grid, dim3(TT * TN), 0, st, a);
   return hipGetLastError();
 }
 
 template <int ORDER, int NDIM, int DIR>
-static hipError_t launch_sweep_o(const SweepArgs& a, bool limit, bool flags, hipStream_t st) {
-  if (limit) {
-    return flags ? launch_sweep_t<ORDER, NDIM, DIR, true, true>(a, st)
-                 : launch_sweep_t<ORDER, NDIM, DIR, true, false>(a, st);
-  }
-  return flags ? launch_sweep_t<ORDER, NDIM, DIR, false, true>(a, st)
-               : launch_sweep_t<ORDER, NDIM, DIR, false, false>(a, st);
+static hipError_t launch_sweep_o(const SweepArgs& a, bool limit, hipStream_t st) {
+  return limit ? launch_sweep_t<ORDER, NDIM, DIR, true>(a, st) : launch_sweep_t<ORDER, NDIM, DIR, false>(a, st);
 }
 
 template <int ORDER>
-static hipError_t launch_sweep_ord(int ndim, int dir, const SweepArgs& a, bool limit, bool flags, hipStream_t st) {
-  if (ndim == 1) return launch_sweep_o<ORDER, 1, 0>(a, limit, flags, st);
+static hipError_t launch_sweep_ord(int ndim, int dir, const SweepArgs& a, bool limit, hipStream_t st) {
+  if (ndim == 1) return launch_sweep_o<ORDER, 1, 0>(a, limit, st);
   if (ndim == 2) {
-    return dir == 0 ? launch_sweep_o<ORDER, 2, 0>(a, limit, flags, st) : launch_sweep_o<ORDER, 2, 1>(a, limit, flags, st);
+    return dir == 0 ? launch_sweep_o<ORDER, 2, 0>(a, limit, st) : launch_sweep_o<ORDER, 2, 1>(a, limit, st);
   }
-  if (dir == 0) return launch_sweep_o<ORDER, 3, 0>(a, limit, flags, st);
-  if (dir == 1) return launch_sweep_o<ORDER, 3, 1>(a, limit, flags, st);
-  return launch_sweep_o<ORDER, 3, 2>(a, limit, flags, st);
+  if (dir == 0) return launch_sweep_o<ORDER, 3, 0>(a, limit, st);
+  if (dir == 1) return launch_sweep_o<ORDER, 3, 1>(a, limit, st);
+  return launch_sweep_o<ORDER, 3, 2>(a, limit, st);
 }
 
-hipError_t launch_sweep(int order, int ndim, int dir, const SweepArgs& a, bool limit, bool flags, hipStream_t st) {
-  return order == 10 ? launch_sweep_ord<10>(ndim, dir, a, limit, flags, st)
-                     : launch_sweep_ord<8>(ndim, dir, a, limit, flags, st);
+hipError_t launch_sweep(int order, int ndim, int dir, const SweepArgs& a, bool limit, hipStream_t st) {
+  return order == 10 ? launch_sweep_ord<10>(ndim, dir, a, limit, st) : launch_sweep_ord<8>(ndim, dir, a, limit, st);
 }
 
 template <int NDIM>

@@ -18,7 +18,10 @@ LLF, RUSANOV = 0, 1
 WS_RHS, WS_STEP = 0, 1
 ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENONPHYSICAL", -5: "EWORKSPACE"}
 
-EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_get_status", "tenoaa_last_hip_error"]
+EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_get_status", "tenoaa_last_hip_error",
+           "tenoaa_timing_enable", "tenoaa_timing_read"]
+KCLASS_SWEEP = (0, 1, 2)
+KCLASS_UPDATE, KCLASS_WAVESPEED = 3, 4
 
 
 class Grid(ctypes.Structure):
@@ -57,6 +60,11 @@ def load():
         L.tenoaa_get_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
         L.tenoaa_last_hip_error.restype = ctypes.c_int
         L.tenoaa_last_hip_error.argtypes = []
+        L.tenoaa_timing_enable.restype = ctypes.c_int
+        L.tenoaa_timing_enable.argtypes = [ctypes.c_int32]
+        L.tenoaa_timing_read.restype = ctypes.c_int
+        L.tenoaa_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
 
@@ -167,6 +175,18 @@ def get_status(ws):
     if rc not in (0, -4):
         _check(rc, "tenoaa_get_status")
     return int(out.value)
+
+
+def timing_enable(on=True):
+    _check(load().tenoaa_timing_enable(1 if on else 0), "tenoaa_timing_enable")
+
+
+def timing_read(kclass):
+    """(launches, total_ms) of one kernel class since its last read."""
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(load().tenoaa_timing_read(kclass, ctypes.byref(n), ctypes.byref(ms)), "tenoaa_timing_read")
+    return int(n.value), float(ms.value)
 
 
 def grid_for(U, bc=None, dx=None):
