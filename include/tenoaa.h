@@ -71,7 +71,7 @@ enum { TENOAA_BC_PERIODIC = 0, TENOAA_BC_OUTFLOW = 1, TENOAA_BC_SYMMETRY = 2, TE
 enum { TENOAA_LLF = 0, TENOAA_RUSANOV = 1 };
 
 /* Workspace purposes for tenoaa_workspace_bytes. */
-enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1 };
+enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1, TENOAA_WS_RHS_VJP = 2, TENOAA_WS_STEP_VJP = 3 };
 
 /* Uniform cell-centred grid: cell i of direction d has centre (i + 1/2) dx[d].
  * n[d] >= order/2 for d < ndim and n[d] == 1 otherwise; dx[d] > 0. */
@@ -114,6 +114,40 @@ int tenoaa_rhs(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamm
 int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,
                 double* dt_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* Vector-Jacobian product of the right-hand side (the adjoint form; not a
+ * formula of the paper).  U_bar (overwritten) = (d dUdt / dU)^T dUdt_bar at
+ * U, with every threshold decision frozen at U: the stencil chosen by the
+ * cascade and the small-stencil deltas (Sec. 3.3), i.e. the linear weights
+ * of each reconstruction, and the cell and sign that attain each splitting
+ * speed.  The limiter is not part of the differentiated map (it acts only
+ * with a dt).  U_bar is accumulated with FP64 atomics, so its last bits can
+ * differ between runs.  U_bar must not alias U or dUdt_bar. */
+int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
+                   const double* dUdt_bar, double* U_bar, void* ws, size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of one SSP-RK3 step with the time step frozen:
+ * Un_bar (overwritten) = (d U^{n+1} / d U^n)^T Unp1_bar.  dt_dev is the device
+ * double holding the dt the forward step used (> 0).  The three stage states
+ * are recomputed from Un inside the call; each stage's decisions are frozen at
+ * its own state.  TENOAA_EUNSUPPORTED with the limiter on.  Un_bar must not
+ * alias Un or Unp1_bar. */
+int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* Un,
+                    const double* dt_dev, const double* Unp1_bar, double* Un_bar, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* Decision modes of tenoaa_step_flags. */
+enum { TENOAA_FLAGS_NONE = 0, TENOAA_FLAGS_RECORD = 1, TENOAA_FLAGS_REPLAY = 2 };
+
+/* tenoaa_step with the threshold decisions of its three stages recorded or
+ * replayed.  flags3 (device, 3 x the flag-array size, stage-major, each
+ * stage in the flag layout above): with TENOAA_FLAGS_RECORD it receives the
+ * decisions every stage takes; with TENOAA_FLAGS_REPLAY each reconstruction
+ * uses the recorded stencil and deltas instead of deciding (the map whose
+ * derivative tenoaa_step_vjp computes), and flags3 is only read;
+ * TENOAA_FLAGS_NONE is tenoaa_step (flags3 may be NULL). */
+int tenoaa_step_flags(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,
+                      double* dt_dev, uint8_t* flags3, int32_t mode, void* ws, size_t ws_bytes, void* stream);
+
 /* Synchronises `stream`, reads and clears the workspace status word.
  * *out = 0 if every state read since the last call was physical, else 1.
  * Returns TENOAA_ENONPHYSICAL if *out != 0, otherwise 0 (or an error). */
@@ -129,7 +163,10 @@ enum {
   TENOAA_KCLASS_SWEEP_Z = 2,
   TENOAA_KCLASS_UPDATE = 3,
   TENOAA_KCLASS_WAVESPEED = 4,
-  TENOAA_KCLASS_COUNT = 5
+  TENOAA_KCLASS_VJP_X = 5,
+  TENOAA_KCLASS_VJP_Y = 6,
+  TENOAA_KCLASS_VJP_Z = 7,
+  TENOAA_KCLASS_COUNT = 8
 };
 
 /* Measurement aid (host state shared by all threads, guarded by a mutex).

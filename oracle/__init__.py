@@ -70,6 +70,8 @@ def lib():
                                    ctypes.c_double, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), dp]
         L.or_rhs_jvp.restype = ctypes.c_int
         L.or_rhs_jvp.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, u8, dp, dp]
+        L.or_step_jvp.restype = ctypes.c_int
+        L.or_step_jvp.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, ctypes.c_double, u8, dp]
         L.or_step.restype = ctypes.c_int
         L.or_step.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, dp, dp, u8, dp]
@@ -174,7 +176,8 @@ def rhs_cells(grid, U, cells, order=10, splitting=LLF, positivity=0, gamma=1.4, 
 
 
 def rhs_jvp(grid, U, V, flags, order=10, splitting=LLF, gamma=1.4):
-    """Exact directional derivative of the RHS with decisions frozen to flags."""
+    """RHS(U) and its exact directional derivative J(U) V (forward mode), decisions
+    frozen to `flags`."""
     U = np.ascontiguousarray(U, dtype=np.float64)
     V = np.ascontiguousarray(V, dtype=np.float64)
     flags = np.ascontiguousarray(flags, dtype=np.uint8)
@@ -185,6 +188,18 @@ def rhs_jvp(grid, U, V, flags, order=10, splitting=LLF, gamma=1.4):
     if rc:
         raise ValueError("oracle rhs_jvp rejected its arguments (rc=%d)" % rc)
     return out, jv
+
+
+def step_jvp(grid, U, V, dt, flags3, order=10, splitting=LLF, gamma=1.4):
+    """Exact derivative of one RK3 step along V (dt fixed, stage decisions frozen)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    flags3 = np.ascontiguousarray(flags3, dtype=np.uint8)
+    out = np.empty_like(U)
+    rc = lib().or_step_jvp(ctypes.byref(grid), order, splitting, gamma, _dp(U), _dp(V), dt, _u8(flags3), _dp(out))
+    if rc:
+        raise ValueError("oracle step_jvp rejected its arguments (rc=%d)" % rc)
+    return out
 
 
 def step(grid, U, order=10, splitting=LLF, positivity=0, gamma=1.4, cfl=0.4, dt=0.0, want_flags=False):

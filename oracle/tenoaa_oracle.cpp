@@ -41,28 +41,49 @@
 // tests then allow disagreement only where this file reports a decision
 // within a relative 1e-12 of its threshold ("margin").
 //
-// The numerical core is templated on the scalar type so that a complex-step
-// evaluation with frozen decisions gives exact directional derivatives for
-// the adjoint tests.
+// The numerical core is templated on the scalar type so that a forward-mode
+// (dual-number) evaluation with frozen decisions gives exact directional
+// derivatives for the adjoint tests.
 #include <algorithm>
 #include <cmath>
-#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <vector>
 
 namespace {
 
-typedef std::complex<double> cplx;
+// Forward-mode derivative pair.  The value part is computed by exactly the
+// FP64 operations of the plain evaluation (fma included), so a derivative
+// evaluation takes the same decisions as the plain one; the d part carries
+// the exact directional derivative (to rounding).
+struct Dual {
+  double v, d;
+  Dual() : v(0.0), d(0.0) {}
+  Dual(double x) : v(x), d(0.0) {}  // NOLINT: constants promote implicitly
+  Dual(double x, double y) : v(x), d(y) {}
+};
+inline Dual operator+(const Dual& a, const Dual& b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(const Dual& a, const Dual& b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(const Dual& a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(const Dual& a, const Dual& b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(const Dual& a, const Dual& b) {
+  const double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
 
 inline double re(double x) { return x; }
-inline double re(const cplx& x) { return x.real(); }
+inline double re(const Dual& x) { return x.v; }
 inline double fmaT(double a, double b, double c) { return std::fma(a, b, c); }
-inline cplx fmaT(const cplx& a, const cplx& b, const cplx& c) { return a * b + c; }
+inline Dual fmaT(const Dual& a, const Dual& b, const Dual& c) {
+  return Dual(std::fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d);
+}
 inline double absT(double x) { return std::fabs(x); }
-inline cplx absT(const cplx& x) { return x.real() < 0.0 ? -x : x; }
+inline Dual absT(const Dual& x) { return x.v < 0.0 ? -x : x; }
 inline double sqrtT(double x) { return std::sqrt(x); }
-inline cplx sqrtT(const cplx& x) { return std::sqrt(x); }
+inline Dual sqrtT(const Dual& x) {
+  const double r = std::sqrt(x.v);
+  return Dual(r, x.d / (2.0 * r));
+}
 
 // ---------------------------------------------------------------- constants
 // Sec. 3.2: eps and q of the scale-separation formula.
@@ -853,24 +874,49 @@ int or_rhs_cells(const or_grid* g, int order, int splitting, int positivity, dou
   return 0;
 }
 
-// RHS with every decision frozen to the given flags, evaluated on U + i*h*V.
-// Returns Im(RHS)/h in jvp: the exact directional derivative of the
-// piecewise-smooth map at U along V (complex-step differentiation).
+// RHS with every decision frozen to the given flags and its exact directional
+// derivative along V (forward mode): rhs_out = RHS(U), jvp = J(U) V.
 int or_rhs_jvp(const or_grid* g, int order, int splitting, double gam, const double* U, const double* V,
                const uint8_t* flags, double* rhs_out, double* jvp) {
   build_beta_tables();
   Grid G = to_grid(g);
   Scheme s{order, splitting, 0};
   if (check_grid(G, s) || !flags) return -1;
-  const double h = 1e-150;
   const int64_t N = (int64_t)(G.ndim + 2) * G.n[0] * G.n[1] * G.n[2];
-  std::vector<cplx> Uc((size_t)N), dUc((size_t)N);
-  for (int64_t i = 0; i < N; ++i) Uc[(size_t)i] = cplx(U[i], h * V[i]);
+  std::vector<Dual> Ud((size_t)N), dUd((size_t)N);
+  for (int64_t i = 0; i < N; ++i) Ud[(size_t)i] = Dual(U[i], V[i]);
   double a[3] = {0, 0, 0};
-  rhs_impl<cplx>(G, s, gam, Uc.data(), dUc.data(), 0.0, a, nullptr, nullptr, flags);
+  rhs_impl<Dual>(G, s, gam, Ud.data(), dUd.data(), 0.0, a, nullptr, nullptr, flags);
   for (int64_t i = 0; i < N; ++i) {
-    if (rhs_out) rhs_out[i] = dUc[(size_t)i].real();
-    jvp[i] = dUc[(size_t)i].imag() / h;
+    if (rhs_out) rhs_out[i] = dUd[(size_t)i].v;
+    jvp[i] = dUd[(size_t)i].d;
+  }
+  return 0;
+}
+
+// Directional derivative of one SSP-RK3 step along V with dt fixed and each
+// stage's decisions frozen to flags3 (stage-major, as written by or_step),
+// in forward mode through the three stages.  Limiter off.
+int or_step_jvp(const or_grid* g, int order, int splitting, double gam, const double* U, const double* V,
+                double dt, const uint8_t* flags3, double* jvp) {
+  build_beta_tables();
+  Grid G = to_grid(g);
+  Scheme s{order, splitting, 0};
+  if (check_grid(G, s) || !flags3 || !(dt > 0.0)) return -1;
+  const int64_t N = (int64_t)(G.ndim + 2) * G.n[0] * G.n[1] * G.n[2];
+  const int64_t nfl = flag_offset(G, G.ndim);
+  std::vector<Dual> Un((size_t)N), U1((size_t)N), U2((size_t)N), L((size_t)N);
+  for (int64_t i = 0; i < N; ++i) Un[(size_t)i] = Dual(U[i], V[i]);
+  double a[3] = {0, 0, 0};
+  rhs_impl<Dual>(G, s, gam, Un.data(), L.data(), 0.0, a, nullptr, nullptr, flags3);
+  for (int64_t i = 0; i < N; ++i) U1[(size_t)i] = Un[(size_t)i] + dt * L[(size_t)i];
+  rhs_impl<Dual>(G, s, gam, U1.data(), L.data(), 0.0, a, nullptr, nullptr, flags3 + nfl);
+  for (int64_t i = 0; i < N; ++i)
+    U2[(size_t)i] = 0.75 * Un[(size_t)i] + 0.25 * U1[(size_t)i] + (0.25 * dt) * L[(size_t)i];
+  rhs_impl<Dual>(G, s, gam, U2.data(), L.data(), 0.0, a, nullptr, nullptr, flags3 + 2 * nfl);
+  for (int64_t i = 0; i < N; ++i) {
+    const Dual u3 = (1.0 / 3.0) * Un[(size_t)i] + (2.0 / 3.0) * U2[(size_t)i] + ((2.0 / 3.0) * dt) * L[(size_t)i];
+    jvp[i] = u3.d;
   }
   return 0;
 }

@@ -6,8 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtenoaa.so")
-SOURCES = ["tenoaa_kernels.hip", "tenoaa_capi.hip"]
-HEADERS = ["tenoaa_internal.h", "tenoaa_sos.h"]
+SOURCES = ["tenoaa_kernels.hip", "tenoaa_adjoint.hip", "tenoaa_capi.hip"]
+HEADERS = ["tenoaa_internal.h", "tenoaa_sos.h", "tenoaa_device.h"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

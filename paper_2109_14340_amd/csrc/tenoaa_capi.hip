@@ -13,6 +13,12 @@
 
 namespace {
 
+// The stage kernels read dt from the workspace scalars; the step adjoint takes
+// it from the caller's device double.
+__global__ void copy_dt_kernel(tenoaa::Scalars* S, const double* dt) {
+  if (threadIdx.x == 0) S->dt = *dt;
+}
+
 thread_local int g_last_hip_error = 0;
 
 int hip_fail(hipError_t e) {
@@ -109,7 +115,10 @@ int64_t faces_total(const tenoaa_grid* g, int d) {
 struct Layout {
   size_t scalars;       // offset of tenoaa::Scalars
   size_t fbuf[3];       // face flux arrays per direction
-  size_t stage;         // RK stage state (step only)
+  size_t vjp_flags;     // one direction's decisions (adjoint calls)
+  size_t vjp_fh;        // one direction's per-field fluxes (adjoint calls)
+  size_t stage;         // RK stage state(s)
+  size_t state_bytes;   // aligned size of one state
   size_t total;
 };
 
@@ -124,8 +133,20 @@ Layout layout(const tenoaa_grid* g, int which) {
     L.fbuf[d] = off;
     if (d < g->ndim) off += align256((size_t)nv * (size_t)faces_total(g, d) * sizeof(double));
   }
+  int64_t max_nft = 0;
+  for (int d = 0; d < g->ndim; ++d) max_nft = faces_total(g, d) > max_nft ? faces_total(g, d) : max_nft;
+  L.vjp_flags = L.vjp_fh = off;
+  if (which == TENOAA_WS_RHS_VJP || which == TENOAA_WS_STEP_VJP) {
+    L.vjp_flags = off;
+    off += align256((size_t)nv * 2 * (size_t)max_nft);
+    L.vjp_fh = off;
+    off += align256((size_t)nv * (size_t)max_nft * sizeof(double));
+  }
   L.stage = off;
-  if (which == TENOAA_WS_STEP) off += align256((size_t)nv * (size_t)ncell * sizeof(double));
+  const size_t state = align256((size_t)nv * (size_t)ncell * sizeof(double));
+  if (which == TENOAA_WS_STEP) off += state;
+  if (which == TENOAA_WS_STEP_VJP) off += 4 * state;  // U1, U2 (later B1), V, B2
+  L.state_bytes = state;
   L.total = off;
   return L;
 }
@@ -141,16 +162,25 @@ struct Ctx {
 };
 
 // Face fluxes of every direction for state U; flags optional.
-int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags) {
+int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint8_t* frozen = nullptr,
+           int only_dir = -1, double* fh_out = nullptr) {
   const tenoaa_grid* g = c.g;
   const int nv = g->ndim + 2;
   int64_t flag_off = 0;
   for (int d = 0; d < g->ndim; ++d) {
+    if (only_dir >= 0 && d != only_dir) {
+      flag_off += (int64_t)nv * 2 * faces_total(g, d);
+      continue;
+    }
     tenoaa::SweepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.U = U;
     a.F = reinterpret_cast<double*>(c.ws + c.L.fbuf[d]);
-    a.flags = flags ? flags + flag_off : nullptr;
+    // with only_dir set, flags/frozen point at that direction's own array
+    const int64_t fo = only_dir >= 0 ? 0 : flag_off;
+    a.flags = flags ? flags + fo : nullptr;
+    a.frozen = frozen ? frozen + fo : nullptr;
+    a.fh_out = fh_out;
     for (int k = 0; k < 3; ++k) a.n[k] = g->n[k];
     a.nf = faces_along(g, d);
     a.nft = faces_total(g, d);
@@ -187,6 +217,42 @@ int update(const Ctx& c, int mode, const double* Un, const double* Us, double* o
   return e == hipSuccess ? TENOAA_OK : hip_fail(e);
 }
 
+// U_bar = (d(dU/dt)/dU)^T R at U, decisions frozen at U.  Per direction the
+// forward sweep records its decisions and per-field fluxes in the workspace,
+// then the reverse sweep accumulates into U_bar.
+int rhs_vjp(const Ctx& c, const double* U, const double* R, double* Ubar) {
+  const tenoaa_grid* g = c.g;
+  const int nv = g->ndim + 2;
+  const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
+  hipError_t e = tenoaa::launch_zero(Ubar, (int64_t)nv * ncell, c.st);
+  if (e != hipSuccess) return hip_fail(e);
+  uint8_t* flags = reinterpret_cast<uint8_t*>(c.ws + c.L.vjp_flags);
+  double* fh = reinterpret_cast<double*>(c.ws + c.L.vjp_fh);
+  for (int d = 0; d < g->ndim; ++d) {
+    const int64_t nft = faces_total(g, d);
+    int rc = sweeps(c, U, false, flags, nullptr, d, fh);
+    if (rc) return rc;
+    tenoaa::AdjointArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.U = U;
+    a.R = R;
+    a.Ubar = Ubar;
+    a.flags = flags;
+    a.fh = fh;
+    a.nft = nft;
+    for (int k = 0; k < 3; ++k) a.n[k] = g->n[k];
+    a.nf = faces_along(g, d);
+    a.bc_lo = g->bc_lo[d];
+    a.bc_hi = g->bc_hi[d];
+    a.splitting = c.s->splitting;
+    a.gamma = c.gamma;
+    a.dx = g->dx[d];
+    e = timed(TENOAA_KCLASS_VJP_X + d, c.st, [&] { return tenoaa::launch_sweep_vjp(c.s->order, g->ndim, d, a, c.st); });
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return TENOAA_OK;
+}
+
 int prepare(Ctx& c, const tenoaa_grid* g, const tenoaa_scheme* s, double gamma, void* ws, size_t ws_bytes,
             void* stream, int which) {
   if (!valid_grid(g, s) || !(gamma > 1.0) || !ws) return TENOAA_EINVAL;
@@ -203,10 +269,7 @@ int prepare(Ctx& c, const tenoaa_grid* g, const tenoaa_scheme* s, double gamma, 
 }
 
 // First device work of an entry point, after every argument check passed.
-int begin(const Ctx&) {
-  hipError_t e = tenoaa::upload_constants();
-  return e == hipSuccess ? TENOAA_OK : hip_fail(e);
-}
+int begin(const Ctx&) { return TENOAA_OK; }
 
 }  // namespace
 
@@ -214,7 +277,7 @@ extern "C" {
 
 size_t tenoaa_workspace_bytes(const tenoaa_grid* grid, const tenoaa_scheme* scheme, int32_t which) {
   if (!valid_grid(grid, scheme)) return 0;
-  if (which != TENOAA_WS_RHS && which != TENOAA_WS_STEP) return 0;
+  if (which < TENOAA_WS_RHS || which > TENOAA_WS_STEP_VJP) return 0;
   return layout(grid, which).total;
 }
 
@@ -242,15 +305,26 @@ int tenoaa_rhs(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamm
 
 int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,
                 double* dt_dev, void* ws, size_t ws_bytes, void* stream) {
+  return tenoaa_step_flags(grid, scheme, gamma, cfl, U, dt_dev, nullptr, TENOAA_FLAGS_NONE, ws, ws_bytes, stream);
+}
+
+int tenoaa_step_flags(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,
+                      double* dt_dev, uint8_t* flags3, int32_t mode, void* ws, size_t ws_bytes, void* stream) {
   Ctx c;
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP);
   if (rc) return rc;
   if (!U || !dt_dev) return TENOAA_EINVAL;
   if (!(cfl > 0.0) || cfl > 1.0) return TENOAA_EINVAL;
   if (scheme->positivity && cfl > 0.5) return TENOAA_EINVAL;
+  if (mode < TENOAA_FLAGS_NONE || mode > TENOAA_FLAGS_REPLAY) return TENOAA_EINVAL;
+  if (mode != TENOAA_FLAGS_NONE && !flags3) return TENOAA_EINVAL;
   if ((rc = begin(c))) return rc;
   const int64_t ncell = grid->n[0] * grid->n[1] * grid->n[2];
   double* Us = reinterpret_cast<double*>(c.ws + c.L.stage);
+  int64_t nfl = 0;
+  for (int d = 0; d < grid->ndim; ++d) nfl += (int64_t)(grid->ndim + 2) * 2 * faces_total(grid, d);
+  auto rec = [&](int st) { return mode == TENOAA_FLAGS_RECORD ? flags3 + st * nfl : nullptr; };
+  auto rep = [&](int st) { return mode == TENOAA_FLAGS_REPLAY ? (const uint8_t*)flags3 + st * nfl : nullptr; };
   const bool limit = scheme->positivity != 0;
   hipError_t e = timed(TENOAA_KCLASS_WAVESPEED, c.st, [&] {
     hipError_t r = tenoaa::launch_wave_speeds(grid->ndim, U, ncell, gamma, c.S, &c.S->status, c.st);
@@ -259,14 +333,61 @@ int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gam
   });
   if (e != hipSuccess) return hip_fail(e);
   // stage 1: U1 = Un + dt L(Un)            -> Us
-  if ((rc = sweeps(c, U, limit, nullptr))) return rc;
+  if ((rc = sweeps(c, U, limit, rec(0), rep(0)))) return rc;
   if ((rc = update(c, 1, U, nullptr, Us))) return rc;
   // stage 2: U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1)   -> Us (in place)
-  if ((rc = sweeps(c, Us, limit, nullptr))) return rc;
+  if ((rc = sweeps(c, Us, limit, rec(1), rep(1)))) return rc;
   if ((rc = update(c, 2, U, Us, Us))) return rc;
   // stage 3: U = 1/3 Un + 2/3 U2 + 2/3 dt L(U2)    -> U (in place)
-  if ((rc = sweeps(c, Us, limit, nullptr))) return rc;
+  if ((rc = sweeps(c, Us, limit, rec(2), rep(2)))) return rc;
   return update(c, 3, U, Us, U);
+}
+
+int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
+                   const double* dUdt_bar, double* U_bar, void* ws, size_t ws_bytes, void* stream) {
+  Ctx c;
+  int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_RHS_VJP);
+  if (rc) return rc;
+  if (!U || !dUdt_bar || !U_bar || U_bar == U || U_bar == dUdt_bar) return TENOAA_EINVAL;
+  if ((rc = begin(c))) return rc;
+  return rhs_vjp(c, U, dUdt_bar, U_bar);
+}
+
+int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* Un,
+                    const double* dt_dev, const double* Unp1_bar, double* Un_bar, void* ws, size_t ws_bytes,
+                    void* stream) {
+  Ctx c;
+  int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP_VJP);
+  if (rc) return rc;
+  if (!Un || !dt_dev || !Unp1_bar || !Un_bar || Un_bar == Unp1_bar || Un_bar == Un) return TENOAA_EINVAL;
+  if (scheme->positivity) return TENOAA_EUNSUPPORTED;
+  if ((rc = begin(c))) return rc;
+  const int64_t N = (int64_t)(grid->ndim + 2) * grid->n[0] * grid->n[1] * grid->n[2];
+  double* S1 = reinterpret_cast<double*>(c.ws + c.L.stage);
+  double* S2 = reinterpret_cast<double*>(c.ws + c.L.stage + c.L.state_bytes);
+  double* V = reinterpret_cast<double*>(c.ws + c.L.stage + 2 * c.L.state_bytes);
+  double* B2 = reinterpret_cast<double*>(c.ws + c.L.stage + 3 * c.L.state_bytes);
+  double* B1 = S2;
+  hipError_t e;
+  // recompute the stages: U1 = Un + dt L(Un), U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1)
+  hipLaunchKernelGGL(copy_dt_kernel, dim3(1), dim3(64), 0, c.st, c.S, dt_dev);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
+  if ((rc = sweeps(c, Un, false, nullptr))) return rc;
+  if ((rc = update(c, 1, Un, nullptr, S1))) return rc;
+  if ((rc = sweeps(c, S1, false, nullptr))) return rc;
+  if ((rc = update(c, 2, Un, S1, S2))) return rc;
+  // reverse: B2 = 2/3 B3 + 2/3 dt J(U2)^T B3
+  if ((rc = rhs_vjp(c, S2, Unp1_bar, V))) return rc;
+  if ((e = tenoaa::launch_axpdtz(B2, 2.0 / 3.0, Unp1_bar, 2.0 / 3.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
+  // B1 = 1/4 B2 + 1/4 dt J(U1)^T B2
+  if ((rc = rhs_vjp(c, S1, B2, V))) return rc;
+  if ((e = tenoaa::launch_axpdtz(B1, 0.25, B2, 0.25, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
+  // Bn = 1/3 B3 + 3/4 B2 + B1 + dt J(Un)^T B1
+  if ((rc = rhs_vjp(c, Un, B1, V))) return rc;
+  if ((e = tenoaa::launch_axpbypcz(Un_bar, 1.0 / 3.0, Unp1_bar, 0.75, B2, 1.0, B1, N, c.st)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = tenoaa::launch_axpdtz(Un_bar, 1.0, Un_bar, 1.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
+  return TENOAA_OK;
 }
 
 int tenoaa_get_status(void* ws, void* stream, int32_t* out) {

@@ -21,6 +21,8 @@ struct SweepArgs {
   const double* U;
   double* F;        // face fluxes of this direction, [nvar][nft]
   uint8_t* flags;   // flags of this direction, [nvar][2][nft], or null
+  const uint8_t* frozen;  // decisions to replay instead of taking them, or null
+  double* fh_out;         // per-field reconstructed fluxes fh_s = f+_s + f-_s, [nvar][nft], or null
   int64_t n[3];
   int64_t nf;       // faces along the direction
   int64_t nft;      // faces of the direction in total
@@ -44,7 +46,28 @@ struct UpdateArgs {
   const double* dt;  // device
 };
 
-hipError_t upload_constants();
+struct AdjointArgs {
+  const double* U;   // state at which the right-hand side is differentiated
+  const double* R;   // seed: adjoint of dU/dt, layout of U
+  double* Ubar;      // accumulated with atomics (caller zeroes it)
+  const uint8_t* flags;  // decisions of this direction's forward sweep at U, [nvar][2][nft]
+  const double* fh;      // per-field fluxes of that sweep, [nvar][nft]
+  int64_t nft;
+  int64_t n[3];
+  int64_t nf;
+  int bc_lo, bc_hi;
+  int splitting;
+  int pad;
+  double gamma;
+  double dx;
+};
+
+hipError_t launch_sweep_vjp(int order, int ndim, int dir, const AdjointArgs& a, hipStream_t st);
+hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
+hipError_t launch_axpbypcz(double* out, double a, const double* x, double b, const double* y, double c,
+                           const double* z, int64_t n, hipStream_t st);
+hipError_t launch_axpdtz(double* out, double a, const double* x, double c, const double* dt, const double* z,
+                         int64_t n, hipStream_t st);
 hipError_t launch_sweep(int order, int ndim, int dir, const SweepArgs& a, bool limit, hipStream_t st);
 hipError_t launch_update(int ndim, int mode, const UpdateArgs& a, hipStream_t st);
 hipError_t launch_wave_speeds(int ndim, const double* U, int64_t ncell, double gam, Scalars* S, int* status,

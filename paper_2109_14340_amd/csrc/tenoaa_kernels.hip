@@ -24,8 +24,8 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "tenoaa_device.h"
 #include "tenoaa_internal.h"
-#include "tenoaa_sos.h"
 
 // Launch-shape tunables (overridable at build time).
 #ifndef TENOAA_WAVES_PER_EU
@@ -50,205 +50,7 @@
 namespace tenoaa {
 namespace {
 
-// ---------------------------------------------------------------- constants
-// Sec. 3.2: eps of the scale-separation formula, q = 7.
-constexpr double EPS = 1e-40;
-// Sec. 3.4: C_r, alpha_1, alpha_2; C_T = 10^{-K}, K = 7..14.
-constexpr double C_R = 0.265;
-constexpr double ALPHA1 = 14.0;
-constexpr double ALPHA2 = 6.4;
-__constant__ double c_ct[8] = {1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12, 1e-13, 1e-14};
-// Sec. 4.1 / 4.2: linear schemes on S3, S4, S5, leftmost coefficient first.
-constexpr double LIN6[6] = {0.02852274270130377, -0.1714015614372447, 0.650378818735941,
-                            0.6253788187359414, -0.1589015614372448, 0.02602274270130375};
-constexpr double LIN8[8] = {-0.006866688980568011, 0.05128582585522106, -0.1968478198727312,
-                            0.6552858258552222,    0.6452858258552218,  -0.1908478198727314,
-                            0.04928582585522098,   -0.006580974694853729};
-constexpr double LIN10[10] = {0.001911786299492748, -0.0170332977472532, 0.07339445614860979,
-                              -0.221228429084247,   0.6657332621611695,  0.6557332621611695,
-                              -0.2145617624175796,  0.07053731329146805, -0.01631901203296621,
-                              0.001832421220128962};
-// Fallback weights w_k = d_k delta_k / sum_l d_l delta_l for the 8 delta masks
-// (d_k of Sec. 4.1), filled by the host with the same IEEE expressions.
-__constant__ double c_wfall[8][3];
-
-// -------------------------------------------------------------- small math
-// Compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1, so
-// every index into a register array or constant table is a constant.
-template <int N, class F>
-__device__ __forceinline__ void unroll(F&& f) {
-  if constexpr (N > 0) {
-    unroll<N - 1>(f);
-    f(std::integral_constant<int, N - 1>{});
-  }
-}
-
-__device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
-
-// Reciprocal for decision-only quantities: the hardware estimate refined by
-// one Newton step (relative error below 3e-15 for finite non-zero x).
-__device__ __forceinline__ double rcp_dec(double x) {
-  const double r = __builtin_amdgcn_rcp(x);
-  const double e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
-// gamma = 1/(beta + eps)^7 (Sec. 3.2, q = 7), decision-only.
-__device__ __forceinline__ double gamma7(double beta) {
-  const double r = rcp_dec(beta + EPS);
-  const double r2 = r * r;
-  const double r4 = r2 * r2;
-  return (r4 * r2) * r;
-}
-
-// Smoothness indicator of a large stencil of width R whose leftmost value is
-// v[P]: the exact sum of squares in the forward-difference basis.
-template <int R, int P, int W>
-__device__ __forceinline__ double sos_beta(const double (&v)[W]) {
-  static_assert(R == 6 || R == 8 || R == 10, "large stencils only");
-  double lev[R];
-  unroll<R>([&](auto q) { lev[q] = v[P + q]; });
-  double dif[R - 1];  // Delta^{m+1} f_P
-  unroll<R - 1>([&](auto mm) {
-    constexpr int m = decltype(mm)::value;
-    unroll<R - 1 - m>([&](auto q) { lev[q] = lev[q + 1] - lev[q]; });
-    dif[m] = lev[0];
-  });
-  double beta = 0.0;
-  unroll<R - 1>([&](auto kk) {
-    constexpr int k = decltype(kk)::value;
-    double y = 0.0;
-    unroll<R - 1>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      if constexpr (m >= k) {
-        constexpr double l = (R == 10) ? SOS_S5_L[m][k] : (R == 8) ? SOS_S4_L[m][k] : SOS_S3_L[m][k];
-        if constexpr (l != 0.0) y = fma(l, dif[m], y);
-      }
-    });
-    constexpr double dk = (R == 10) ? SOS_S5_D[k] : (R == 8) ? SOS_S4_D[k] : SOS_S3_D[k];
-    beta = fma(dk, y * y, beta);
-  });
-  return beta;
-}
-
-template <int R>
-__device__ __host__ constexpr double lin_coef(int q) {
-  return (R == 10) ? LIN10[q] : (R == 8) ? LIN8[q] : LIN6[q];
-}
-
-// Linear scheme of width R on the values starting at v[P] (Sec. 4.1).
-template <int R, int P, int W>
-__device__ __forceinline__ double linear_flux(const double (&v)[W]) {
-  constexpr double c0 = lin_coef<R>(0);
-  double acc = c0 * v[P];
-  unroll<R - 1>([&](auto qq) {
-    constexpr int q = decltype(qq)::value;
-    constexpr double c = lin_coef<R>(q + 1);
-    acc = fma(c, v[P + q + 1], acc);
-  });
-  return acc;
-}
-
-// ------------------------------------------------- scalar TENO-AA (Sec. 3-4)
-// v[0..W-1] = f_{i-G+1..i+G}.  Returns fhat_{i+1/2}; flag gets the decision
-// byte (bits 0-1 large stencil, 2-4 deltas, 5-7 K-7).
-template <int ORDER>
-__device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& flag) {
-  constexpr int G = ORDER / 2;
-  constexpr int I = G - 1;  // index of f_i
-
-  // Sec. 3.4: eta_j = (|2 a b| + eps) / (a^2 + b^2 + eps), j = -1..2, with
-  // a = f_{j+1} - f_j, b = f_j - f_{j-1}; the minimum is located by cross
-  // multiplication and divided out once.
-  double dd[5];  // f_{k+1} - f_k for k = -2..2
-  unroll<5>([&](auto q) { dd[q] = v[I - 2 + q + 1] - v[I - 2 + q]; });
-  double nb = 0.0, db = 1.0;
-  unroll<4>([&](auto jj) {
-    const double a = dd[jj + 1];
-    const double b = dd[jj];
-    const double num = fabs((2.0 * a) * b) + EPS;
-    const double den = (a * a + b * b) + EPS;
-    if (jj == 0 || num * db < nb * den) {
-      nb = num;
-      db = den;
-    }
-  });
-  const double etabar = nb / db;
-  double ratio = etabar * (1.0 / C_R);
-  if (ratio > 1.0) ratio = 1.0;
-  const double m = 1.0 - ratio;
-  const double om = 1.0 - m;
-  const double om2 = om * om;
-  const double g = (om2 * om2) * (1.0 + 4.0 * m);
-  const double B = ALPHA1 - ALPHA2 * (1.0 - g);
-  int K = (int)floor(B);
-  K = K < 7 ? 7 : (K > 14 ? 14 : K);
-  const double CT = c_ct[K - 7];
-  const uint8_t kbits = (uint8_t)((K - 7) << 5);
-
-  // small stencils (Sec. 4.2, printed WENO-JS indicators) in difference form
-  const double b0a = dd[1] + dd[2];                // f_{i+1} - f_{i-1}
-  const double b0b = dd[2] - dd[1];                // f_{i-1} - 2 f_i + f_{i+1}
-  const double b1a = (dd[3] - dd[2]) - 2.0 * dd[2];  // f_{i+2} - 4 f_{i+1} + 3 f_i
-  const double b1b = dd[3] - dd[2];
-  const double b2a = (dd[1] - dd[0]) + 2.0 * dd[1];  // f_{i-2} - 4 f_{i-1} + 3 f_i
-  const double b2b = dd[1] - dd[0];
-  constexpr double C13 = 13.0 / 12.0;
-  const double g0 = gamma7(fma(C13, b0b * b0b, 0.25 * (b0a * b0a)));
-  const double g1 = gamma7(fma(C13, b1b * b1b, 0.25 * (b1a * b1a)));
-  const double g2 = gamma7(fma(C13, b2b * b2b, 0.25 * (b2a * b2a)));
-  const double S = (g0 + g1) + g2;
-
-  // Sec. 3.3: the groups (S0,S1,S2,Sp), largest p first; Sp is taken when
-  // chi_p = gamma_p / (S + gamma_p) >= C_T.
-  if constexpr (ORDER == 10) {
-    const double gp = gamma7(sos_beta<10, 0>(v));
-    if (gp >= CT * (S + gp)) {
-      flag = (uint8_t)(3 | kbits);
-      return linear_flux<10, 0>(v);
-    }
-  }
-  {
-    constexpr int P = (ORDER == 10) ? 1 : 0;
-    const double gp = gamma7(sos_beta<8, P>(v));
-    if (gp >= CT * (S + gp)) {
-      flag = (uint8_t)(2 | kbits);
-      return linear_flux<8, P>(v);
-    }
-  }
-  {
-    constexpr int P = (ORDER == 10) ? 2 : 1;
-    const double gp = gamma7(sos_beta<6, P>(v));
-    if (gp >= CT * (S + gp)) {
-      flag = (uint8_t)(1 | kbits);
-      return linear_flux<6, P>(v);
-    }
-  }
-  // fallback: TENO5 cut-off among the small stencils (Sec. 3.3)
-  const double cs = CT * S;
-  const int dm = (g0 >= cs ? 1 : 0) | (g1 >= cs ? 2 : 0) | (g2 >= cs ? 4 : 0);
-  flag = (uint8_t)((dm << 2) | kbits);
-  const double fm1 = v[I - 1], f0 = v[I], f1 = v[I + 1];
-  const double h0 = ((-fm1 + 5.0 * f0) + 2.0 * f1) / 6.0;
-  const double h1 = ((2.0 * f0 + 5.0 * f1) - v[I + 2]) / 6.0;
-  const double h2 = ((2.0 * v[I - 2] - 7.0 * fm1) + 11.0 * f0) / 6.0;
-  return fma(c_wfall[dm][2], h2, fma(c_wfall[dm][1], h1, c_wfall[dm][0] * h0));
-}
-
 // ------------------------------------------------------------ sweep kernel
-// Local frame of direction DIR: component 0 = rho, 1 = normal momentum,
-// 2.. = tangential momenta in ascending axis order, last = E.
-template <int NDIM, int DIR>
-struct Frame {
-  static constexpr int NV = NDIM + 2;
-  // axis index of tangential k (k = 0 .. NDIM-2)
-  static __host__ __device__ constexpr int tan_axis(int k) { return (k < DIR) ? k : k + 1; }
-  // local velocity slot (0 = normal, 1 + k = tangential k) of axis a
-  static __host__ __device__ constexpr int slot_of_axis(int a) {
-    return a == DIR ? 0 : (a < DIR ? 1 + a : a);
-  }
-};
-
 template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT>
 __global__ __launch_bounds__(TT* TN)
 #if TENOAA_WAVES_PER_EU > 0
@@ -411,6 +213,7 @@ void sweep_kernel(SweepArgs A) {
     flin = f * fstr[DIR] + t * fstr[AX_A] + bcoord * fstr[AX_B];
   }
   uint8_t* const flag_out = A.flags ? A.flags + flin : nullptr;
+  const uint8_t* const frozen = A.frozen ? A.frozen + flin : nullptr;
 
   double Fh[NV];  // back-projected flux, local frame
   unroll<NV>([&](auto c) { Fh[c] = 0.0; });
@@ -469,15 +272,25 @@ void sweep_kernel(SweepArgs A) {
 #endif
     });
     uint8_t flp = 0, flm = 0;
-    const double hp = teno_aa<ORDER>(gp, flp);
-    // keep the two reconstructions from being interleaved (register pressure)
-    __builtin_amdgcn_sched_barrier(0);
-    const double hm = teno_aa<ORDER>(gm, flm);
+    double hp, hm;
+    if (frozen) {
+      // replay recorded decisions
+      flp = frozen[(int64_t)(s * 2 + 0) * A.nft];
+      flm = frozen[(int64_t)(s * 2 + 1) * A.nft];
+      hp = replay_recon<ORDER>(gp, flp);
+      hm = replay_recon<ORDER>(gm, flm);
+    } else {
+      hp = teno_aa<ORDER>(gp, flp);
+      // keep the two reconstructions from being interleaved (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
+      hm = teno_aa<ORDER>(gm, flm);
+    }
     if (flag_out) {
       flag_out[(int64_t)(s * 2 + 0) * A.nft] = flp;
       flag_out[(int64_t)(s * 2 + 1) * A.nft] = flm;
     }
     const double fh = hp + hm;
+    if (A.fh_out) A.fh_out[(int64_t)s * A.nft + flin] = fh;
     // back-projection F = sum_s R[:, s] fh_s, accumulated over s in order
     double r1 = 0.0, re = 0.0;
     if (s == 0) {
@@ -685,25 +498,6 @@ __global__ void finalize_dt_kernel(Scalars* S, int ndim, double dx0, double dx1,
 }  // namespace
 
 // ------------------------------------------------------------ host launchers
-hipError_t upload_constants() {
-  static bool done = false;
-  if (done) return hipSuccess;
-  const double DK[3] = {0.5065006634, 0.3699651429, 0.1235341937};
-  double w[8][3];
-  for (int mask = 0; mask < 8; ++mask) {
-    const double del[3] = {(mask & 1) ? 1.0 : 0.0, (mask & 2) ? 1.0 : 0.0, (mask & 4) ? 1.0 : 0.0};
-    volatile double t0 = DK[0] * del[0], t1 = DK[1] * del[1], t2 = DK[2] * del[2];
-    volatile double dsum = (t0 + t1) + t2;
-    for (int k = 0; k < 3; ++k) {
-      volatile double num = DK[k] * del[k];
-      w[mask][k] = num / dsum;
-    }
-  }
-  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_wfall), w, sizeof(w));
-  if (e == hipSuccess) done = true;
-  return e;
-}
-
 template <int ORDER, int NDIM, int DIR, bool LIMIT>
 static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   constexpr int TT = (NDIM == 1) ? 1 : (DIR == 0 ? TENOAA_TT_X : TENOAA_TT_YZ);

@@ -15,13 +15,15 @@ LIB_PATH = os.path.join(HERE, "libtenoaa.so")
 
 BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP = 0, 1, 2, 3
 LLF, RUSANOV = 0, 1
-WS_RHS, WS_STEP = 0, 1
+WS_RHS, WS_STEP, WS_RHS_VJP, WS_STEP_VJP = 0, 1, 2, 3
 ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENONPHYSICAL", -5: "EWORKSPACE"}
 
-EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_get_status", "tenoaa_last_hip_error",
-           "tenoaa_timing_enable", "tenoaa_timing_read"]
+FLAGS_NONE, FLAGS_RECORD, FLAGS_REPLAY = 0, 1, 2
+EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_step_flags", "tenoaa_rhs_vjp", "tenoaa_step_vjp",
+           "tenoaa_get_status", "tenoaa_last_hip_error", "tenoaa_timing_enable", "tenoaa_timing_read"]
 KCLASS_SWEEP = (0, 1, 2)
 KCLASS_UPDATE, KCLASS_WAVESPEED = 3, 4
+KCLASS_VJP = (5, 6, 7)
 
 
 class Grid(ctypes.Structure):
@@ -56,6 +58,13 @@ def load():
         L.tenoaa_rhs.argtypes = [gp, sp, ctypes.c_double, vp, vp, ctypes.c_double, vp, vp, ctypes.c_size_t, vp]
         L.tenoaa_step.restype = ctypes.c_int
         L.tenoaa_step.argtypes = [gp, sp, ctypes.c_double, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tenoaa_step_flags.restype = ctypes.c_int
+        L.tenoaa_step_flags.argtypes = [gp, sp, ctypes.c_double, ctypes.c_double, vp, vp, vp, ctypes.c_int32, vp,
+                                        ctypes.c_size_t, vp]
+        L.tenoaa_rhs_vjp.restype = ctypes.c_int
+        L.tenoaa_rhs_vjp.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tenoaa_step_vjp.restype = ctypes.c_int
+        L.tenoaa_step_vjp.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.tenoaa_get_status.restype = ctypes.c_int
         L.tenoaa_get_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
         L.tenoaa_last_hip_error.restype = ctypes.c_int
@@ -165,6 +174,48 @@ def step(grid, scheme, U, dt_dev, gamma=1.4, cfl=0.4, ws=None):
     rc = load().tenoaa_step(ctypes.byref(grid), ctypes.byref(scheme), gamma, cfl, _ptr(U), _ptr(dt_dev),
                             _ptr(ws), ws.numel(), _stream())
     _check(rc, "tenoaa_step")
+    return U
+
+
+def rhs_vjp(grid, scheme, U, dUdt_bar, gamma=1.4, out=None, ws=None):
+    """(d dU/dt / dU)^T dUdt_bar at U with the decisions frozen at U."""
+    import torch
+    _check_state(U, grid)
+    _check_state(dUdt_bar, grid)
+    if out is None:
+        out = torch.empty_like(U)
+    if ws is None:
+        ws = workspace(grid, scheme, WS_RHS_VJP, U.device)
+    rc = load().tenoaa_rhs_vjp(ctypes.byref(grid), ctypes.byref(scheme), gamma, _ptr(U), _ptr(dUdt_bar), _ptr(out),
+                               _ptr(ws), ws.numel(), _stream())
+    _check(rc, "tenoaa_rhs_vjp")
+    return out
+
+
+def step_vjp(grid, scheme, Un, dt_dev, Unp1_bar, gamma=1.4, out=None, ws=None):
+    """(d U^{n+1} / d U^n)^T Unp1_bar for the step of size *dt_dev from Un."""
+    import torch
+    _check_state(Un, grid)
+    _check_state(Unp1_bar, grid)
+    if out is None:
+        out = torch.empty_like(Un)
+    if ws is None:
+        ws = workspace(grid, scheme, WS_STEP_VJP, Un.device)
+    rc = load().tenoaa_step_vjp(ctypes.byref(grid), ctypes.byref(scheme), gamma, _ptr(Un), _ptr(dt_dev),
+                                _ptr(Unp1_bar), _ptr(out), _ptr(ws), ws.numel(), _stream())
+    _check(rc, "tenoaa_step_vjp")
+    return out
+
+
+def step_flags(grid, scheme, U, dt_dev, flags3, mode, gamma=1.4, cfl=0.4, ws=None):
+    """tenoaa_step recording (mode FLAGS_RECORD) or replaying (FLAGS_REPLAY) the
+    decisions of its three stages in flags3 (uint8, 3 * flags_size(grid))."""
+    _check_state(U, grid)
+    if ws is None:
+        ws = workspace(grid, scheme, WS_STEP, U.device)
+    rc = load().tenoaa_step_flags(ctypes.byref(grid), ctypes.byref(scheme), gamma, cfl, _ptr(U), _ptr(dt_dev),
+                                  _ptr(flags3), mode, _ptr(ws), ws.numel(), _stream())
+    _check(rc, "tenoaa_step_flags")
     return U
 
 

@@ -507,3 +507,51 @@ def test_margins_report_near_decisions():
     f = np.sin(np.arange(10) * 0.3)
     _, _, m = oracle.teno(10, f)
     assert m > 1e-3
+
+
+# ------------------------------------------------ derivative evaluation
+
+
+@pytest.mark.parametrize("shape", [(24,), (10, 8), (7, 6, 6)])
+def test_oracle_jvp_matches_finite_differences(shape):
+    """The forward-mode derivative the adjoint tests compare against: its value
+    part is the plain RHS bit for bit, and on smooth data (no decision can flip
+    for a small perturbation) it matches central differences of the plain RHS."""
+    from paper_2109_14340_amd import inputs
+    U = inputs.random_smooth(shape, seed=11, kmax=1)
+    g = _grid(shape)
+    d, flags, margins = oracle.rhs(g, U, order=10)
+    V = np.random.default_rng(3).standard_normal(U.shape) * 1e-2
+    val, jv = oracle.rhs_jvp(g, U, V, flags, order=10)
+    assert np.array_equal(val, d)
+    eps = 1e-5
+    dp, fp, _ = oracle.rhs(g, U + eps * V, order=10)
+    dm, fm, _ = oracle.rhs(g, U - eps * V, order=10)
+    assert np.array_equal(fp, flags) and np.array_equal(fm, flags)
+    fd = (dp - dm) / (2 * eps)
+    assert np.abs(fd - jv).max() <= 1e-6 * np.abs(jv).max()
+    # linearity in the direction
+    _, jv2 = oracle.rhs_jvp(g, U, 3.0 * V, flags, order=10)
+    assert np.abs(jv2 - 3.0 * jv).max() <= 1e-13 * np.abs(jv).max()
+
+
+def test_oracle_step_jvp_is_the_stage_composition():
+    """The step derivative equals the chain of stage derivatives (Sec. 5 RK3)."""
+    from paper_2109_14340_amd import inputs
+    U = inputs.shock_tube_1d(40)
+    g = _grid((40,), oracle.BC_OUTFLOW)
+    _, dt, fl3, _ = oracle.step(g, U, order=8, cfl=0.4, want_flags=True)
+    nfl = fl3.size // 3
+    V = np.random.default_rng(4).standard_normal(U.shape)
+    jv = oracle.step_jvp(g, U, V, dt, fl3, order=8)
+    L0, _, _ = oracle.rhs(g, U, order=8)
+    U1 = U + dt * L0
+    L1, _, _ = oracle.rhs(g, U1, order=8)
+    U2 = 0.75 * U + 0.25 * U1 + (0.25 * dt) * L1
+    _, j0 = oracle.rhs_jvp(g, U, V, fl3[:nfl], order=8)
+    V1 = V + dt * j0
+    _, j1 = oracle.rhs_jvp(g, U1, V1, fl3[nfl:2 * nfl], order=8)
+    V2 = 0.75 * V + 0.25 * V1 + 0.25 * dt * j1
+    _, j2 = oracle.rhs_jvp(g, U2, V2, fl3[2 * nfl:], order=8)
+    V3 = V / 3 + 2.0 / 3.0 * V2 + (2.0 / 3.0) * dt * j2
+    assert np.abs(V3 - jv).max() <= 1e-12 * np.abs(V3).max()
