@@ -42,6 +42,52 @@ def cpu_baseline(n=64):
                       "%d^3 periodic grid: %d face reconstructions in %.2f s" % (n, work, el)}
 
 
+def fwd_adj_leg(shape, steps, warmup, U0):
+    """Forward step plus its adjoint (tenoaa_step_vjp, which recomputes the
+    stages) on one state, TENO10-AA, LLF, no limiter (the adjoint does not
+    differentiate the limiter), dt from CFL 0.4 then frozen for the adjoint.
+    The 3D state is the Gaussian random field without the blast and cavity
+    spheres, which need the limiter to stay physical."""
+    import torch
+
+    from paper_2109_14340_amd import tenoaa
+
+    dev = U0.device
+    grid = tenoaa.make_grid(shape)
+    sch = tenoaa.make_scheme(10, tenoaa.LLF, 0)
+    ws = tenoaa.workspace(grid, sch, tenoaa.WS_STEP, dev)
+    wsv = tenoaa.workspace(grid, sch, tenoaa.WS_STEP_VJP, dev)
+    U = U0.clone()
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    bar = torch.randn(U.shape, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(14340))
+    out = torch.empty_like(bar)
+
+    def fwd():
+        U.copy_(U0)
+        dt.zero_()
+        tenoaa.step(grid, sch, U, dt, gamma=1.4, cfl=0.4, ws=ws)
+
+    def adj():
+        tenoaa.step_vjp(grid, sch, U0, dt, bar, gamma=1.4, out=out, ws=wsv)
+
+    res = {}
+    for name, fn in (("fwd", fwd), ("adj", adj)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / steps * 1e3
+    work = 3 * len(shape) * U0[0].numel()
+    return {"grid": list(shape), "fwd_ms": round(res["fwd"], 3), "adj_ms": round(res["adj"], 3),
+            "adj_over_fwd": round(res["adj"] / res["fwd"], 3),
+            "value": round(work / ((res["fwd"] + res["adj"]) * 1e-3) / 1e9, 4), "unit": "Gface-recon/s",
+            "note": "face reconstructions of the forward step / (step + step VJP time); the forward "
+                    "copy of the input state is inside fwd_ms"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +95,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fwd-adj", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -135,8 +182,13 @@ def main():
                      "algorithmic_flops_per_launch": fl_total,
                      "path_counts": {"S5": hist[3], "S4": hist[2], "S3": hist[1], "fallback": hist[0]},
                      "per_kernel_avg_ms": {k: round(v[1] / max(v[0], 1), 4) for k, v in per.items()}},
-        "fwd_adj": None,
     }
+    if not args.no_fwd_adj:
+        U3 = torch.from_numpy(inputs.grf_3d(n, spheres=False)).to(dev)
+        U2 = torch.from_numpy(inputs.grf_2d(512, jump=False)).to(dev)
+        line["fwd_adj"] = {"3d": fwd_adj_leg((n, n, n), 3, 1, U3),
+                           "2d_512_periodic": fwd_adj_leg((512, 512), 20, 3, U2)}
+        del U3, U2
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
