@@ -40,6 +40,9 @@
 #ifndef TENOAA_ADJ_TT_YZ
 #define TENOAA_ADJ_TT_YZ 8
 #endif
+#ifndef TENOAA_ADJ_WAVES_PER_EU
+#define TENOAA_ADJ_WAVES_PER_EU 0
+#endif
 
 namespace tenoaa {
 namespace {
@@ -78,7 +81,11 @@ __device__ __forceinline__ void recon_weights(uint8_t flag, double (&w)[ORDER]) 
 __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
 
 template <int ORDER, int NDIM, int DIR, int TT, int TN>
-__global__ __launch_bounds__(TT* TN) void sweep_vjp_kernel(AdjointArgs A) {
+__global__ __launch_bounds__(TT* TN)
+#if TENOAA_ADJ_WAVES_PER_EU > 0
+__attribute__((amdgpu_waves_per_eu(TENOAA_ADJ_WAVES_PER_EU)))
+#endif
+void sweep_vjp_kernel(AdjointArgs A) {
   constexpr int G = ORDER / 2;
   constexpr int W = ORDER;
   constexpr int NV = NDIM + 2;
