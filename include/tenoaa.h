@@ -13,7 +13,8 @@
  *  - Memory: every double/uint8 array argument is DEVICE memory on the
  *    current HIP device unless stated otherwise.  Grid and scheme structs are
  *    HOST memory and are read before the call returns.  The caller owns all
- *    buffers; the library never allocates or frees in these calls.
+ *    buffers; the library never allocates or frees, except that a batch plan
+ *    owns the device memory it allocates at creation and frees at destruction.
  *  - Layout of a state array U: float64, structure of arrays
  *    U[v][k][j][i] with i (x) fastest, v = 0..nvar-1, nvar = ndim + 2 and
  *    components (rho, rho*u, [rho*v], [rho*w], E).  Sizes of unused
@@ -57,7 +58,8 @@ enum {
   TENOAA_EUNSUPPORTED = -2,
   TENOAA_EHIP = -3,
   TENOAA_ENONPHYSICAL = -4,
-  TENOAA_EWORKSPACE = -5
+  TENOAA_EWORKSPACE = -5,
+  TENOAA_ETIMEOUT = -6
 };
 
 /* Boundary conditions (Appendix A of the paper; OUTFLOW copies the nearest
@@ -152,6 +154,62 @@ int tenoaa_step_flags(const tenoaa_grid* grid, const tenoaa_scheme* scheme, doub
  * *out = 0 if every state read since the last call was physical, else 1.
  * Returns TENOAA_ENONPHYSICAL if *out != 0, otherwise 0 (or an error). */
 int tenoaa_get_status(void* ws, void* stream, int32_t* out);
+
+/* ---- Batched form (not a formula of the paper): many independent 2D
+ * problems of uneven size, each advanced by SSP-RK3 steps with its own dt, in
+ * one persistent launch replayed from a HIP graph.  Every problem evolves
+ * exactly (bit for bit) as nsteps calls of tenoaa_step on it would. */
+typedef struct tenoaa_batch_plan tenoaa_batch_plan;
+
+/* Plans nprob >= 1 problems (grids[p]: host array, each with ndim == 2 and
+ * valid as for tenoaa_step) sharing one scheme, gamma and cfl (dt of every
+ * step of every problem from the CFL condition on its own state), nsteps >= 1
+ * steps per run.  The plan owns its device workspace (a stage state and the
+ * face fluxes of every problem, about 3 states' worth) and a HIP graph of
+ * one clearing kernel and the persistent kernel, all created here on the
+ * current device.  Tile shapes (two candidates per sweep direction for each
+ * of three n_x buckets: <= 160, <= 320, larger), the items taken per queue
+ * access and the blocks per compute unit are chosen as follows: with
+ * tune_cache_path NULL or "", defaults; otherwise the JSON-lines file is
+ * searched for this plan's key ("gfx950 order=O split=S limit=L
+ * buckets=a,b,c", the counts of problems per n_x bucket) and, when absent,
+ * the choices are tuned now on the device by timing one step of the batch
+ * from a uniform state, and appended to the file as
+ * {"key": ..., "tile_x": [3], "tile_y": [3], "chunk": c, "blocks_per_cu": b,
+ * "step_ms": t}.  Results do not depend on these choices.  Returns EINVAL
+ * for bad arguments, EUNSUPPORTED for ndim != 2, EHIP on a HIP failure;
+ * *out is NULL unless 0 is returned. */
+int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const tenoaa_scheme* scheme, double gamma,
+                             double cfl, int32_t nsteps, const char* tune_cache_path, tenoaa_batch_plan** out);
+
+/* Packed layout of the batch state: out (host, nprob + 1 entries) receives
+ * the offset in doubles of problem p's state (the single-grid layout) for
+ * p < nprob, then the total length.  Problems are packed densely in the
+ * caller's order. */
+int tenoaa_batch_offsets(const tenoaa_batch_plan* plan, int64_t* out);
+
+/* Advances every problem of the packed device state U_packed by the plan's
+ * nsteps steps in place: one graph launch on `stream`, no allocation and no
+ * host synchronisation.  dt_out (device, nprob * nsteps doubles, problem-major)
+ * receives every dt used, or is NULL.  Runs of one plan share its workspace:
+ * the caller orders them (one stream, or events). */
+int tenoaa_batch_run(tenoaa_batch_plan* plan, double* U_packed, double* dt_out, void* stream);
+
+/* Synchronises `stream` and reports the last run: status_out (host, nprob
+ * entries, or NULL) receives 1 for each problem in which a non-physical
+ * state was read.  Returns TENOAA_ETIMEOUT if the launch abandoned the run
+ * at a phase barrier (its grid was not resident; results invalid),
+ * TENOAA_ENONPHYSICAL if any problem was non-physical, else 0. */
+int tenoaa_batch_get_status(tenoaa_batch_plan* plan, void* stream, int32_t* status_out);
+
+/* Launch choices of a plan: info (host, n >= 10 entries) receives blocks
+ * launched, blocks per compute unit, items per queue access, how the choices
+ * were made (0 defaults, 1 tuned now, 2 from the cache file), then the x-tile
+ * and y-tile candidates of the three n_x buckets. */
+int tenoaa_batch_plan_info(const tenoaa_batch_plan* plan, int32_t* info, int32_t n);
+
+/* Releases the plan's device memory and graph (after its runs completed). */
+int tenoaa_batch_plan_destroy(tenoaa_batch_plan* plan);
 
 /* hipError_t of the last failed HIP call in this thread (0 if none). */
 int tenoaa_last_hip_error(void);

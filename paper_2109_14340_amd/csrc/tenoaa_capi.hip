@@ -73,8 +73,8 @@ hipError_t collect_timing() {
     if (e != hipSuccess) return e;
     g_launches[t.cls] += 1;
     g_total_ms[t.cls] += ms;
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
   g_timed.clear();
   return hipSuccess;
@@ -272,6 +272,11 @@ int prepare(Ctx& c, const tenoaa_grid* g, const tenoaa_scheme* s, double gamma, 
 int begin(const Ctx&) { return TENOAA_OK; }
 
 }  // namespace
+
+namespace tenoaa {
+bool grid_ok(const tenoaa_grid* g, const tenoaa_scheme* s) { return valid_grid(g, s); }
+void record_hip_error(hipError_t e) { g_last_hip_error = (int)e; }
+}  // namespace tenoaa
 
 extern "C" {
 

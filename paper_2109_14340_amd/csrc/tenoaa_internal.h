@@ -62,6 +62,11 @@ struct AdjointArgs {
   double dx;
 };
 
+// Argument check of a grid and scheme (shared by every entry point).
+bool grid_ok(const tenoaa_grid* g, const tenoaa_scheme* s);
+// Keeps e for tenoaa_last_hip_error().
+void record_hip_error(hipError_t e);
+
 hipError_t launch_sweep_vjp(int order, int ndim, int dir, const AdjointArgs& a, hipStream_t st);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
 hipError_t launch_axpbypcz(double* out, double a, const double* x, double b, const double* y, double c,

@@ -1,0 +1,461 @@
+// Device bodies of the forward path, shared by the per-grid kernels
+// (tenoaa_kernels.hip) and the batched persistent kernel (tenoaa_batch.hip),
+// so that both evaluate every face and cell with the same operations:
+//
+//   sweep_tile   one tile of faces of one direction: staging of the cell
+//                records in LDS (boundary conditions by index mapping, cell
+//                primitives and physical flux, Sec. 1), then per face the Roe
+//                average and eigenvectors, projection, LLF/Rusanov split,
+//                TENO-AA reconstruction of both sides (Sec. 3, 4),
+//                back-projection and the optional positivity limiter (Sec. 5);
+//   update_cell  flux difference and the SSP-RK3 stage of one cell;
+//   cell_speeds  |u_d| + c of one cell for the CFL condition;
+//   dt_and_mu    dt = CFL / sum_d a_d/dx_d and the limiter factors.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "tenoaa_device.h"
+#include "tenoaa_internal.h"
+
+// 1: a scheduling barrier after each window cell of the projection (tuning)
+#ifndef TENOAA_CELL_BARRIER
+#define TENOAA_CELL_BARRIER 0
+#endif
+
+namespace tenoaa {
+namespace {
+
+// Tile geometry of a sweep: TN faces along the direction for each of TT
+// pencils; the tile stages TN + W - 1 cells per pencil.
+template <int ORDER, int NDIM, int TT, int TN>
+struct SweepShape {
+  static constexpr int W = ORDER;
+  static constexpr int NV = NDIM + 2;
+  static constexpr int NT = (NDIM > 1) ? NDIM - 1 : 1;
+  static constexpr int NC = TN + W - 1;
+  static constexpr int NCT = TT * NC;
+  static constexpr int NTH = TT * TN;
+  // per-cell records: NV double2 (conserved, flux) + un, c, sqrt(rho), H + NT tangential velocities
+  static constexpr int LDS_BYTES = NCT * (16 * NV + 8 * (4 + NT));
+};
+
+// One tile of faces.  (bx, by, bz) = (tile index along the direction, tile
+// index across it, coordinate along the remaining axis).  `lds` holds at
+// least SweepShape::LDS_BYTES bytes, 16-byte aligned; the caller separates
+// consecutive tiles that reuse it with a barrier.  `mu` is the limiter factor
+// of this direction (used when LIMIT).
+template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT>
+__device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_t bx, int64_t by, int64_t bz,
+                                           double mu) {
+  using Sh = SweepShape<ORDER, NDIM, TT, TN>;
+  constexpr int G = ORDER / 2;
+  constexpr int W = ORDER;
+  constexpr int NV = Sh::NV;
+  constexpr int NT = Sh::NT;
+  constexpr int NC = Sh::NC;
+  constexpr int NCT = Sh::NCT;
+  constexpr int AX_A = (DIR == 0) ? 1 : 0;  // transverse axis spread over threads
+  constexpr int AX_B = (DIR == 2) ? 1 : 2;  // remaining axis
+  using Fr = Frame<NDIM, DIR>;
+
+  // per-cell records: (conserved, flux) pairs in the local frame, then
+  // normal velocity, sound speed, sqrt(rho), enthalpy, tangential velocities
+  double2* const sWF = reinterpret_cast<double2*>(lds);
+  double* const sUn = reinterpret_cast<double*>(lds + 16 * NV * NCT);
+  double* const sC = sUn + NCT;
+  double* const sSr = sC + NCT;
+  double* const sH = sSr + NCT;
+  double* const sUt = sH + NCT;
+
+  const int64_t nN = A.n[DIR];
+  const int64_t nA = A.n[AX_A];
+  const int64_t stride[3] = {1, A.n[0], A.n[0] * A.n[1]};
+  const int64_t ncell = A.n[0] * A.n[1] * A.n[2];
+  const int64_t f0 = bx * TN;
+  const int64_t t0 = by * TT;
+  const int64_t bcoord = bz;
+  const double gam = A.gamma;
+  const double gm1 = gam - 1.0;
+
+  // ---- stage the tile: cells f0-G .. f0+TN+G-2 along the normal
+  for (int ct = threadIdx.x; ct < NCT; ct += TT * TN) {
+    int tt, nn;
+    if (DIR == 0) {
+      tt = ct / NC;
+      nn = ct % NC;
+    } else {
+      tt = ct % TT;
+      nn = ct / TT;
+    }
+    int64_t t = t0 + tt;
+    if (t >= nA) t = nA - 1;
+    int64_t l = f0 - G + nn;
+    bool mirror = false;
+    int bc = -1;
+    if (l < 0 || l >= nN) {
+      bc = (l < 0) ? A.bc_lo : A.bc_hi;
+      if (bc == TENOAA_BC_PERIODIC) {
+        l = ((l % nN) + nN) % nN;
+      } else if (bc == TENOAA_BC_OUTFLOW) {
+        l = (l < 0) ? 0 : nN - 1;
+      } else {
+        l = (l < 0) ? -l - 1 : 2 * nN - 1 - l;
+        mirror = true;
+      }
+      if (l < 0) l = 0;
+      if (l >= nN) l = nN - 1;
+    }
+    const int64_t off = l * stride[DIR] + t * stride[AX_A] + bcoord * stride[AX_B];
+    double Wc[NV];
+    unroll<NV>([&](auto c) { Wc[c] = A.U[c * ncell + off]; });
+    if (mirror) {
+      if (bc == TENOAA_BC_SYMMETRY) {
+        Wc[1 + DIR] = -Wc[1 + DIR];
+      } else {
+        unroll<NDIM>([&](auto k) { Wc[1 + k] = -Wc[1 + k]; });
+      }
+    }
+    // cell primitives (Sec. 1), axis order
+    const double rho = Wc[0];
+    double u[NDIM];
+    double q2 = 0.0;
+    unroll<NDIM>([&](auto k) {
+      u[k] = Wc[1 + k] / rho;
+      q2 = (k == 0) ? u[0] * u[0] : q2 + u[k] * u[k];
+    });
+    const double E = Wc[NV - 1];
+    const double p = gm1 * (E - (0.5 * rho) * q2);
+    const double c = sqrt((gam * p) / rho);
+    const double H = (E + p) / rho;
+    const double sr = sqrt(rho);
+    const double un = u[DIR];
+    if (!(rho > 0.0) || !(p > 0.0)) atomicOr(A.status, 1);
+    // conserved state and physical flux along DIR in the local frame
+    sWF[ct] = make_double2(rho, Wc[1 + DIR]);
+    unroll<NDIM>([&](auto k) {
+      constexpr int slot = Fr::slot_of_axis(decltype(k)::value);
+      sWF[(1 + slot) * NCT + ct] = make_double2(Wc[1 + k], (k == DIR) ? Wc[1 + k] * un + p : Wc[1 + k] * un);
+      if constexpr (slot > 0) sUt[(slot - 1) * NCT + ct] = u[k];
+    });
+    sWF[(NV - 1) * NCT + ct] = make_double2(E, (E + p) * un);
+    sUn[ct] = un;
+    sC[ct] = c;
+    sSr[ct] = sr;
+    sH[ct] = H;
+  }
+  __syncthreads();
+
+  // ---- one face per thread
+  int tt, fn;
+  if (DIR == 0) {
+    tt = threadIdx.x / TN;
+    fn = threadIdx.x % TN;
+  } else {
+    tt = threadIdx.x % TT;
+    fn = threadIdx.x / TT;
+  }
+  const int64_t f = f0 + fn;
+  const int64_t t = t0 + tt;
+  if (f >= A.nf || t >= nA) return;
+  // LDS index of window cell j (cells f-G .. f+G-1)
+  const int lbase = (DIR == 0) ? tt * NC + fn : fn * TT + tt;
+  constexpr int LSTEP = (DIR == 0) ? 1 : TT;
+  const int ia = lbase + (G - 1) * LSTEP, ib = lbase + G * LSTEP;
+
+  // Roe average (Sec. 5: characteristic decomposition at the face)
+  const double sa = sSr[ia], sb = sSr[ib];
+  const double den = sa + sb;
+  const double un = (sa * sUn[ia] + sb * sUn[ib]) / den;
+  double ut[NT];
+  unroll<NDIM - 1>([&](auto k) { ut[k] = (sa * sUt[k * NCT + ia] + sb * sUt[k * NCT + ib]) / den; });
+  double q2 = 0.0;  // |u|^2 summed in axis order
+  unroll<NDIM>([&](auto a) {
+    constexpr int slot = Fr::slot_of_axis(decltype(a)::value);
+    double ua;
+    if constexpr (slot == 0) ua = un;
+    else ua = ut[slot - 1];
+    q2 = (a == 0) ? ua * ua : q2 + ua * ua;
+  });
+  const double Hr = (sa * sH[ia] + sb * sH[ib]) / den;
+  const double qq = 0.5 * q2;
+  const double c2 = gm1 * (Hr - qq);
+  const double cr = sqrt(c2);
+  const double b1 = gm1 / c2;
+  const double b2 = b1 * qq;
+  const double unc = un / cr;
+  const double ic = 1.0 / cr;
+  // splitting speeds over the window
+  double am = 0.0, a0 = 0.0, ap = 0.0;
+  unroll<W>([&](auto j) {
+    const int li = lbase + j * LSTEP;
+    const double u = sUn[li], c = sC[li];
+    if (A.splitting == TENOAA_LLF) {
+      am = dmax(am, fabs(u - c));
+      a0 = dmax(a0, fabs(u));
+      ap = dmax(ap, fabs(u + c));
+    } else {
+      a0 = dmax(a0, fabs(u) + c);
+    }
+  });
+  if (A.splitting != TENOAA_LLF) am = ap = a0;
+
+  int64_t flin;
+  {
+    int64_t m[3] = {A.n[0], A.n[1], A.n[2]};
+    m[DIR] = A.nf;
+    const int64_t fstr[3] = {1, m[0], m[0] * m[1]};
+    flin = f * fstr[DIR] + t * fstr[AX_A] + bcoord * fstr[AX_B];
+  }
+  uint8_t* const flag_out = A.flags ? A.flags + flin : nullptr;
+  const uint8_t* const frozen = A.frozen ? A.frozen + flin : nullptr;
+
+  double Fh[NV];  // back-projected flux, local frame
+  unroll<NV>([&](auto c) { Fh[c] = 0.0; });
+#pragma unroll 1
+  for (int s = 0; s < NV; ++s) {
+    const bool shear = (s >= 2 && s <= NV - 2);
+    const bool acoustic = (s == 0 || s == NV - 1);
+    // left eigenvector row s (local frame), the reading of the Roe eigenvectors
+    double L[NV];
+    if (acoustic) {
+      L[0] = (s == 0) ? 0.5 * (b2 + unc) : 0.5 * (b2 - unc);
+      L[1] = (s == 0) ? 0.5 * (-b1 * un - ic) : 0.5 * (-b1 * un + ic);
+      unroll<NDIM - 1>([&](auto k) { L[2 + k] = 0.5 * (-b1 * ut[k]); });
+      L[NV - 1] = 0.5 * b1;
+    } else {
+      L[0] = 1.0 - b2;
+      L[1] = b1 * un;
+      unroll<NDIM - 1>([&](auto k) { L[2 + k] = b1 * ut[k]; });
+      L[NV - 1] = -b1;
+    }
+    double mut = 0.0;
+    int sl = 2;
+    if constexpr (NDIM == 3) {
+      mut = (s == 3) ? -ut[1] : -ut[0];
+      sl = s;
+    } else if constexpr (NDIM == 2) {
+      mut = -ut[0];
+    }
+    const double alpha = (s == 0) ? am : (s == NV - 1 ? ap : a0);
+    // projection of the window's state and flux on field s, then the split
+    double gp[W], gm[W];
+    unroll<W>([&](auto j) {
+      const int li = lbase + j * LSTEP;
+      double v, g;
+      if (!shear) {
+        const double2 w0 = sWF[li];
+        v = L[0] * w0.x;
+        g = L[0] * w0.y;
+        unroll<NV - 1>([&](auto cc) {
+          const double2 w = sWF[(cc + 1) * NCT + li];
+          v = fma(L[cc + 1], w.x, v);
+          g = fma(L[cc + 1], w.y, g);
+        });
+      } else {
+        const double2 w0 = sWF[li];
+        const double2 ws = sWF[sl * NCT + li];
+        v = mut * w0.x + ws.x;
+        g = mut * w0.y + ws.y;
+      }
+      gp[j] = 0.5 * fma(alpha, v, g);
+      gm[W - 1 - j] = 0.5 * fma(-alpha, v, g);  // mirrored for the - side
+#if TENOAA_CELL_BARRIER
+      __builtin_amdgcn_sched_barrier(0);
+#endif
+    });
+    uint8_t flp = 0, flm = 0;
+    double hp, hm;
+    if (frozen) {
+      // replay recorded decisions
+      flp = frozen[(int64_t)(s * 2 + 0) * A.nft];
+      flm = frozen[(int64_t)(s * 2 + 1) * A.nft];
+      hp = replay_recon<ORDER>(gp, flp);
+      hm = replay_recon<ORDER>(gm, flm);
+    } else {
+      hp = teno_aa<ORDER>(gp, flp);
+      // keep the two reconstructions from being interleaved (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
+      hm = teno_aa<ORDER>(gm, flm);
+    }
+    if (flag_out) {
+      flag_out[(int64_t)(s * 2 + 0) * A.nft] = flp;
+      flag_out[(int64_t)(s * 2 + 1) * A.nft] = flm;
+    }
+    const double fh = hp + hm;
+    if (A.fh_out) A.fh_out[(int64_t)s * A.nft + flin] = fh;
+    // back-projection F = sum_s R[:, s] fh_s, accumulated over s in order
+    double r1 = 0.0, re = 0.0;
+    if (s == 0) {
+      r1 = un - cr;
+      re = Hr - un * cr;
+    } else if (s == NV - 1) {
+      r1 = un + cr;
+      re = Hr + un * cr;
+    } else if (s == 1) {
+      r1 = un;
+      re = qq;
+    } else {
+      if constexpr (NDIM == 3) re = (s == 3) ? ut[1] : ut[0];
+      else if constexpr (NDIM == 2) re = ut[0];
+    }
+    const double r0 = shear ? 0.0 : 1.0;
+    if (s == 0) {
+      Fh[0] = r0 * fh;
+      Fh[1] = r1 * fh;
+      unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = ut[k] * fh; });
+      Fh[NV - 1] = re * fh;
+    } else {
+      Fh[0] = fma(r0, fh, Fh[0]);
+      Fh[1] = fma(r1, fh, Fh[1]);
+      unroll<NDIM - 1>([&](auto k) {
+        const double rk = shear ? (s == 2 + (int)k ? 1.0 : 0.0) : ut[k];
+        Fh[2 + k] = fma(rk, fh, Fh[2 + k]);
+      });
+      Fh[NV - 1] = fma(re, fh, Fh[NV - 1]);
+    }
+  }
+
+  if constexpr (LIMIT) {
+    // Positivity limiter (reading of Hu, Adams & Shu 2013, applied in Sec. 5.3).
+    const double sA = fabs(sUn[ia]) + sC[ia];
+    const double sB = fabs(sUn[ib]) + sC[ib];
+    const double aL = (sA >= sB) ? sA : sB;
+    double FL[NV];
+    unroll<NV>([&](auto c) {
+      const double2 wa = sWF[c * NCT + ia], wb = sWF[c * NCT + ib];
+      FL[c] = 0.5 * ((wa.y + wb.y) - aL * (wb.x - wa.x));
+    });
+    auto pressure = [&](const double (&X)[NV]) {
+      const double rho = X[0];
+      double q = 0.0;
+      unroll<NDIM>([&](auto a) {
+        const double ua = X[1 + Fr::slot_of_axis(decltype(a)::value)] / rho;
+        q = (a == 0) ? ua * ua : q + ua * ua;
+      });
+      return gm1 * (X[NV - 1] - (0.5 * rho) * q);
+    };
+    double th_r = 1.0;
+    unroll<2>([&](auto side) {
+      const int li = side == 0 ? ia : ib;
+      const double sg = side == 0 ? -1.0 : 1.0;
+      const double r = sWF[li].x;
+      const double rL = r + (sg * mu) * FL[0];
+      const double rH = r + (sg * mu) * Fh[0];
+      const double eps = rL < 1e-13 ? rL : 1e-13;
+      const double th = (rH < eps) ? (rL - eps) / (rL - rH) : 1.0;
+      th_r = th < th_r ? th : th_r;
+    });
+    double Fs[NV];
+    unroll<NV>([&](auto c) { Fs[c] = (th_r < 1.0) ? FL[c] + th_r * (Fh[c] - FL[c]) : Fh[c]; });
+    double th_p = 1.0;
+    unroll<2>([&](auto side) {
+      const int li = side == 0 ? ia : ib;
+      const double sg = side == 0 ? -1.0 : 1.0;
+      double X[NV];
+      unroll<NV>([&](auto c) { X[c] = sWF[c * NCT + li].x + (sg * mu) * FL[c]; });
+      const double pL = pressure(X);
+      unroll<NV>([&](auto c) { X[c] = sWF[c * NCT + li].x + (sg * mu) * Fs[c]; });
+      const double pS = pressure(X);
+      const double eps = pL < 1e-13 ? pL : 1e-13;
+      const double th = (pS < eps) ? (pL - eps) / (pL - pS) : 1.0;
+      th_p = th < th_p ? th : th_p;
+    });
+    unroll<NV>([&](auto c) { Fh[c] = (th_p < 1.0) ? FL[c] + th_p * (Fs[c] - FL[c]) : Fs[c]; });
+  } else {
+    (void)mu;
+  }
+
+  // store in axis order
+  A.F[flin] = Fh[0];
+  A.F[(int64_t)(NV - 1) * A.nft + flin] = Fh[NV - 1];
+  unroll<NDIM>([&](auto a) {
+    constexpr int slot = Fr::slot_of_axis(decltype(a)::value);
+    A.F[(int64_t)(1 + a) * A.nft + flin] = Fh[1 + slot];
+  });
+}
+
+// |u_d| + c of one cell (state Wc, conserved, axis order) folded into amax;
+// `bad` is set for a non-physical state.
+template <int NDIM>
+__device__ __forceinline__ void cell_speeds(const double (&Wc)[NDIM + 2], double gam, double (&amax)[NDIM],
+                                            bool& bad) {
+  constexpr int NV = NDIM + 2;
+  const double rho = Wc[0];
+  double u[NDIM];
+  double q2 = 0.0;
+  unroll<NDIM>([&](auto k) {
+    u[k] = Wc[1 + k] / rho;
+    q2 = (k == 0) ? u[0] * u[0] : q2 + u[k] * u[k];
+  });
+  const double p = (gam - 1.0) * (Wc[NV - 1] - (0.5 * rho) * q2);
+  const double c = sqrt((gam * p) / rho);
+  if (!(rho > 0.0) || !(p > 0.0)) bad = true;
+  unroll<NDIM>([&](auto d) { amax[d] = dmax(amax[d], fabs(u[d]) + c); });
+}
+
+// Flux difference and SSP-RK3 stage of cell idx (MODE 0: dU/dt; 1-3: stage).
+// The new state of the cell is left in Wn.
+template <int NDIM, int MODE>
+__device__ __forceinline__ void update_cell(const UpdateArgs& A, int64_t idx, double dt, double (&Wn)[NDIM + 2]) {
+  constexpr int NV = NDIM + 2;
+  const int64_t ncell = A.n[0] * A.n[1] * A.n[2];
+  int64_t co[3];
+  co[0] = idx % A.n[0];
+  co[1] = (idx / A.n[0]) % A.n[1];
+  co[2] = idx / (A.n[0] * A.n[1]);
+  int64_t fl[3], fr[3];
+  unroll<NDIM>([&](auto d) {
+    int64_t m[3] = {A.n[0], A.n[1], A.n[2]};
+    m[d] = A.nf[d];
+    const int64_t fs[3] = {1, m[0], m[0] * m[1]};
+    int64_t c2[3] = {co[0], co[1], co[2]};
+    fl[d] = c2[0] * fs[0] + c2[1] * fs[1] + c2[2] * fs[2];
+    int64_t r = co[d] + 1;
+    if (r == A.nf[d]) r = 0;  // periodic wrap (nf == n)
+    c2[d] = r;
+    fr[d] = c2[0] * fs[0] + c2[1] * fs[1] + c2[2] * fs[2];
+  });
+  unroll<NV>([&](auto c) {
+    double du = 0.0;
+    unroll<NDIM>([&](auto d) {
+      const double* F = A.F[d] + (int64_t)c * A.nft[d];
+      du = du - (F[fr[d]] - F[fl[d]]) / A.dx[d];
+    });
+    const int64_t e = (int64_t)c * ncell + idx;
+    double v;
+    if (MODE == 0) {
+      v = du;
+    } else if (MODE == 1) {
+      v = A.Un[e] + dt * du;
+    } else if (MODE == 2) {
+      v = 0.75 * A.Un[e] + 0.25 * A.Us[e] + (0.25 * dt) * du;
+    } else {
+      v = (1.0 / 3.0) * A.Un[e] + (2.0 / 3.0) * A.Us[e] + ((2.0 / 3.0) * dt) * du;
+    }
+    A.out[e] = v;
+    Wn[c] = v;
+  });
+}
+
+// dt = cfl / sum_d a_d/dx_d (reading of the multi-dimensional CFL condition)
+// unless dt_given > 0; limiter factors mu_d = 2 S / a_d with
+// S = sum_d (dt/dx_d) a_d.
+__device__ __forceinline__ void dt_and_mu(const unsigned long long* amax_bits, int ndim, const double* dx,
+                                          double cfl, double dt_given, double& dt, double* mu) {
+  double a[3];
+  for (int d = 0; d < 3; ++d) a[d] = d < ndim ? __longlong_as_double((long long)amax_bits[d]) : 0.0;
+  dt = dt_given;
+  if (!(dt > 0.0)) {
+    double s = a[0] / dx[0];
+    for (int d = 1; d < ndim; ++d) s = s + a[d] / dx[d];
+    dt = cfl / s;
+  }
+  double Ssum = (dt / dx[0]) * a[0];
+  for (int d = 1; d < ndim; ++d) Ssum = Ssum + (dt / dx[d]) * a[d];
+  for (int d = 0; d < 3; ++d) mu[d] = (d < ndim) ? (2.0 * Ssum) / a[d] : 0.0;
+}
+
+}  // namespace
+}  // namespace tenoaa

@@ -11,6 +11,10 @@ Workloads (cell centres at (i + 1/2) dx on the unit interval/square/cube):
 * ``shock_tube_1d`` - left/right constant states (rho, u, p) drawn from
   U[0.1, 4] x U[-1, 1] x U[0.1, 4], jump at x0 ~ U[0.3, 0.7], the right state's
   density multiplied by (1 + 0.2 sin(5 pi x)) so it stays positive.
+* ``batch_sizes`` / ``riemann_2d`` - the batched workload: side lengths
+  n_x, n_y ~ U{64..512} independently per problem, and per problem a planar
+  jump in x between two constant states drawn like the shock tube's, with a
+  transverse velocity v ~ U[-1, 1] per side (outflow boundaries).
 * ``grf_2d`` / ``grf_3d`` - Gaussian random fields (integer wave-vectors with
   1 <= |k| <= 32, shell-summed spectrum ~ k^-2) mapped affinely to [0.5, 2]
   for rho and p; velocity components are independent fields of the same
@@ -103,6 +107,29 @@ def grf_2d(n=1024, gamma=1.4, seed=SEED_BASE + 2, jump=True):
         inside = (X - 0.5) ** 2 + (Y - 0.5) ** 2 < 0.2 ** 2
         p = np.where(inside, 10.0 * p, p)
     return _as_layout(conserved_from_primitive(rho, vel, p, gamma), 2)
+
+
+def batch_sizes(nprob=512, seed=SEED_BASE + 4, lo=64, hi=512):
+    """Side lengths (n_x, n_y) of the batched workload's problems."""
+    rng = np.random.default_rng(seed)
+    return [(int(a), int(b)) for a, b in rng.integers(lo, hi + 1, size=(nprob, 2))]
+
+
+def riemann_2d(nx, ny, index, gamma=1.4, seed=SEED_BASE + 4):
+    """Problem `index` of the batched workload on an nx x ny grid."""
+    rng = np.random.default_rng([seed, index])
+    rl, rr = rng.uniform(0.1, 4.0, 2)
+    ul, ur = rng.uniform(-1.0, 1.0, 2)
+    vl, vr = rng.uniform(-1.0, 1.0, 2)
+    pl, pr = rng.uniform(0.1, 4.0, 2)
+    x0 = rng.uniform(0.3, 0.7)
+    x = cell_centres(nx)[:, None] * np.ones((1, ny))
+    left = x < x0
+    rho = np.where(left, rl, rr * (1.0 + 0.2 * np.sin(5.0 * np.pi * x)))
+    u = np.where(left, ul, ur)
+    v = np.where(left, vl, vr)
+    p = np.where(left, pl, pr)
+    return _as_layout(conserved_from_primitive(rho, [u, v], p, gamma), 2)
 
 
 def grf_3d(n=256, gamma=1.4, seed=SEED_BASE + 3, spheres=True):

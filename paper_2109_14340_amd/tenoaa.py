@@ -16,11 +16,13 @@ LIB_PATH = os.path.join(HERE, "libtenoaa.so")
 BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP = 0, 1, 2, 3
 LLF, RUSANOV = 0, 1
 WS_RHS, WS_STEP, WS_RHS_VJP, WS_STEP_VJP = 0, 1, 2, 3
-ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENONPHYSICAL", -5: "EWORKSPACE"}
+ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENONPHYSICAL", -5: "EWORKSPACE", -6: "ETIMEOUT"}
 
 FLAGS_NONE, FLAGS_RECORD, FLAGS_REPLAY = 0, 1, 2
 EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_step_flags", "tenoaa_rhs_vjp", "tenoaa_step_vjp",
-           "tenoaa_get_status", "tenoaa_last_hip_error", "tenoaa_timing_enable", "tenoaa_timing_read"]
+           "tenoaa_get_status", "tenoaa_last_hip_error", "tenoaa_timing_enable", "tenoaa_timing_read",
+           "tenoaa_batch_plan_create", "tenoaa_batch_offsets", "tenoaa_batch_run", "tenoaa_batch_get_status",
+           "tenoaa_batch_plan_info", "tenoaa_batch_plan_destroy"]
 KCLASS_SWEEP = (0, 1, 2)
 KCLASS_UPDATE, KCLASS_WAVESPEED = 3, 4
 KCLASS_VJP = (5, 6, 7)
@@ -74,6 +76,19 @@ def load():
         L.tenoaa_timing_read.restype = ctypes.c_int
         L.tenoaa_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_double)]
+        L.tenoaa_batch_plan_create.restype = ctypes.c_int
+        L.tenoaa_batch_plan_create.argtypes = [gp, ctypes.c_int32, sp, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(vp)]
+        L.tenoaa_batch_offsets.restype = ctypes.c_int
+        L.tenoaa_batch_offsets.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.tenoaa_batch_run.restype = ctypes.c_int
+        L.tenoaa_batch_run.argtypes = [vp, vp, vp, vp]
+        L.tenoaa_batch_get_status.restype = ctypes.c_int
+        L.tenoaa_batch_get_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
+        L.tenoaa_batch_plan_info.restype = ctypes.c_int
+        L.tenoaa_batch_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+        L.tenoaa_batch_plan_destroy.restype = ctypes.c_int
+        L.tenoaa_batch_plan_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -238,6 +253,88 @@ def timing_read(kclass):
     ms = ctypes.c_double(0.0)
     _check(load().tenoaa_timing_read(kclass, ctypes.byref(n), ctypes.byref(ms)), "tenoaa_timing_read")
     return int(n.value), float(ms.value)
+
+
+class BatchPlan:
+    """A tenoaa_batch_plan: nprob independent 2D grids (tenoaa Grid structs,
+    ndim 2) advanced together by `nsteps` SSP-RK3 steps per run."""
+
+    def __init__(self, grids, scheme, nsteps, gamma=1.4, cfl=0.4, tune_cache=None):
+        L = load()
+        self.nprob = len(grids)
+        arr = (Grid * self.nprob)(*grids)
+        self._grids = arr
+        self.nsteps = nsteps
+        h = ctypes.c_void_p(None)
+        path = tune_cache.encode() if tune_cache else None
+        rc = L.tenoaa_batch_plan_create(arr, self.nprob, ctypes.byref(scheme), gamma, cfl, nsteps, path,
+                                        ctypes.byref(h))
+        _check(rc, "tenoaa_batch_plan_create")
+        self._h = h
+        offs = (ctypes.c_int64 * (self.nprob + 1))()
+        _check(L.tenoaa_batch_offsets(h, offs), "tenoaa_batch_offsets")
+        self.offsets = [int(o) for o in offs]
+
+    def info(self):
+        """(blocks, blocks per CU, chunk, how chosen, x tiles per bucket, y tiles per bucket)."""
+        buf = (ctypes.c_int32 * 10)()
+        _check(load().tenoaa_batch_plan_info(self._h, buf, 10), "tenoaa_batch_plan_info")
+        v = list(buf)
+        return {"blocks": v[0], "blocks_per_cu": v[1], "chunk": v[2], "chosen": ("defaults", "tuned", "cache")[v[3]],
+                "tile_x": v[4:7], "tile_y": v[7:10]}
+
+    def pack(self, states, device="cuda"):
+        """Packed float64 device tensor of the problems' (4, 1, ny, nx) states."""
+        import torch
+        out = torch.empty(self.offsets[-1], dtype=torch.float64, device=device)
+        for p, U in enumerate(states):
+            t = U if isinstance(U, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(U))
+            out[self.offsets[p]:self.offsets[p + 1]].copy_(t.reshape(-1))
+        return out
+
+    def unpack(self, packed, p):
+        g = self._grids[p]
+        return packed[self.offsets[p]:self.offsets[p + 1]].view(4, 1, g.n[1], g.n[0])
+
+    def run(self, packed, dt_out=None):
+        """Advances every problem in place on torch's current stream; dt_out:
+        optional float64 device tensor of nprob * nsteps."""
+        import torch
+        if packed.dtype != torch.float64 or not packed.is_cuda or packed.numel() != self.offsets[-1]:
+            raise TenoaaError("packed state must be float64 on the device with %d elements" % self.offsets[-1])
+        if dt_out is not None and (dt_out.dtype != torch.float64 or dt_out.numel() != self.nprob * self.nsteps):
+            raise TenoaaError("dt_out must be float64 with nprob * nsteps elements")
+        _check(load().tenoaa_batch_run(self._h, _ptr(packed), _ptr(dt_out), _stream()), "tenoaa_batch_run")
+        return packed
+
+    def status(self):
+        """Synchronises; per-problem non-physical flags (list of 0/1)."""
+        out = (ctypes.c_int32 * self.nprob)()
+        rc = load().tenoaa_batch_get_status(self._h, _stream(), out)
+        if rc not in (0, -4):
+            _check(rc, "tenoaa_batch_get_status")
+        return list(out)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().tenoaa_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_cache_key(scheme, grids):
+    """Key under which tenoaa_batch_plan_create files its tuned choices."""
+    cnt = [0, 0, 0]
+    for g in grids:
+        nx = g.n[0]
+        cnt[0 if nx <= 160 else (1 if nx <= 320 else 2)] += 1
+    return "gfx950 order=%d split=%d limit=%d buckets=%d,%d,%d" % (scheme.order, scheme.splitting,
+                                                                   scheme.positivity, *cnt)
 
 
 def grid_for(U, bc=None, dx=None):

@@ -92,3 +92,40 @@ def test_bad_call_arguments_rejected():
     need_r = L.tenoaa_workspace_bytes(ctypes.byref(g), ctypes.byref(s), 0)
     assert L.tenoaa_rhs(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(256), 0.0, None, vp(1024), need_r,
                         None) == -1
+
+
+def test_batch_plan_rejects_bad_arguments():
+    """Every check of tenoaa_batch_plan_create happens before any HIP call."""
+    L = _lib()
+    vp = ctypes.c_void_p
+    s = tenoaa.make_scheme(8)
+    good = [tenoaa.make_grid((64, 80), bc_lo=[1, 1]), tenoaa.make_grid((96, 64), bc_lo=[1, 1])]
+
+    def create(grids, nprob=None, scheme=s, gamma=1.4, cfl=0.4, nsteps=3):
+        arr = (tenoaa.Grid * len(grids))(*grids) if grids else None
+        h = vp(None)
+        rc = L.tenoaa_batch_plan_create(arr, len(grids) if nprob is None else nprob, ctypes.byref(scheme), gamma,
+                                        cfl, nsteps, None, ctypes.byref(h))
+        assert h.value is None
+        return rc
+
+    assert create(good, nprob=0) == -1
+    assert create([], nprob=2) == -1  # null grid array
+    assert create(good, nsteps=0) == -1
+    assert create(good, gamma=1.0) == -1
+    assert create(good, cfl=1.5) == -1
+    lim = tenoaa.make_scheme(8, positivity=1)
+    assert create(good, scheme=lim, cfl=0.6) == -1
+    assert create(good + [tenoaa.make_grid((3, 64))]) == -1  # n < G
+    assert create(good + [tenoaa.make_grid((64,))]) == -2  # 1D grid: not a batched form
+    assert create(good + [tenoaa.make_grid((16, 16, 16))]) == -2
+    assert L.tenoaa_batch_run(None, vp(256), None, None) == -1
+    assert L.tenoaa_batch_get_status(None, None, None) == -1
+    assert L.tenoaa_batch_plan_info(None, None, 10) == -1
+    assert L.tenoaa_batch_plan_destroy(None) == -1
+
+
+def test_batch_cache_key_buckets():
+    s = tenoaa.make_scheme(8)
+    grids = [tenoaa.make_grid((n, 64)) for n in (64, 160, 161, 320, 321, 512)]
+    assert tenoaa.batch_cache_key(s, grids) == "gfx950 order=8 split=0 limit=0 buckets=2,2,2"
