@@ -88,6 +88,76 @@ def fwd_adj_leg(shape, steps, warmup, U0):
                     "copy of the input state is inside fwd_ms"}
 
 
+def batched_leg(nprob=512, nsteps=20, tune_cache=None):
+    """The batched workload: nprob 2D problems with n_x, n_y ~ U{64..512},
+    TENO8-AA, LLF, outflow, nsteps SSP-RK3 steps each with its own dt, in one
+    persistent graph launch; against the same steps launched per problem."""
+    import tempfile
+
+    import torch
+
+    from paper_2109_14340_amd import inputs, tenoaa
+
+    sizes = inputs.batch_sizes(nprob)
+    sch = tenoaa.make_scheme(8, tenoaa.LLF, 0)
+    bc = [tenoaa.BC_OUTFLOW, tenoaa.BC_OUTFLOW]
+    grids = [tenoaa.make_grid((nx, ny), bc_lo=bc, bc_hi=bc) for nx, ny in sizes]
+    states = [inputs.riemann_2d(nx, ny, p) for p, (nx, ny) in enumerate(sizes)]
+    faces = sum((nx + 1) * ny + (ny + 1) * nx for nx, ny in sizes) * 3 * nsteps
+    path = tune_cache or os.path.join(tempfile.mkdtemp(prefix="tenoaa_tune_"), "tune.jsonl")
+    t0 = time.perf_counter()
+    plan = tenoaa.BatchPlan(grids, sch, nsteps, tune_cache=path)
+    t_plan = time.perf_counter() - t0
+    packed0 = plan.pack(states)
+    packed = packed0.clone()
+    dtb = torch.zeros(nprob * nsteps, dtype=torch.float64, device="cuda")
+    plan.run(packed, dtb)  # warm-up
+    reps = 3
+    times = []
+    for _ in range(reps):
+        packed.copy_(packed0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run(packed, dtb)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    if any(plan.status()):
+        raise RuntimeError("non-physical state in the batched run")
+    t_batch = min(times)
+
+    # per problem: the same steps through tenoaa_step, one problem after another;
+    # a plain pass for the wall time, then a pass with per-kernel events
+    wss = [tenoaa.workspace(g, sch, tenoaa.WS_STEP) for g in grids]
+    dts = torch.zeros(nprob * nsteps, dtype=torch.float64, device="cuda")
+
+    def per_problem():
+        Us = [plan.unpack(packed0, p).clone() for p in range(nprob)]
+        dts.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p in range(nprob):
+            for n in range(nsteps):
+                tenoaa.step(grids[p], sch, Us[p], dts[p * nsteps + n:p * nsteps + n + 1], cfl=0.4, ws=wss[p])
+        torch.cuda.synchronize()
+        return Us, time.perf_counter() - t0
+
+    per_problem()  # warm-up
+    Us, t_pp = per_problem()
+    tenoaa.timing_enable(True)
+    per_problem()
+    ksum = 0.0
+    for k in range(8):
+        ksum += tenoaa.timing_read(k)[1]
+    tenoaa.timing_enable(False)
+    same = all(torch.equal(plan.unpack(packed, p), Us[p]) for p in range(nprob)) and torch.equal(dts, dtb)
+    return {"problems": nprob, "steps": nsteps, "cells": sum(nx * ny for nx, ny in sizes),
+            "face_recons": faces, "batched_ms": round(t_batch * 1e3, 2),
+            "value": round(faces / t_batch / 1e9, 4), "unit": "Gface-recon/s",
+            "per_problem_wall_ms": round(t_pp * 1e3, 2), "per_problem_kernel_sum_ms": round(ksum, 2),
+            "speedup_vs_wall": round(t_pp / t_batch, 3), "speedup_vs_kernel_sum": round(ksum / 1e3 / t_batch, 3),
+            "bitwise_equal_to_per_problem": bool(same), "plan": plan.info(), "plan_create_s": round(t_plan, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +166,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fwd-adj", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--tune-cache", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -189,6 +261,8 @@ def main():
         line["fwd_adj"] = {"3d": fwd_adj_leg((n, n, n), 3, 1, U3),
                            "2d_512_periodic": fwd_adj_leg((512, 512), 20, 3, U2)}
         del U3, U2
+    if not args.no_batched:
+        line["batched"] = batched_leg(tune_cache=args.tune_cache)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
