@@ -47,38 +47,47 @@
 namespace tenoaa {
 namespace {
 
-// Derivative of the frozen reconstruction chosen by `flag` with respect to
-// the window values f_{-G+1..G} (w[q] = d fhat / d v[q]).
+// Derivatives of the frozen reconstructions with respect to the window values
+// f_{-G+1..G}: one row per outcome of the cascade.  Rows 0-7: the TENO5
+// fallback with delta mask 0-7 (weights d_k delta_k / sum, Sec. 3.3, times the
+// three third-order candidates); rows 8, 9, 10: the linear schemes on S3, S4,
+// S5 (Sec. 4.1).
+constexpr int NROW = 11;
 template <int ORDER>
-__device__ __forceinline__ void recon_weights(uint8_t flag, double (&w)[ORDER]) {
+__device__ __forceinline__ double weight_entry(int row, int q) {
   constexpr int G = ORDER / 2;
   constexpr int I = G - 1;
-  unroll<ORDER>([&](auto q) { w[q] = 0.0; });
-  const int sel = flag & 3;
-  if (ORDER == 10 && sel == 3) {
-    unroll<10>([&](auto q) {
-      constexpr int qq = decltype(q)::value;
-      if constexpr (qq < ORDER) w[qq] = lin_coef<10>(qq);
-    });
-  } else if (sel == 2) {
+  if (row == 10) return ORDER == 10 ? lin_coef<10>(q) : 0.0;
+  if (row == 9) {
     constexpr int P = (ORDER == 10) ? 1 : 0;
-    unroll<8>([&](auto q) { w[P + q] = lin_coef<8>(q); });
-  } else if (sel == 1) {
-    constexpr int P = (ORDER == 10) ? 2 : 1;
-    unroll<6>([&](auto q) { w[P + q] = lin_coef<6>(q); });
-  } else {
-    const int dm = (flag >> 2) & 7;
-    const double w0 = WFALL.w[dm][0], w1 = WFALL.w[dm][1], w2 = WFALL.w[dm][2];
-    constexpr double s6 = 1.0 / 6.0;
-    w[I - 2] = w2 * (2.0 * s6);
-    w[I - 1] = w0 * (-s6) + w2 * (-7.0 * s6);
-    w[I] = w0 * (5.0 * s6) + w1 * (2.0 * s6) + w2 * (11.0 * s6);
-    w[I + 1] = w0 * (2.0 * s6) + w1 * (5.0 * s6);
-    w[I + 2] = w1 * (-s6);
+    return (q >= P && q < P + 8) ? lin_coef<8>(q - P) : 0.0;
   }
+  if (row == 8) {
+    constexpr int P = (ORDER == 10) ? 2 : 1;
+    return (q >= P && q < P + 6) ? lin_coef<6>(q - P) : 0.0;
+  }
+  const double w0 = WFALL.w[row][0], w1 = WFALL.w[row][1], w2 = WFALL.w[row][2];
+  constexpr double s6 = 1.0 / 6.0;
+  if (q == I - 2) return w2 * (2.0 * s6);
+  if (q == I - 1) return w0 * (-s6) + w2 * (-7.0 * s6);
+  if (q == I) return w0 * (5.0 * s6) + w1 * (2.0 * s6) + w2 * (11.0 * s6);
+  if (q == I + 1) return w0 * (2.0 * s6) + w1 * (5.0 * s6);
+  if (q == I + 2) return w1 * (-s6);
+  return 0.0;
+}
+
+// Row of the weight table selected by a decision byte.
+__device__ __forceinline__ int weight_row(uint8_t flag) {
+  const int sel = flag & 3;
+  return sel == 0 ? (flag >> 2) & 7 : 7 + sel;
 }
 
 __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
+
+// Materialises x in a register here: keeps the compiler from sinking the
+// accumulations of a window cell past the next cell (which would keep every
+// cell's operands alive until the end of the window).
+__device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
 
 template <int ORDER, int NDIM, int DIR, int TT, int TN>
 __global__ __launch_bounds__(TT* TN)
@@ -104,6 +113,9 @@ void sweep_vjp_kernel(AdjointArgs A) {
   // adjoint accumulators per tile cell: conserved state, physical flux,
   // velocity (local slots: 0 normal, 1.. tangential), sound speed, enthalpy, sqrt(rho)
   __shared__ double aW[NV][NCT], aF[NV][NCT], aU[NDIM][NCT], aC[NCT], aH[NCT], aS[NCT];
+  // derivative weights of the frozen reconstructions, [row][window position]
+  __shared__ double sWT[NROW * W];
+  for (int e = threadIdx.x; e < NROW * W; e += NTH) sWT[e] = weight_entry<ORDER>(e / W, e % W);
 
   const int64_t nN = A.n[DIR];
   const int64_t nA = A.n[AX_A];
@@ -274,162 +286,187 @@ void sweep_vjp_kernel(AdjointArgs A) {
       jm = jp = j0;
     }
 
-    auto left_row = [&](int s, double (&L)[NV]) {
-      unroll<NV>([&](auto c) { L[c] = 0.0; });
-      if (s == 0 || s == NV - 1) {
-        L[0] = (s == 0) ? 0.5 * (b2 + unc) : 0.5 * (b2 - unc);
-        L[1] = (s == 0) ? 0.5 * (-b1 * un - ic) : 0.5 * (-b1 * un + ic);
-        unroll<NDIM - 1>([&](auto k) { L[2 + k] = 0.5 * (-b1 * ut[k]); });
-        L[NV - 1] = 0.5 * b1;
-      } else if (s == 1) {
-        L[0] = 1.0 - b2;
-        L[1] = b1 * un;
-        unroll<NDIM - 1>([&](auto k) { L[2 + k] = b1 * ut[k]; });
-        L[NV - 1] = -b1;
-      } else {
-        if constexpr (NDIM >= 2) {
-          const double utk = (NDIM == 3 && s == 3) ? ut[NT - 1] : ut[0];
-          L[0] = -utk;
-          unroll<NV>([&](auto c) {
-            if (c == s) L[c] = 1.0;
-          });
-        }
-      }
-    };
-    auto right_col = [&](int s, double (&Rc)[NV]) {
-      unroll<NV>([&](auto c) { Rc[c] = 0.0; });
-      if (s == 0 || s == 1 || s == NV - 1) {
-        Rc[0] = 1.0;
-        Rc[1] = (s == 0) ? un - cr : (s == 1 ? un : un + cr);
-        unroll<NDIM - 1>([&](auto k) { Rc[2 + k] = ut[k]; });
-        Rc[NV - 1] = (s == 0) ? Hr - un * cr : (s == 1 ? qq : Hr + un * cr);
-      } else {
-        if constexpr (NDIM >= 2) {
-          unroll<NV>([&](auto c) {
-            if (c == s) Rc[c] = 1.0;
-          });
-          Rc[NV - 1] = (NDIM == 3 && s == 3) ? ut[NT - 1] : ut[0];
-        }
-      }
-    };
-    auto project = [&](const double (&L)[NV], int j, double& v, double& g) {
-      const int li = lbase + j * LSTEP;
-      const double2 w0 = sWF[0][li];
-      v = L[0] * w0.x;
-      g = L[0] * w0.y;
-      unroll<NV - 1>([&](auto cc) {
-        const double2 w = sWF[cc + 1][li];
-        v = fma(L[cc + 1], w.x, v);
-        g = fma(L[cc + 1], w.y, g);
-      });
-    };
-
     // ---- reverse pass
     double un_b = 0.0, Hr_b = 0.0, qq_b = 0.0, cr_b = 0.0, b1_b = 0.0, b2_b = 0.0, unc_b = 0.0, ic_b = 0.0;
     double ut_b[NT];
     unroll<NT>([&](auto k) { ut_b[k] = 0.0; });
-#pragma unroll 1
-    for (int s = 0; s < NV; ++s) {
+
+    // back-projection F = sum_s R[:, s] fh_s: adjoints of fh_s and of R's entries
+    double fhb[NV];
+    unroll<NV>([&](auto ss) {
+      constexpr int s = decltype(ss)::value;
+      constexpr bool shear = (s >= 2 && s <= NV - 2);
       const double fh = A.fh[(int64_t)s * A.nft + flin];
-      // back-projection F = sum_s R[:, s] fh_s
-      double Rc[NV];
-      right_col(s, Rc);
-      double fh_b = 0.0;
-      unroll<NV>([&](auto c) { fh_b = fma(Rc[c], Fb[c], fh_b); });
-      // adjoints of the R entries (column s)
-      if (s == 0 || s == 1 || s == NV - 1) {
-        const double r1 = Fb[1] * fh, re = Fb[NV - 1] * fh;
+      if constexpr (!shear) {
+        const double r1 = (s == 0) ? un - cr : (s == 1 ? un : un + cr);
+        const double re = (s == 0) ? Hr - un * cr : (s == 1 ? qq : Hr + un * cr);
+        double acc = Fb[0];
+        acc = fma(r1, Fb[1], acc);
+        unroll<NDIM - 1>([&](auto k) { acc = fma(ut[k], Fb[2 + k], acc); });
+        fhb[s] = fma(re, Fb[NV - 1], acc);
+        const double r1b = Fb[1] * fh, reb = Fb[NV - 1] * fh;
         unroll<NDIM - 1>([&](auto k) { ut_b[k] += Fb[2 + k] * fh; });
-        if (s == 0) {
-          un_b += r1 - cr * re;
-          cr_b += -r1 - un * re;
-          Hr_b += re;
-        } else if (s == 1) {
-          un_b += r1;
-          qq_b += re;
+        if constexpr (s == 0) {
+          un_b += r1b - cr * reb;
+          cr_b += -r1b - un * reb;
+          Hr_b += reb;
+        } else if constexpr (s == 1) {
+          un_b += r1b;
+          qq_b += reb;
         } else {
-          un_b += r1 + cr * re;
-          cr_b += r1 + un * re;
-          Hr_b += re;
+          un_b += r1b + cr * reb;
+          cr_b += r1b + un * reb;
+          Hr_b += reb;
         }
       } else {
-        const double re = Fb[NV - 1] * fh;
-        if (NDIM == 3 && s == 3) ut_b[NT - 1] += re;
-        else ut_b[0] += re;
+        fhb[s] = fma(ut[s - 2], Fb[NV - 1], Fb[s]);
+        ut_b[s - 2] += Fb[NV - 1] * fh;
       }
-      // reconstructions with frozen weights
-      double wp[W], wm[W];
-      recon_weights<ORDER>(A.flags[(int64_t)(2 * s) * A.nft + flin], wp);
-      recon_weights<ORDER>(A.flags[(int64_t)(2 * s + 1) * A.nft + flin], wm);
-      double L[NV];
-      left_row(s, L);
-      const double alpha = (s == 0) ? am : (s == NV - 1 ? ap : a0);
-      const int jstar = (s == 0) ? jm : (s == NV - 1 ? jp : j0);
-      double alpha_b = 0.0;
-      double Lb[NV];
-      unroll<NV>([&](auto c) { Lb[c] = 0.0; });
-      unroll<W>([&](auto j) {
+    });
+
+    // left eigenvector rows: full rows for the acoustic and entropy fields
+    // (local slots 0, 1, NV-1 -> rows 0, 1, 2 here), -u_t + e_s for the shear fields
+    double L[3][NV];
+    unroll<2>([&](auto side) {
+      constexpr int r = side == 0 ? 0 : 2;
+      const double sg = side == 0 ? 1.0 : -1.0;
+      L[r][0] = 0.5 * (b2 + sg * unc);
+      L[r][1] = 0.5 * (-b1 * un - sg * ic);
+      unroll<NDIM - 1>([&](auto k) { L[r][2 + k] = 0.5 * (-b1 * ut[k]); });
+      L[r][NV - 1] = 0.5 * b1;
+    });
+    L[1][0] = 1.0 - b2;
+    L[1][1] = b1 * un;
+    unroll<NDIM - 1>([&](auto k) { L[1][2 + k] = b1 * ut[k]; });
+    L[1][NV - 1] = -b1;
+    // frozen reconstructions: row of the weight table per field and side
+    int rowp[NV], rowm[NV];
+    unroll<NV>([&](auto ss) {
+      constexpr int s = decltype(ss)::value;
+      rowp[s] = weight_row(A.flags[(int64_t)(2 * s) * A.nft + flin]);
+      rowm[s] = weight_row(A.flags[(int64_t)(2 * s + 1) * A.nft + flin]);
+    });
+    double Lb[3][NV], Lbs[NT];
+    unroll<3>([&](auto r) { unroll<NV>([&](auto c) { Lb[r][c] = 0.0; }); });
+    unroll<NT>([&](auto k) { Lbs[k] = 0.0; });
+    double am_b = 0.0, a0_b = 0.0, ap_b = 0.0;
+
+    unroll<W>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      const int li = lbase + j * LSTEP;
+      double2 w[NV];
+      unroll<NV>([&](auto c) { w[c] = sWF[c][li]; });
+      double vb[NV], gb[NV];
+      unroll<NV>([&](auto ss) {
+        constexpr int s = decltype(ss)::value;
+        constexpr bool shear = (s >= 2 && s <= NV - 2);
+        constexpr int r = (s == 0) ? 0 : (s == 1 ? 1 : 2);
         double v, g;
-        project(L, j, v, g);
-        const double gpb = wp[j] * fh_b;
-        const double gmb = wm[W - 1 - j] * fh_b;
-        const double g_b = 0.5 * (gpb + gmb);
-        const double v_b = 0.5 * alpha * (gpb - gmb);
-        alpha_b += 0.5 * v * (gpb - gmb);
-        const int li = lbase + j * LSTEP;
-        unroll<NV>([&](auto c) {
-          const double2 w = sWF[c][li];
-          Lb[c] = fma(v_b, w.x, fma(g_b, w.y, Lb[c]));
-          if (L[c] != 0.0) {
-            lds_add(&aW[c][li], L[c] * v_b);
-            lds_add(&aF[c][li], L[c] * g_b);
-          }
-        });
-        __builtin_amdgcn_sched_barrier(0);
-      });
-      // splitting speed: frozen argmax cell and sign
-      {
-        const int li = lbase + jstar * LSTEP;
-        const double u = sUn[li], c = sC[li];
-        if (A.splitting == TENOAA_LLF) {
-          const double lam = (s == 0) ? u - c : (s == NV - 1 ? u + c : u);
-          const double sg = lam < 0.0 ? -1.0 : 1.0;
-          lds_add(&aU[0][li], sg * alpha_b);
-          if (s == 0) lds_add(&aC[li], -sg * alpha_b);
-          if (s == NV - 1) lds_add(&aC[li], sg * alpha_b);
+        if constexpr (!shear) {
+          v = L[r][0] * w[0].x;
+          g = L[r][0] * w[0].y;
+          unroll<NV - 1>([&](auto cc) {
+            v = fma(L[r][cc + 1], w[cc + 1].x, v);
+            g = fma(L[r][cc + 1], w[cc + 1].y, g);
+          });
         } else {
-          const double sg = u < 0.0 ? -1.0 : 1.0;
-          lds_add(&aU[0][li], sg * alpha_b);
-          lds_add(&aC[li], alpha_b);
+          v = fma(-ut[s - 2], w[0].x, w[s].x);
+          g = fma(-ut[s - 2], w[0].y, w[s].y);
         }
+        const double cp = sWT[rowp[s] * W + j] * fhb[s];
+        const double cm = sWT[rowm[s] * W + (W - 1 - j)] * fhb[s];
+        const double alpha = (s == 0) ? am : (s == NV - 1 ? ap : a0);
+        const double d = cp - cm;
+        vb[s] = (0.5 * alpha) * d;
+        gb[s] = 0.5 * (cp + cm);
+        const double ab = (0.5 * v) * d;
+        if constexpr (s == 0) am_b += ab;
+        else if constexpr (s == NV - 1) ap_b += ab;
+        else a0_b += ab;
+        if constexpr (!shear) {
+          unroll<NV>([&](auto c) { Lb[r][c] = fma(vb[s], w[c].x, fma(gb[s], w[c].y, Lb[r][c])); });
+        } else {
+          Lbs[s - 2] = fma(vb[s], w[0].x, fma(gb[s], w[0].y, Lbs[s - 2]));
+        }
+      });
+      // adjoints of this cell's conserved state and flux: L^T (vb, gb)
+      unroll<NV>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        double sw = L[0][c] * vb[0] + L[1][c] * vb[1] + L[2][c] * vb[NV - 1];
+        double sf = L[0][c] * gb[0] + L[1][c] * gb[1] + L[2][c] * gb[NV - 1];
+        if constexpr (c == 0) {
+          unroll<NT>([&](auto k) {
+            if constexpr (NDIM > 1) {
+              sw = fma(-ut[k], vb[2 + k], sw);
+              sf = fma(-ut[k], gb[2 + k], sf);
+            }
+          });
+        } else if constexpr (c >= 2 && c <= NV - 2) {
+          sw += vb[c];
+          sf += gb[c];
+        }
+        lds_add(&aW[c][li], sw);
+        lds_add(&aF[c][li], sf);
+      });
+      unroll<3>([&](auto r) { unroll<NV>([&](auto c) { pin(Lb[r][c]); }); });
+      unroll<NT>([&](auto k) { pin(Lbs[k]); });
+      pin(am_b);
+      pin(a0_b);
+      pin(ap_b);
+      __builtin_amdgcn_sched_barrier(0);
+    });
+
+    // splitting speeds: frozen argmax cells and signs
+    if (A.splitting == TENOAA_LLF) {
+      {
+        const int li = lbase + jm * LSTEP;
+        const double sg = (sUn[li] - sC[li]) < 0.0 ? -1.0 : 1.0;
+        lds_add(&aU[0][li], sg * am_b);
+        lds_add(&aC[li], -sg * am_b);
       }
-      // adjoints of the L entries (row s)
-      if (s == 0 || s == NV - 1) {
-        const double sgn = (s == 0) ? 1.0 : -1.0;
-        b2_b += 0.5 * Lb[0];
-        unc_b += 0.5 * sgn * Lb[0];
-        b1_b += -0.5 * un * Lb[1];
-        un_b += -0.5 * b1 * Lb[1];
-        ic_b += -0.5 * sgn * Lb[1];
-        unroll<NDIM - 1>([&](auto k) {
-          b1_b += -0.5 * ut[k] * Lb[2 + k];
-          ut_b[k] += -0.5 * b1 * Lb[2 + k];
-        });
-        b1_b += 0.5 * Lb[NV - 1];
-      } else if (s == 1) {
-        b2_b -= Lb[0];
-        b1_b += un * Lb[1];
-        un_b += b1 * Lb[1];
-        unroll<NDIM - 1>([&](auto k) {
-          b1_b += ut[k] * Lb[2 + k];
-          ut_b[k] += b1 * Lb[2 + k];
-        });
-        b1_b -= Lb[NV - 1];
-      } else {
-        if (NDIM == 3 && s == 3) ut_b[NT - 1] -= Lb[0];
-        else ut_b[0] -= Lb[0];
+      {
+        const int li = lbase + j0 * LSTEP;
+        const double sg = sUn[li] < 0.0 ? -1.0 : 1.0;
+        lds_add(&aU[0][li], sg * a0_b);
       }
+      {
+        const int li = lbase + jp * LSTEP;
+        const double sg = (sUn[li] + sC[li]) < 0.0 ? -1.0 : 1.0;
+        lds_add(&aU[0][li], sg * ap_b);
+        lds_add(&aC[li], sg * ap_b);
+      }
+    } else {
+      const int li = lbase + j0 * LSTEP;
+      const double sg = sUn[li] < 0.0 ? -1.0 : 1.0;
+      const double tot = (am_b + a0_b) + ap_b;
+      lds_add(&aU[0][li], sg * tot);
+      lds_add(&aC[li], tot);
     }
+
+    // adjoints of the L entries
+    unroll<2>([&](auto side) {
+      constexpr int r = side == 0 ? 0 : 2;
+      const double sgn = side == 0 ? 1.0 : -1.0;
+      b2_b += 0.5 * Lb[r][0];
+      unc_b += 0.5 * sgn * Lb[r][0];
+      b1_b += -0.5 * un * Lb[r][1];
+      un_b += -0.5 * b1 * Lb[r][1];
+      ic_b += -0.5 * sgn * Lb[r][1];
+      unroll<NDIM - 1>([&](auto k) {
+        b1_b += -0.5 * ut[k] * Lb[r][2 + k];
+        ut_b[k] += -0.5 * b1 * Lb[r][2 + k];
+      });
+      b1_b += 0.5 * Lb[r][NV - 1];
+    });
+    b2_b -= Lb[1][0];
+    b1_b += un * Lb[1][1];
+    un_b += b1 * Lb[1][1];
+    unroll<NDIM - 1>([&](auto k) {
+      b1_b += ut[k] * Lb[1][2 + k];
+      ut_b[k] += b1 * Lb[1][2 + k];
+    });
+    b1_b -= Lb[1][NV - 1];
+    unroll<NDIM - 1>([&](auto k) { ut_b[k] -= Lbs[k]; });
 
     // ---- Roe average and eigen-system parameters
     un_b += unc_b / cr;

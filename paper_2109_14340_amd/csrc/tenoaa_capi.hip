@@ -115,8 +115,8 @@ int64_t faces_total(const tenoaa_grid* g, int d) {
 struct Layout {
   size_t scalars;       // offset of tenoaa::Scalars
   size_t fbuf[3];       // face flux arrays per direction
-  size_t vjp_flags;     // one direction's decisions (adjoint calls)
-  size_t vjp_fh;        // one direction's per-field fluxes (adjoint calls)
+  size_t vjp[3][3];     // adjoint calls: [stage][direction] decisions, then per-field fluxes
+  size_t vjp_fh_rel[3]; // offset of a direction's per-field fluxes after its decisions
   size_t stage;         // RK stage state(s)
   size_t state_bytes;   // aligned size of one state
   size_t total;
@@ -133,14 +133,17 @@ Layout layout(const tenoaa_grid* g, int which) {
     L.fbuf[d] = off;
     if (d < g->ndim) off += align256((size_t)nv * (size_t)faces_total(g, d) * sizeof(double));
   }
-  int64_t max_nft = 0;
-  for (int d = 0; d < g->ndim; ++d) max_nft = faces_total(g, d) > max_nft ? faces_total(g, d) : max_nft;
-  L.vjp_flags = L.vjp_fh = off;
-  if (which == TENOAA_WS_RHS_VJP || which == TENOAA_WS_STEP_VJP) {
-    L.vjp_flags = off;
-    off += align256((size_t)nv * 2 * (size_t)max_nft);
-    L.vjp_fh = off;
-    off += align256((size_t)nv * (size_t)max_nft * sizeof(double));
+  // decisions and per-field fluxes of every direction, for one stage (RHS_VJP)
+  // or the three stages of a step (STEP_VJP)
+  const int nstage = which == TENOAA_WS_STEP_VJP ? 3 : (which == TENOAA_WS_RHS_VJP ? 1 : 0);
+  for (int st = 0; st < 3; ++st) {
+    for (int d = 0; d < 3; ++d) {
+      L.vjp[st][d] = off;
+      if (st < nstage && d < g->ndim) {
+        L.vjp_fh_rel[d] = align256((size_t)nv * 2 * (size_t)faces_total(g, d));
+        off += L.vjp_fh_rel[d] + align256((size_t)nv * (size_t)faces_total(g, d) * sizeof(double));
+      }
+    }
   }
   L.stage = off;
   const size_t state = align256((size_t)nv * (size_t)ncell * sizeof(double));
@@ -217,29 +220,35 @@ int update(const Ctx& c, int mode, const double* Un, const double* Us, double* o
   return e == hipSuccess ? TENOAA_OK : hip_fail(e);
 }
 
-// U_bar = (d(dU/dt)/dU)^T R at U, decisions frozen at U.  Per direction the
-// forward sweep records its decisions and per-field fluxes in the workspace,
-// then the reverse sweep accumulates into U_bar.
-int rhs_vjp(const Ctx& c, const double* U, const double* R, double* Ubar) {
+// Forward sweeps of U in every direction that also leave the decisions and
+// per-field fluxes of adjoint stage slot `st` in the workspace.
+int recorded_sweeps(const Ctx& c, const double* U, int st) {
+  for (int d = 0; d < c.g->ndim; ++d) {
+    uint8_t* flags = reinterpret_cast<uint8_t*>(c.ws + c.L.vjp[st][d]);
+    double* fh = reinterpret_cast<double*>(c.ws + c.L.vjp[st][d] + c.L.vjp_fh_rel[d]);
+    int rc = sweeps(c, U, false, flags, nullptr, d, fh);
+    if (rc) return rc;
+  }
+  return TENOAA_OK;
+}
+
+// U_bar = (d(dU/dt)/dU)^T R at U, decisions frozen at U, from the decisions
+// and per-field fluxes that recorded_sweeps(U) left in stage slot `st`.
+int rhs_vjp(const Ctx& c, const double* U, const double* R, double* Ubar, int st) {
   const tenoaa_grid* g = c.g;
   const int nv = g->ndim + 2;
   const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
   hipError_t e = tenoaa::launch_zero(Ubar, (int64_t)nv * ncell, c.st);
   if (e != hipSuccess) return hip_fail(e);
-  uint8_t* flags = reinterpret_cast<uint8_t*>(c.ws + c.L.vjp_flags);
-  double* fh = reinterpret_cast<double*>(c.ws + c.L.vjp_fh);
   for (int d = 0; d < g->ndim; ++d) {
-    const int64_t nft = faces_total(g, d);
-    int rc = sweeps(c, U, false, flags, nullptr, d, fh);
-    if (rc) return rc;
     tenoaa::AdjointArgs a;
     std::memset(&a, 0, sizeof(a));
     a.U = U;
     a.R = R;
     a.Ubar = Ubar;
-    a.flags = flags;
-    a.fh = fh;
-    a.nft = nft;
+    a.flags = reinterpret_cast<const uint8_t*>(c.ws + c.L.vjp[st][d]);
+    a.fh = reinterpret_cast<const double*>(c.ws + c.L.vjp[st][d] + c.L.vjp_fh_rel[d]);
+    a.nft = faces_total(g, d);
     for (int k = 0; k < 3; ++k) a.n[k] = g->n[k];
     a.nf = faces_along(g, d);
     a.bc_lo = g->bc_lo[d];
@@ -355,7 +364,8 @@ int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double 
   if (rc) return rc;
   if (!U || !dUdt_bar || !U_bar || U_bar == U || U_bar == dUdt_bar) return TENOAA_EINVAL;
   if ((rc = begin(c))) return rc;
-  return rhs_vjp(c, U, dUdt_bar, U_bar);
+  if ((rc = recorded_sweeps(c, U, 0))) return rc;
+  return rhs_vjp(c, U, dUdt_bar, U_bar, 0);
 }
 
 int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* Un,
@@ -374,21 +384,24 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
   double* B2 = reinterpret_cast<double*>(c.ws + c.L.stage + 3 * c.L.state_bytes);
   double* B1 = S2;
   hipError_t e;
-  // recompute the stages: U1 = Un + dt L(Un), U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1)
+  // recompute the stages, recording each stage's decisions and per-field
+  // fluxes: U1 = Un + dt L(Un), U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1), and the
+  // sweeps of U2
   hipLaunchKernelGGL(copy_dt_kernel, dim3(1), dim3(64), 0, c.st, c.S, dt_dev);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
-  if ((rc = sweeps(c, Un, false, nullptr))) return rc;
+  if ((rc = recorded_sweeps(c, Un, 0))) return rc;
   if ((rc = update(c, 1, Un, nullptr, S1))) return rc;
-  if ((rc = sweeps(c, S1, false, nullptr))) return rc;
+  if ((rc = recorded_sweeps(c, S1, 1))) return rc;
   if ((rc = update(c, 2, Un, S1, S2))) return rc;
+  if ((rc = recorded_sweeps(c, S2, 2))) return rc;
   // reverse: B2 = 2/3 B3 + 2/3 dt J(U2)^T B3
-  if ((rc = rhs_vjp(c, S2, Unp1_bar, V))) return rc;
+  if ((rc = rhs_vjp(c, S2, Unp1_bar, V, 2))) return rc;
   if ((e = tenoaa::launch_axpdtz(B2, 2.0 / 3.0, Unp1_bar, 2.0 / 3.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
   // B1 = 1/4 B2 + 1/4 dt J(U1)^T B2
-  if ((rc = rhs_vjp(c, S1, B2, V))) return rc;
+  if ((rc = rhs_vjp(c, S1, B2, V, 1))) return rc;
   if ((e = tenoaa::launch_axpdtz(B1, 0.25, B2, 0.25, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
   // Bn = 1/3 B3 + 3/4 B2 + B1 + dt J(Un)^T B1
-  if ((rc = rhs_vjp(c, Un, B1, V))) return rc;
+  if ((rc = rhs_vjp(c, Un, B1, V, 0))) return rc;
   if ((e = tenoaa::launch_axpbypcz(Un_bar, 1.0 / 3.0, Unp1_bar, 0.75, B2, 1.0, B1, N, c.st)) != hipSuccess)
     return hip_fail(e);
   if ((e = tenoaa::launch_axpdtz(Un_bar, 1.0, Un_bar, 1.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);

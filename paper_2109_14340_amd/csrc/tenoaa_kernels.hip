@@ -30,7 +30,7 @@
 
 // Launch-shape tunables (overridable at build time).
 #ifndef TENOAA_WAVES_PER_EU
-#define TENOAA_WAVES_PER_EU 0
+#define TENOAA_WAVES_PER_EU 3
 #endif
 #ifndef TENOAA_TN_X
 #define TENOAA_TN_X 64
@@ -39,10 +39,10 @@
 #define TENOAA_TT_X 4
 #endif
 #ifndef TENOAA_TN_YZ
-#define TENOAA_TN_YZ 16
+#define TENOAA_TN_YZ 32
 #endif
 #ifndef TENOAA_TT_YZ
-#define TENOAA_TT_YZ 16
+#define TENOAA_TT_YZ 8
 #endif
 
 namespace tenoaa {
