@@ -75,6 +75,18 @@ __device__ __forceinline__ double rcp_dec(double x) {
   return fma(r, e, r);
 }
 
+// x / 6 correctly rounded: one product by RN(1/6) and one fma correction of
+// the exact remainder (Markstein's theorem: the reciprocal within 1/2 ulp and
+// the first quotient within 1 ulp make the corrected quotient the correctly
+// rounded one, in round-to-nearest, away from underflow and overflow).  Equal
+// to the IEEE division x / 6.0 bit for bit in that range.
+__device__ __forceinline__ double div6(double x) {
+  constexpr double y = 1.0 / 6.0;
+  const double q = x * y;
+  const double r = fma(-6.0, q, x);
+  return fma(r, y, q);
+}
+
 // gamma = 1/(beta + eps)^7 (Sec. 3.2, q = 7), decision-only.
 __device__ __forceinline__ double gamma7(double beta) {
   const double r = rcp_dec(beta + EPS);
@@ -155,7 +167,7 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
       db = den;
     }
   });
-  const double etabar = nb / db;
+  const double etabar = nb * rcp_dec(db);  // decision-only
   double ratio = etabar * (1.0 / C_R);
   if (ratio > 1.0) ratio = 1.0;
   const double m = 1.0 - ratio;
@@ -211,9 +223,9 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   const int dm = (g0 >= cs ? 1 : 0) | (g1 >= cs ? 2 : 0) | (g2 >= cs ? 4 : 0);
   flag = (uint8_t)((dm << 2) | kbits);
   const double fm1 = v[I - 1], f0 = v[I], f1 = v[I + 1];
-  const double h0 = ((-fm1 + 5.0 * f0) + 2.0 * f1) / 6.0;
-  const double h1 = ((2.0 * f0 + 5.0 * f1) - v[I + 2]) / 6.0;
-  const double h2 = ((2.0 * v[I - 2] - 7.0 * fm1) + 11.0 * f0) / 6.0;
+  const double h0 = div6((-fm1 + 5.0 * f0) + 2.0 * f1);
+  const double h1 = div6((2.0 * f0 + 5.0 * f1) - v[I + 2]);
+  const double h2 = div6((2.0 * v[I - 2] - 7.0 * fm1) + 11.0 * f0);
   return fma(WFALL.w[dm][2], h2, fma(WFALL.w[dm][1], h1, WFALL.w[dm][0] * h0));
 }
 
@@ -231,9 +243,9 @@ __device__ __forceinline__ double replay_recon(const double (&v)[ORDER], uint8_t
   if (sel == 1) return linear_flux<6, (ORDER == 10) ? 2 : 1>(v);
   const int dm = (flag >> 2) & 7;
   const double fm1 = v[I - 1], f0 = v[I], f1 = v[I + 1];
-  const double h0 = ((-fm1 + 5.0 * f0) + 2.0 * f1) / 6.0;
-  const double h1 = ((2.0 * f0 + 5.0 * f1) - v[I + 2]) / 6.0;
-  const double h2 = ((2.0 * v[I - 2] - 7.0 * fm1) + 11.0 * f0) / 6.0;
+  const double h0 = div6((-fm1 + 5.0 * f0) + 2.0 * f1);
+  const double h1 = div6((2.0 * f0 + 5.0 * f1) - v[I + 2]);
+  const double h2 = div6((2.0 * v[I - 2] - 7.0 * fm1) + 11.0 * f0);
   return fma(WFALL.w[dm][2], h2, fma(WFALL.w[dm][1], h1, WFALL.w[dm][0] * h0));
 }
 
