@@ -36,6 +36,10 @@
 namespace tenoaa {
 namespace {
 
+#ifndef TENOAA_BATCH_WAVES_PER_EU
+#define TENOAA_BATCH_WAVES_PER_EU 3
+#endif
+
 constexpr int BT = 256;         // threads per block
 constexpr int CELLS_ITEM = 1024;  // cells per update / wave-speed item
 constexpr int NBUCKET = 3;        // size buckets of the tile choice (by n_x)
@@ -275,7 +279,11 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs& B, unsigned long l
 }
 
 template <int ORDER, bool LIMIT>
-__global__ __launch_bounds__(BT) void batch_kernel(BatchArgs B) {
+__global__ __launch_bounds__(BT)
+#if TENOAA_BATCH_WAVES_PER_EU > 0
+__attribute__((amdgpu_waves_per_eu(TENOAA_BATCH_WAVES_PER_EU)))
+#endif
+void batch_kernel(BatchArgs B) {
   __shared__ __align__(16) char arena[arena_bytes<ORDER>()];
   __shared__ int64_t s_first;
   __shared__ int s_flag;

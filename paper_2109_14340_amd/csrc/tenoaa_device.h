@@ -111,10 +111,14 @@ __device__ __forceinline__ double sos_beta(const double (&v)[W]) {
   double beta = 0.0;
   unroll<R - 1>([&](auto kk) {
     constexpr int k = decltype(kk)::value;
-    double y = 0.0;
+    // y_k = sum_{m >= k} L[m][k] dif[m]; L has a unit diagonal, so the sum
+    // starts from dif[k] itself (no addition of a zero)
+    constexpr double lkk = (R == 10) ? SOS_S5_L[k][k] : (R == 8) ? SOS_S4_L[k][k] : SOS_S3_L[k][k];
+    static_assert(lkk == 1.0, "the factor must have a unit diagonal");
+    double y = dif[k];
     unroll<R - 1>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
-      if constexpr (m >= k) {
+      if constexpr (m > k) {
         constexpr double l = (R == 10) ? SOS_S5_L[m][k] : (R == 8) ? SOS_S4_L[m][k] : SOS_S3_L[m][k];
         if constexpr (l != 0.0) y = fma(l, dif[m], y);
       }
