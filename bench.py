@@ -53,7 +53,7 @@ def measured_traffic(kernel):
     return t.get("traffic_bytes")
 
 
-def cpu_baseline(n=64):
+def cpu_baseline(n=72):
     """The oracle, single-threaded, on one step of the same recipe at n^3."""
     import numpy as np  # noqa: F401
     import oracle
