@@ -66,9 +66,19 @@ def cpu_baseline(n=72):
     oracle.step(g, U, order=10, splitting=0, positivity=1, gamma=1.4, cfl=0.4)
     el = time.perf_counter() - t
     work = 9 * n ** 3
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": work / el / 1e9, "unit": "Gface-recon/s", "cores": 1, "kind": "oracle",
             "sample": "one SSP-RK3 step (TENO10-AA, LLF, limiter, CFL 0.4) of the same recipe on a "
-                      "%d^3 periodic grid: %d face reconstructions in %.2f s" % (n, work, el)}
+                      "%d^3 periodic grid: %d face reconstructions in %.2f s, one thread of %s (%d visible "
+                      "cores)" % (n, work, el, model, os.cpu_count() or 0)}
 
 
 def fwd_adj_leg(shape, steps, warmup, U0):

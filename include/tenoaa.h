@@ -118,24 +118,28 @@ int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gam
 
 /* Vector-Jacobian product of the right-hand side (the adjoint form; not a
  * formula of the paper).  U_bar (overwritten) = (d dUdt / dU)^T dUdt_bar at
- * U, with every threshold decision frozen at U: the stencil chosen by the
- * cascade and the small-stencil deltas (Sec. 3.3), i.e. the linear weights
- * of each reconstruction, and the cell and sign that attain each splitting
- * speed.  The limiter is not part of the differentiated map (it acts only
- * with a dt).  U_bar is accumulated with FP64 atomics, so its last bits can
- * differ between runs.  U_bar must not alias U or dUdt_bar. */
+ * U, with every threshold decision frozen: the stencil chosen by the cascade
+ * and the small-stencil deltas (Sec. 3.3), i.e. the linear weights of each
+ * reconstruction, and the cell and sign that attain each splitting speed.
+ * flags: NULL to freeze the decisions taken at U, or a flag array (layout
+ * above, e.g. recorded by tenoaa_rhs at another state) whose decisions are
+ * used instead.  The limiter is not part of the differentiated map (it acts
+ * only with a dt).  U_bar is accumulated with FP64 atomics, so its last bits
+ * can differ between runs.  U_bar must not alias U or dUdt_bar. */
 int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
-                   const double* dUdt_bar, double* U_bar, void* ws, size_t ws_bytes, void* stream);
+                   const double* dUdt_bar, double* U_bar, const uint8_t* flags, void* ws, size_t ws_bytes,
+                   void* stream);
 
 /* Vector-Jacobian product of one SSP-RK3 step with the time step frozen:
  * Un_bar (overwritten) = (d U^{n+1} / d U^n)^T Unp1_bar.  dt_dev is the device
  * double holding the dt the forward step used (> 0).  The three stage states
  * are recomputed from Un inside the call; each stage's decisions are frozen at
- * its own state.  TENOAA_EUNSUPPORTED with the limiter on.  Un_bar must not
- * alias Un or Unp1_bar. */
+ * its own state, or, with flags3 non-NULL, taken from flags3 (the three
+ * stages' decisions as recorded by tenoaa_step_flags).  TENOAA_EUNSUPPORTED
+ * with the limiter on.  Un_bar must not alias Un or Unp1_bar. */
 int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* Un,
-                    const double* dt_dev, const double* Unp1_bar, double* Un_bar, void* ws, size_t ws_bytes,
-                    void* stream);
+                    const double* dt_dev, const double* Unp1_bar, double* Un_bar, const uint8_t* flags3, void* ws,
+                    size_t ws_bytes, void* stream);
 
 /* Decision modes of tenoaa_step_flags. */
 enum { TENOAA_FLAGS_NONE = 0, TENOAA_FLAGS_RECORD = 1, TENOAA_FLAGS_REPLAY = 2 };

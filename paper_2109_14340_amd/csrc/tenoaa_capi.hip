@@ -221,15 +221,25 @@ int update(const Ctx& c, int mode, const double* Un, const double* Us, double* o
 }
 
 // Forward sweeps of U in every direction that also leave the decisions and
-// per-field fluxes of adjoint stage slot `st` in the workspace.
-int recorded_sweeps(const Ctx& c, const double* U, int st) {
+// per-field fluxes of adjoint stage slot `st` in the workspace.  With
+// `frozen` (a flag array in the layout of tenoaa_rhs) the sweeps replay those
+// decisions instead of taking them.
+int recorded_sweeps(const Ctx& c, const double* U, int st, const uint8_t* frozen) {
+  int64_t off = 0;
   for (int d = 0; d < c.g->ndim; ++d) {
     uint8_t* flags = reinterpret_cast<uint8_t*>(c.ws + c.L.vjp[st][d]);
     double* fh = reinterpret_cast<double*>(c.ws + c.L.vjp[st][d] + c.L.vjp_fh_rel[d]);
-    int rc = sweeps(c, U, false, flags, nullptr, d, fh);
+    int rc = sweeps(c, U, false, flags, frozen ? frozen + off : nullptr, d, fh);
     if (rc) return rc;
+    off += (int64_t)(c.g->ndim + 2) * 2 * faces_total(c.g, d);
   }
   return TENOAA_OK;
+}
+
+int64_t flag_count(const tenoaa_grid* g) {
+  int64_t n = 0;
+  for (int d = 0; d < g->ndim; ++d) n += (int64_t)(g->ndim + 2) * 2 * faces_total(g, d);
+  return n;
 }
 
 // U_bar = (d(dU/dt)/dU)^T R at U, decisions frozen at U, from the decisions
@@ -358,19 +368,20 @@ int tenoaa_step_flags(const tenoaa_grid* grid, const tenoaa_scheme* scheme, doub
 }
 
 int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
-                   const double* dUdt_bar, double* U_bar, void* ws, size_t ws_bytes, void* stream) {
+                   const double* dUdt_bar, double* U_bar, const uint8_t* flags, void* ws, size_t ws_bytes,
+                   void* stream) {
   Ctx c;
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_RHS_VJP);
   if (rc) return rc;
   if (!U || !dUdt_bar || !U_bar || U_bar == U || U_bar == dUdt_bar) return TENOAA_EINVAL;
   if ((rc = begin(c))) return rc;
-  if ((rc = recorded_sweeps(c, U, 0))) return rc;
+  if ((rc = recorded_sweeps(c, U, 0, flags))) return rc;
   return rhs_vjp(c, U, dUdt_bar, U_bar, 0);
 }
 
 int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* Un,
-                    const double* dt_dev, const double* Unp1_bar, double* Un_bar, void* ws, size_t ws_bytes,
-                    void* stream) {
+                    const double* dt_dev, const double* Unp1_bar, double* Un_bar, const uint8_t* flags3, void* ws,
+                    size_t ws_bytes, void* stream) {
   Ctx c;
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP_VJP);
   if (rc) return rc;
@@ -389,11 +400,13 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
   // sweeps of U2
   hipLaunchKernelGGL(copy_dt_kernel, dim3(1), dim3(64), 0, c.st, c.S, dt_dev);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
-  if ((rc = recorded_sweeps(c, Un, 0))) return rc;
+  const int64_t nfl = flag_count(grid);
+  auto stage_flags = [&](int st) { return flags3 ? flags3 + st * nfl : nullptr; };
+  if ((rc = recorded_sweeps(c, Un, 0, stage_flags(0)))) return rc;
   if ((rc = update(c, 1, Un, nullptr, S1))) return rc;
-  if ((rc = recorded_sweeps(c, S1, 1))) return rc;
+  if ((rc = recorded_sweeps(c, S1, 1, stage_flags(1)))) return rc;
   if ((rc = update(c, 2, Un, S1, S2))) return rc;
-  if ((rc = recorded_sweeps(c, S2, 2))) return rc;
+  if ((rc = recorded_sweeps(c, S2, 2, stage_flags(2)))) return rc;
   // reverse: B2 = 2/3 B3 + 2/3 dt J(U2)^T B3
   if ((rc = rhs_vjp(c, S2, Unp1_bar, V, 2))) return rc;
   if ((e = tenoaa::launch_axpdtz(B2, 2.0 / 3.0, Unp1_bar, 2.0 / 3.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);

@@ -64,9 +64,9 @@ def load():
         L.tenoaa_step_flags.argtypes = [gp, sp, ctypes.c_double, ctypes.c_double, vp, vp, vp, ctypes.c_int32, vp,
                                         ctypes.c_size_t, vp]
         L.tenoaa_rhs_vjp.restype = ctypes.c_int
-        L.tenoaa_rhs_vjp.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tenoaa_rhs_vjp.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.tenoaa_step_vjp.restype = ctypes.c_int
-        L.tenoaa_step_vjp.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tenoaa_step_vjp.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.tenoaa_get_status.restype = ctypes.c_int
         L.tenoaa_get_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
         L.tenoaa_last_hip_error.restype = ctypes.c_int
@@ -192,8 +192,9 @@ def step(grid, scheme, U, dt_dev, gamma=1.4, cfl=0.4, ws=None):
     return U
 
 
-def rhs_vjp(grid, scheme, U, dUdt_bar, gamma=1.4, out=None, ws=None):
-    """(d dU/dt / dU)^T dUdt_bar at U with the decisions frozen at U."""
+def rhs_vjp(grid, scheme, U, dUdt_bar, gamma=1.4, out=None, ws=None, flags=None):
+    """(d dU/dt / dU)^T dUdt_bar at U with the decisions frozen at U, or taken
+    from `flags` (uint8 device tensor of flags_size(grid)) when given."""
     import torch
     _check_state(U, grid)
     _check_state(dUdt_bar, grid)
@@ -201,14 +202,17 @@ def rhs_vjp(grid, scheme, U, dUdt_bar, gamma=1.4, out=None, ws=None):
         out = torch.empty_like(U)
     if ws is None:
         ws = workspace(grid, scheme, WS_RHS_VJP, U.device)
+    if flags is not None and (flags.dtype != torch.uint8 or flags.numel() < flags_size(grid)):
+        raise TenoaaError("flags must be uint8 with flags_size(grid) elements")
     rc = load().tenoaa_rhs_vjp(ctypes.byref(grid), ctypes.byref(scheme), gamma, _ptr(U), _ptr(dUdt_bar), _ptr(out),
-                               _ptr(ws), ws.numel(), _stream())
+                               _ptr(flags), _ptr(ws), ws.numel(), _stream())
     _check(rc, "tenoaa_rhs_vjp")
     return out
 
 
-def step_vjp(grid, scheme, Un, dt_dev, Unp1_bar, gamma=1.4, out=None, ws=None):
-    """(d U^{n+1} / d U^n)^T Unp1_bar for the step of size *dt_dev from Un."""
+def step_vjp(grid, scheme, Un, dt_dev, Unp1_bar, gamma=1.4, out=None, ws=None, flags3=None):
+    """(d U^{n+1} / d U^n)^T Unp1_bar for the step of size *dt_dev from Un;
+    flags3: optional recorded decisions of the three stages."""
     import torch
     _check_state(Un, grid)
     _check_state(Unp1_bar, grid)
@@ -216,8 +220,10 @@ def step_vjp(grid, scheme, Un, dt_dev, Unp1_bar, gamma=1.4, out=None, ws=None):
         out = torch.empty_like(Un)
     if ws is None:
         ws = workspace(grid, scheme, WS_STEP_VJP, Un.device)
+    if flags3 is not None and (flags3.dtype != torch.uint8 or flags3.numel() < 3 * flags_size(grid)):
+        raise TenoaaError("flags3 must be uint8 with 3 * flags_size(grid) elements")
     rc = load().tenoaa_step_vjp(ctypes.byref(grid), ctypes.byref(scheme), gamma, _ptr(Un), _ptr(dt_dev),
-                                _ptr(Unp1_bar), _ptr(out), _ptr(ws), ws.numel(), _stream())
+                                _ptr(Unp1_bar), _ptr(out), _ptr(flags3), _ptr(ws), ws.numel(), _stream())
     _check(rc, "tenoaa_step_vjp")
     return out
 

@@ -121,3 +121,43 @@ def test_step_vjp_rejects_limiter():
     dtd = torch.tensor([1e-3], dtype=torch.float64, device="cuda")
     with pytest.raises(tenoaa.TenoaaError):
         tenoaa.step_vjp(g, sch, U, dtd, U.clone())
+
+
+def test_rhs_vjp_with_flags_of_another_state():
+    """Decisions given by the caller (here those the oracle takes at a
+    perturbed state) are the ones differentiated: dot test against the
+    oracle's JVP with the same flags."""
+    U = np.ascontiguousarray(inputs.grf_2d(24, seed=41)[:, :, :20, :])
+    shape, bc = (24, 20), [0, 0]
+    g_or, g_gpu = _grids(shape, bc)
+    rng = np.random.default_rng(42)
+    Up = U * (1.0 + 0.05 * rng.standard_normal(U.shape))
+    _, fl_u, _ = oracle.rhs(g_or, U, order=10)
+    _, fl_p, _ = oracle.rhs(g_or, Up, order=10)
+    assert (fl_p != fl_u).sum() > 0
+    V = rng.standard_normal(U.shape) * np.abs(U).reshape(U.shape[0], -1).max(axis=1)[:, None, None, None]
+    Wt = rng.standard_normal(U.shape)
+    _, jv = oracle.rhs_jvp(g_or, U, V, fl_p, order=10)
+    sch = tenoaa.make_scheme(10, 0, 0)
+    jtw = tenoaa.to_numpy(tenoaa.rhs_vjp(g_gpu, sch, _dev(U), _dev(Wt), flags=_dev(fl_p)))
+    lhs, rhs = float(np.sum(Wt * jv)), float(np.sum(jtw * V))
+    scale = float(np.sum(np.abs(Wt * jv)))
+    print("flags of another state: %d differ; <w,Jv> %.15e <J^T w,v> %.15e rel %.2e" % (
+        int((fl_p != fl_u).sum()), lhs, rhs, abs(lhs - rhs) / scale))
+    assert abs(lhs - rhs) <= 1e-11 * scale
+
+
+def test_step_vjp_with_recorded_flags_matches_recompute():
+    U = np.ascontiguousarray(inputs.grf_2d(32, seed=43)[:, :, :24, :])
+    g = tenoaa.make_grid((32, 24))
+    sch = tenoaa.make_scheme(10, 0, 0)
+    Ud = _dev(U)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fl3 = torch.zeros(3 * tenoaa.flags_size(g), dtype=torch.uint8, device="cuda")
+    tenoaa.step_flags(g, sch, Ud.clone(), dt, fl3, tenoaa.FLAGS_RECORD)
+    W = _dev(np.random.default_rng(44).standard_normal(U.shape))
+    a = tenoaa.step_vjp(g, sch, Ud, dt, W)
+    b = tenoaa.step_vjp(g, sch, Ud, dt, W, flags3=fl3)
+    err = float((a - b).abs().max() / a.abs().max())
+    print("step VJP with recorded flags vs recomputed: max rel %.2e" % err)
+    assert err <= 1e-13

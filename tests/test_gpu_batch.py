@@ -153,3 +153,16 @@ def test_batch_rebinds_state_between_runs():
     for p in range(3):
         assert torch.equal(plan.unpack(a, p), ref[p])
         assert torch.equal(plan.unpack(b, p), ref2[p])
+
+
+def test_batch_reports_non_physical_problem():
+    sch = tenoaa.make_scheme(8, tenoaa.LLF, 0)
+    grids, states = _problems(SIZES[:3])
+    bad = states[1].copy()
+    bad[3, 0, 10:20, 10:20] = 0.0  # E = 0 with momentum: negative pressure
+    plan = tenoaa.BatchPlan(grids, sch, 1)
+    packed = plan.pack([states[0], bad, states[2]])
+    plan.run(packed)
+    assert plan.status() == [0, 1, 0]
+    ref, _ = _per_problem([grids[0]], [states[0]], sch, 1)
+    assert torch.equal(plan.unpack(packed, 0), ref[0])
