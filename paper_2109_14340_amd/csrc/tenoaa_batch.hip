@@ -221,8 +221,11 @@ __device__ __forceinline__ void update_item(const BatchArgs& B, char* arena, int
   for (int r = 0; r < CELLS_ITEM / BT; ++r) {
     const int64_t idx = k * CELLS_ITEM + r * BT + threadIdx.x;
     if (idx < ncell) {
+      // a problem has fewer than 2^31 cells (checked when the plan is made)
+      const uint32_t q = (uint32_t)idx / (uint32_t)P.n[0];
+      const int64_t co[3] = {(int64_t)((uint32_t)idx - q * (uint32_t)P.n[0]), (int64_t)q, 0};
       double Wn[4];
-      update_cell<2, MODE>(A, idx, dt, Wn);
+      update_cell<2, MODE>(A, idx, co, dt, Wn);
       if (speeds) cell_speeds<2>(Wn, B.gamma, amax, bad);
     }
   }
@@ -674,6 +677,7 @@ int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const teno
   for (int q = 0; q < nprob; ++q) {
     if (!tenoaa::grid_ok(&grids[q], scheme)) return TENOAA_EINVAL;
     if (grids[q].ndim != 2) return TENOAA_EUNSUPPORTED;
+    if (grids[q].n[0] * grids[q].n[1] >= ((int64_t)1 << 31)) return TENOAA_EINVAL;
     total += 4 * grids[q].n[0] * grids[q].n[1];
     if (total > ((int64_t)1 << 40)) return TENOAA_EINVAL;
   }

@@ -35,6 +35,7 @@ struct SweepArgs {
 };
 
 struct UpdateArgs {
+  uint32_t div_m[2], div_l[2];  // fast division by n0 and n1 (grids below 2^32 cells)
   const double* F[3];
   int64_t nft[3];
   int64_t nf[3];

@@ -65,10 +65,24 @@ template <int NDIM, int MODE>
 __global__ __launch_bounds__(256) void update_kernel(UpdateArgs A) {
   const int64_t ncell = A.n[0] * A.n[1] * A.n[2];
   const double dt = (MODE == 0) ? 0.0 : *A.dt;
+  const bool small = ncell < ((int64_t)1 << 32);
+  const FastDiv d0{A.div_m[0], A.div_l[0]}, d1{A.div_m[1], A.div_l[1]};
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ncell;
        idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t co[3];
+    if (small) {
+      const uint32_t q0 = fastdiv((uint32_t)idx, d0);
+      const uint32_t q1 = fastdiv(q0, d1);
+      co[0] = (int64_t)((uint32_t)idx - q0 * (uint32_t)A.n[0]);
+      co[1] = (int64_t)(q0 - q1 * (uint32_t)A.n[1]);
+      co[2] = (int64_t)q1;
+    } else {
+      co[0] = idx % A.n[0];
+      co[1] = (idx / A.n[0]) % A.n[1];
+      co[2] = idx / (A.n[0] * A.n[1]);
+    }
     double Wn[NDIM + 2];
-    update_cell<NDIM, MODE>(A, idx, dt, Wn);
+    update_cell<NDIM, MODE>(A, idx, co, dt, Wn);
   }
 }
 
@@ -158,9 +172,22 @@ hipError_t launch_sweep(int order, int ndim, int dir, const SweepArgs& a, bool l
   return order == 10 ? launch_sweep_ord<10>(ndim, dir, a, limit, st) : launch_sweep_ord<8>(ndim, dir, a, limit, st);
 }
 
+// Multiplier and shift of fastdiv for the divisor d (1 <= d < 2^32).
+static void fastdiv_make(uint64_t d, uint32_t& m, uint32_t& l) {
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  l = s;
+  m = (uint32_t)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+}
+
 template <int NDIM>
-static hipError_t launch_update_n(int mode, const UpdateArgs& a, hipStream_t st) {
+static hipError_t launch_update_n(int mode, const UpdateArgs& a0, hipStream_t st) {
+  UpdateArgs a = a0;
   const int64_t ncell = a.n[0] * a.n[1] * a.n[2];
+  for (int k = 0; k < 2; ++k) {
+    const uint64_t d = (uint64_t)a.n[k];
+    if (d >= 1 && d < (1ull << 32)) fastdiv_make(d, a.div_m[k], a.div_l[k]);
+  }
   int64_t blocks = (ncell + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   dim3 g((unsigned)blocks);

@@ -395,16 +395,13 @@ __device__ __forceinline__ void cell_speeds(const double (&Wc)[NDIM + 2], double
   unroll<NDIM>([&](auto d) { amax[d] = dmax(amax[d], fabs(u[d]) + c); });
 }
 
-// Flux difference and SSP-RK3 stage of cell idx (MODE 0: dU/dt; 1-3: stage).
-// The new state of the cell is left in Wn.
+// Flux difference and SSP-RK3 stage of cell idx = co[0] + n0 (co[1] + n1 co[2])
+// (MODE 0: dU/dt; 1-3: stage).  The new state of the cell is left in Wn.
 template <int NDIM, int MODE>
-__device__ __forceinline__ void update_cell(const UpdateArgs& A, int64_t idx, double dt, double (&Wn)[NDIM + 2]) {
+__device__ __forceinline__ void update_cell(const UpdateArgs& A, int64_t idx, const int64_t (&co)[3], double dt,
+                                            double (&Wn)[NDIM + 2]) {
   constexpr int NV = NDIM + 2;
   const int64_t ncell = A.n[0] * A.n[1] * A.n[2];
-  int64_t co[3];
-  co[0] = idx % A.n[0];
-  co[1] = (idx / A.n[0]) % A.n[1];
-  co[2] = idx / (A.n[0] * A.n[1]);
   int64_t fl[3], fr[3];
   unroll<NDIM>([&](auto d) {
     int64_t m[3] = {A.n[0], A.n[1], A.n[2]};
@@ -437,6 +434,16 @@ __device__ __forceinline__ void update_cell(const UpdateArgs& A, int64_t idx, do
     A.out[e] = v;
     Wn[c] = v;
   });
+}
+
+// Division of 32-bit unsigned integers by an invariant divisor d >= 1 with a
+// multiply-high and a shift (Granlund and Montgomery): m and l from
+// fastdiv_make on the host.
+struct FastDiv {
+  uint32_t m, l;
+};
+__device__ __forceinline__ uint32_t fastdiv(uint32_t n, FastDiv f) {
+  return (uint32_t)(((uint64_t)__umulhi(f.m, n) + n) >> f.l);
 }
 
 // dt = cfl / sum_d a_d/dx_d (reading of the multi-dimensional CFL condition)
