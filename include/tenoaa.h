@@ -180,7 +180,10 @@ typedef struct tenoaa_batch_plan tenoaa_batch_plan;
  * the choices are tuned now on the device by timing one step of the batch
  * from a uniform state, and appended to the file as
  * {"key": ..., "tile_x": [3], "tile_y": [3], "chunk": c, "blocks_per_cu": b,
- * "step_ms": t}.  Results do not depend on these choices.  Returns EINVAL
+ * "step_ms": t}.  Results do not depend on these choices.  A phase barrier
+ * of the persistent kernel gives up after 20 s (the environment variable
+ * TENOAA_BATCH_BARRIER_TIMEOUT_US, read here, sets another limit; tests use it
+ * to exercise tenoaa_batch_get_status's TENOAA_ETIMEOUT).  Returns EINVAL
  * for bad arguments, EUNSUPPORTED for ndim != 2, EHIP on a HIP failure;
  * *out is NULL unless 0 is returned. */
 int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const tenoaa_scheme* scheme, double gamma,

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -714,8 +715,12 @@ int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const teno
   }
   P->max_bpc = nblk;
   P->bpc = nblk;
-  // a barrier wait longer than 20 s means the grid is not resident
-  P->args.timeout_ticks = (int64_t)(rate_khz > 0 ? rate_khz : 100000) * 1000 * 20;
+  // a barrier wait longer than 20 s means the grid is not resident; the
+  // environment can shorten the limit to exercise the abandon path
+  double limit_us = 20.0e6;
+  if (const char* env = std::getenv("TENOAA_BATCH_BARRIER_TIMEOUT_US")) limit_us = std::atof(env);
+  if (!(limit_us >= 0.0) || limit_us > 600.0e6) limit_us = 20.0e6;
+  P->args.timeout_ticks = (int64_t)((double)(rate_khz > 0 ? rate_khz : 100000) * 1e-3 * limit_us);
 
   int64_t s_total = 0, f_total = 0;
   for (const tenoaa_grid& g : P->grids) {

@@ -166,3 +166,23 @@ def test_batch_reports_non_physical_problem():
     assert plan.status() == [0, 1, 0]
     ref, _ = _per_problem([grids[0]], [states[0]], sch, 1)
     assert torch.equal(plan.unpack(packed, 0), ref[0])
+
+
+def test_batch_barrier_time_limit_abandons_run(monkeypatch):
+    """A barrier limit of zero forces the abandon path from the host: every
+    block leaves, the status call reports ETIMEOUT, and a normal plan runs
+    correctly afterwards."""
+    sch = tenoaa.make_scheme(8, tenoaa.LLF, 0)
+    grids, states = _problems(SIZES[:4])
+    monkeypatch.setenv("TENOAA_BATCH_BARRIER_TIMEOUT_US", "0")
+    plan = tenoaa.BatchPlan(grids, sch, 3)
+    monkeypatch.delenv("TENOAA_BATCH_BARRIER_TIMEOUT_US")
+    packed = plan.pack(states)
+    plan.run(packed)
+    with pytest.raises(tenoaa.TenoaaError, match="ETIMEOUT"):
+        plan.status()
+    plan.close()
+    plan2, packed2, dtb, st = _batched(grids, states, sch, 3)
+    assert st == [0] * 4
+    ref, dtr = _per_problem(grids, states, sch, 3)
+    _assert_same(plan2, packed2, dtb, ref, dtr)
