@@ -360,15 +360,16 @@ void cell_state(int ndim, double gam, int d, const T* W, CellQ<T>& q) {
   const int nv = ndim + 2;
   for (int c = 0; c < nv; ++c) q.W[c] = W[c];
   const T rho = W[0];
+  const T ir = 1.0 / rho;  // divisions by rho as products with its reciprocal
   T q2 = T(0.0);
   for (int k = 0; k < ndim; ++k) {
-    q.u[k] = W[1 + k] / rho;
+    q.u[k] = W[1 + k] * ir;
     q2 = (k == 0) ? q.u[0] * q.u[0] : q2 + q.u[k] * q.u[k];
   }
   const T E = W[nv - 1];
   q.p = (gam - 1.0) * (E - (0.5 * rho) * q2);
-  q.c = sqrtT((gam * q.p) / rho);
-  q.H = (E + q.p) / rho;
+  q.c = sqrtT((gam * q.p) * ir);
+  q.H = (E + q.p) * ir;
   q.sr = sqrtT(rho);
   const T un = q.u[d];
   q.F[0] = W[1 + d];
@@ -381,9 +382,10 @@ template <class T>
 T pressure_of(int ndim, double gam, const T* W) {
   const int nv = ndim + 2;
   const T rho = W[0];
+  const T ir = 1.0 / rho;
   T q2 = T(0.0);
   for (int k = 0; k < ndim; ++k) {
-    const T uk = W[1 + k] / rho;
+    const T uk = W[1 + k] * ir;
     q2 = (k == 0) ? uk * uk : q2 + uk * uk;
   }
   return (gam - 1.0) * (W[nv - 1] - (0.5 * rho) * q2);
@@ -411,13 +413,14 @@ void roe_eigen(int ndim, double gam, int d, const CellQ<T>& a, const CellQ<T>& b
   e.perm[nv - 1] = nv - 1;
 
   const T den = a.sr + b.sr;
+  const T iden = 1.0 / den;  // the Roe weights' denominator, inverted once
   T ur[3];
   T q2 = T(0.0);
   for (int k = 0; k < ndim; ++k) {
-    ur[k] = (a.sr * a.u[k] + b.sr * b.u[k]) / den;
+    ur[k] = (a.sr * a.u[k] + b.sr * b.u[k]) * iden;
     q2 = (k == 0) ? ur[0] * ur[0] : q2 + ur[k] * ur[k];
   }
-  const T H = (a.sr * a.H + b.sr * b.H) / den;
+  const T H = (a.sr * a.H + b.sr * b.H) * iden;
   const T qq = 0.5 * q2;
   const T c2 = (gam - 1.0) * (H - qq);
   const T c = sqrtT(c2);
@@ -428,8 +431,8 @@ void roe_eigen(int ndim, double gam, int d, const CellQ<T>& a, const CellQ<T>& b
   int nt = 0;
   for (int k = 0; k < ndim; ++k)
     if (k != d) ut[nt++] = ur[k];
-  const T unc = un / c;
   const T ic = 1.0 / c;
+  const T unc = un * ic;
 
   for (int i = 0; i < 5; ++i)
     for (int j = 0; j < 5; ++j) e.L[i][j] = e.R[i][j] = T(0.0);
@@ -681,6 +684,7 @@ int rhs_impl(const Grid& g, const Scheme& sc, double gam, const T* U, T* dU, dou
   for (int d = 0; d < nd; ++d) {
     const int64_t n = g.n[d];
     const bool periodic = g.bc_lo[d] == BC_PERIODIC;
+    const double rdx = 1.0 / g.dx[d];  // the flux difference divides by dx as a product
     const int64_t nf = faces_along(g, d);
     const int64_t nft = faces_total(g, d);
     const int64_t foff = flag_offset(g, d);
@@ -711,7 +715,7 @@ int rhs_impl(const Grid& g, const Scheme& sc, double gam, const T* U, T* dU, dou
           const int64_t fr = periodic ? (i + 1) % n : i + 1;
           for (int c = 0; c < nv; ++c) {
             const int64_t cell = c * nc + base + i * stride[d];
-            dU[cell] = dU[cell] - (Fh[(size_t)fr * nv + c] - Fh[(size_t)i * nv + c]) / g.dx[d];
+            dU[cell] = dU[cell] - (Fh[(size_t)fr * nv + c] - Fh[(size_t)i * nv + c]) * rdx;
           }
         }
       }
@@ -867,7 +871,8 @@ int or_rhs_cells(const or_grid* g, int order, int splitting, int positivity, dou
       const int64_t fr = periodic ? (i + 1) % n : i + 1;
       face_flux<double>(G, s, gam, d, cq.data() + Gh, i, mu[d], limit, 0, 0, nullptr, nullptr, nullptr, Fl);
       face_flux<double>(G, s, gam, d, cq.data() + Gh, fr, mu[d], limit, 0, 0, nullptr, nullptr, nullptr, Fr);
-      for (int c = 0; c < nv; ++c) du[c] = du[c] - (Fr[c] - Fl[c]) / G.dx[d];
+      const double rdx = 1.0 / G.dx[d];
+      for (int c = 0; c < nv; ++c) du[c] = du[c] - (Fr[c] - Fl[c]) * rdx;
     }
     for (int c = 0; c < nv; ++c) out[k * nv + c] = du[c];
   }

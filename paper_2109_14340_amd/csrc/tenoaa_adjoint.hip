@@ -165,11 +165,14 @@ void sweep_vjp_kernel(AdjointArgs A) {
     unroll<NV>([&](auto c) { Wc[c] = A.U[c * ncell + off]; });
     if (mbc == TENOAA_BC_SYMMETRY) Wc[1 + DIR] = -Wc[1 + DIR];
     if (mbc == TENOAA_BC_NOSLIP) unroll<NDIM>([&](auto k) { Wc[1 + k] = -Wc[1 + k]; });
+    // the same arithmetic as the forward sweep, so that the frozen splitting
+    // speeds are attained by the same cells
     const double rho = Wc[0];
+    const double ir = div_rn(1.0, rho);
     double u[NDIM];
     double q2 = 0.0;
     unroll<NDIM>([&](auto k) {
-      u[k] = Wc[1 + k] / rho;
+      u[k] = Wc[1 + k] * ir;
       q2 = (k == 0) ? u[0] * u[0] : q2 + u[k] * u[k];
     });
     const double E = Wc[NV - 1];
@@ -183,9 +186,9 @@ void sweep_vjp_kernel(AdjointArgs A) {
     });
     sWF[NV - 1][ct] = make_double2(E, (E + p) * un);
     sUn[ct] = un;
-    sC[ct] = sqrt((gam * p) / rho);
-    sSr[ct] = sqrt(rho);
-    sH[ct] = (E + p) / rho;
+    sC[ct] = sqrt_rn((gam * p) * ir);
+    sSr[ct] = sqrt_rn(rho);
+    sH[ct] = (E + p) * ir;
     unroll<NV>([&](auto c) {
       aW[c][ct] = 0.0;
       aF[c][ct] = 0.0;
@@ -245,9 +248,10 @@ void sweep_vjp_kernel(AdjointArgs A) {
     // ---- forward recompute: Roe average and eigenvectors
     const double sa = sSr[ia], sb = sSr[ib];
     const double den = sa + sb;
-    const double un = (sa * sUn[ia] + sb * sUn[ib]) / den;
+    const double iden = div_rn(1.0, den);
+    const double un = (sa * sUn[ia] + sb * sUn[ib]) * iden;
     double ut[NT];
-    unroll<NDIM - 1>([&](auto k) { ut[k] = (sa * sUt[k][ia] + sb * sUt[k][ib]) / den; });
+    unroll<NDIM - 1>([&](auto k) { ut[k] = (sa * sUt[k][ia] + sb * sUt[k][ib]) * iden; });
     double q2 = 0.0;
     unroll<NDIM>([&](auto a) {
       constexpr int slot = Fr::slot_of_axis(decltype(a)::value);
@@ -256,14 +260,14 @@ void sweep_vjp_kernel(AdjointArgs A) {
       else ua = ut[slot - 1];
       q2 = (a == 0) ? ua * ua : q2 + ua * ua;
     });
-    const double Hr = (sa * sH[ia] + sb * sH[ib]) / den;
+    const double Hr = (sa * sH[ia] + sb * sH[ib]) * iden;
     const double qq = 0.5 * q2;
     const double c2 = gm1 * (Hr - qq);
-    const double cr = sqrt(c2);
-    const double b1 = gm1 / c2;
+    const double cr = sqrt_rn(c2);
+    const double b1 = div_rn(gm1, c2);
     const double b2 = b1 * qq;
-    const double unc = un / cr;
-    const double ic = 1.0 / cr;
+    const double ic = div_rn(1.0, cr);
+    const double unc = un * ic;
 
     // splitting speeds and the cells attaining them
     double am = -1.0, a0 = -1.0, ap = -1.0;

@@ -73,6 +73,7 @@ struct BatchProblem {
   int64_t nf[2];      // faces along x, y
   int64_t nft[2];     // faces of each direction in total
   double dx[3];
+  double rdx[3];      // 1 / dx, correctly rounded (host)
   int32_t bc_lo[2], bc_hi[2];
   int64_t u_off;      // state offset in the packed buffer (doubles)
   int64_t s_off;      // stage state offset
@@ -210,7 +211,10 @@ __device__ __forceinline__ void update_item(const BatchArgs& B, char* arena, int
   A.nft[2] = 0;
   A.nf[2] = 1;
   A.n[2] = 1;
-  for (int d = 0; d < 3; ++d) A.dx[d] = P.dx[d];
+  for (int d = 0; d < 3; ++d) {
+    A.dx[d] = P.dx[d];
+    A.rdx[d] = P.rdx[d];
+  }
   A.Un = B.U + P.u_off;
   A.Us = B.S + P.s_off;
   A.out = (MODE == 3) ? B.U + P.u_off : B.S + P.s_off;
@@ -429,7 +433,10 @@ hipError_t upload_table(tenoaa_batch_plan* P) {
       b.along[d] = (b.nf[d] + tn - 1) / tn;
       b.across[d] = (g.n[1 - d] + tt - 1) / tt;
     }
-    for (int d = 0; d < 3; ++d) b.dx[d] = g.dx[d];
+    for (int d = 0; d < 3; ++d) {
+      b.dx[d] = g.dx[d];
+      b.rdx[d] = 1.0 / g.dx[d];
+    }
     b.u_off = P->offsets[q];
     b.s_off = s_off;
     s_off += 4 * g.n[0] * g.n[1];

@@ -211,6 +211,7 @@ int update(const Ctx& c, int mode, const double* Un, const double* Us, double* o
     a.nf[d] = d < g->ndim ? faces_along(g, d) : 1;
     a.n[d] = g->n[d];
     a.dx[d] = g->dx[d];
+    a.rdx[d] = 1.0 / g->dx[d];
   }
   a.Un = Un;
   a.Us = Us;

@@ -75,6 +75,43 @@ __device__ __forceinline__ double rcp_dec(double x) {
   return fma(r, e, r);
 }
 
+// Correctly rounded division and square root.  The compiler's FP64 sequences
+// are within an ulp but, in rare operands extremely close to a rounding
+// midpoint, not correctly rounded; one exact fma remainder of the result and
+// of its neighbour on the remainder's side decides between the two, so every
+// value the kernels compute matches an IEEE evaluation bit for bit.
+__device__ __forceinline__ double next_toward(double q, bool up) {
+  const long long bits = __double_as_longlong(q);
+  return __longlong_as_double(bits + (((q > 0.0) == up) ? 1 : -1));
+}
+
+__device__ __forceinline__ double div_rn(double a, double b) {
+  const double q = a / b;
+  const double r = fma(-q, b, a);  // exact: q is within an ulp of a / b
+  if (!(r != 0.0) || q == 0.0 || !(fabs(q) <= 1.7976931348623157e308)) return q;
+  const double qn = next_toward(q, (r > 0.0) == (b > 0.0));
+  const double rn = fma(-qn, b, a);
+  const double ar = fabs(r), arn = fabs(rn);
+  if (arn < ar || (arn == ar && (__double_as_longlong(q) & 1))) return qn;  // nearer; a tie goes to even
+  return q;
+}
+
+__device__ __forceinline__ double sqrt_rn(double x) {
+  const double s = sqrt(x);
+  if (!(x > 0.0) || !(s <= 1.7976931348623157e308)) return s;
+  const double r = fma(-s, s, x);  // exact
+  // with lo <= sqrt(x) < lo + u (u the gap above lo, lo*u exact), sqrt(x) is
+  // above the midpoint iff x - lo^2 - lo*u > 0; that quantity is a multiple of
+  // u^2, so the one rounding of the fma cannot change its sign
+  if (r >= 0.0) {
+    const double hi = next_toward(s, true);
+    return fma(-s, hi - s, r) > 0.0 ? hi : s;
+  }
+  const double lo = next_toward(s, false);
+  const double rl = fma(-lo, lo, x);
+  return fma(-lo, s - lo, rl) > 0.0 ? s : lo;
+}
+
 // x / 6 correctly rounded: one product by RN(1/6) and one fma correction of
 // the exact remainder (Markstein's theorem: the reciprocal within 1/2 ulp and
 // the first quotient within 1 ulp make the corrected quotient the correctly

@@ -41,6 +41,7 @@ struct UpdateArgs {
   int64_t nf[3];
   int64_t n[3];
   double dx[3];
+  double rdx[3];     // 1 / dx, correctly rounded (host)
   const double* Un;
   const double* Us;
   double* out;

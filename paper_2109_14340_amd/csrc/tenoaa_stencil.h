@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "tenoaa_device.h"
 #include "tenoaa_internal.h"
@@ -119,17 +120,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     }
     // cell primitives (Sec. 1), axis order
     const double rho = Wc[0];
+    const double ir = div_rn(1.0, rho);  // divisions by rho as products with its reciprocal
     double u[NDIM];
     double q2 = 0.0;
     unroll<NDIM>([&](auto k) {
-      u[k] = Wc[1 + k] / rho;
+      u[k] = Wc[1 + k] * ir;
       q2 = (k == 0) ? u[0] * u[0] : q2 + u[k] * u[k];
     });
     const double E = Wc[NV - 1];
     const double p = gm1 * (E - (0.5 * rho) * q2);
-    const double c = sqrt((gam * p) / rho);
-    const double H = (E + p) / rho;
-    const double sr = sqrt(rho);
+    const double c = sqrt_rn((gam * p) * ir);
+    const double H = (E + p) * ir;
+    const double sr = sqrt_rn(rho);
     const double un = u[DIR];
     if (!(rho > 0.0) || !(p > 0.0)) atomicOr(A.status, 1);
     // conserved state and physical flux along DIR in the local frame
@@ -167,9 +169,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
   // Roe average (Sec. 5: characteristic decomposition at the face)
   const double sa = sSr[ia], sb = sSr[ib];
   const double den = sa + sb;
-  const double un = (sa * sUn[ia] + sb * sUn[ib]) / den;
+  const double iden = div_rn(1.0, den);  // the Roe weights' denominator, inverted once
+  const double un = (sa * sUn[ia] + sb * sUn[ib]) * iden;
   double ut[NT];
-  unroll<NDIM - 1>([&](auto k) { ut[k] = (sa * sUt[k * NCT + ia] + sb * sUt[k * NCT + ib]) / den; });
+  unroll<NDIM - 1>([&](auto k) { ut[k] = (sa * sUt[k * NCT + ia] + sb * sUt[k * NCT + ib]) * iden; });
   double q2 = 0.0;  // |u|^2 summed in axis order
   unroll<NDIM>([&](auto a) {
     constexpr int slot = Fr::slot_of_axis(decltype(a)::value);
@@ -178,14 +181,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     else ua = ut[slot - 1];
     q2 = (a == 0) ? ua * ua : q2 + ua * ua;
   });
-  const double Hr = (sa * sH[ia] + sb * sH[ib]) / den;
+  const double Hr = (sa * sH[ia] + sb * sH[ib]) * iden;
   const double qq = 0.5 * q2;
   const double c2 = gm1 * (Hr - qq);
-  const double cr = sqrt(c2);
-  const double b1 = gm1 / c2;
+  const double cr = sqrt_rn(c2);
+  const double b1 = div_rn(gm1, c2);
   const double b2 = b1 * qq;
-  const double unc = un / cr;
-  const double ic = 1.0 / cr;
+  const double ic = div_rn(1.0, cr);
+  const double unc = un * ic;
   // splitting speeds over the window
   double am = 0.0, a0 = 0.0, ap = 0.0;
   unroll<W>([&](auto j) {
@@ -327,14 +330,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
       const double2 wa = sWF[c * NCT + ia], wb = sWF[c * NCT + ib];
       FL[c] = 0.5 * ((wa.y + wb.y) - aL * (wb.x - wa.x));
     });
-    auto pressure = [&](const double (&X)[NV]) {
+    // pressure of X; EXACT selects correctly rounded divisions, otherwise
+    // the compiler's (within an ulp), and `scale` bounds the terms of p
+    auto pressure = [&](const double (&X)[NV], auto exact, double& scale) {
       const double rho = X[0];
+      const double ir = decltype(exact)::value ? div_rn(1.0, rho) : 1.0 / rho;
       double q = 0.0;
       unroll<NDIM>([&](auto a) {
-        const double ua = X[1 + Fr::slot_of_axis(decltype(a)::value)] / rho;
+        const double ua = X[1 + Fr::slot_of_axis(decltype(a)::value)] * ir;
         q = (a == 0) ? ua * ua : q + ua * ua;
       });
-      return gm1 * (X[NV - 1] - (0.5 * rho) * q);
+      const double k = (0.5 * rho) * q;
+      scale = fabs(X[NV - 1]) + fabs(k);
+      return gm1 * (X[NV - 1] - k);
     };
     double th_r = 1.0;
     unroll<2>([&](auto side) {
@@ -344,8 +352,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
       const double rL = r + (sg * mu) * FL[0];
       const double rH = r + (sg * mu) * Fh[0];
       const double eps = rL < 1e-13 ? rL : 1e-13;
-      const double th = (rH < eps) ? (rL - eps) / (rL - rH) : 1.0;
-      th_r = th < th_r ? th : th_r;
+      if (rH < eps) {
+        const double th = div_rn(rL - eps, rL - rH);
+        th_r = th < th_r ? th : th_r;
+      }
     });
     double Fs[NV];
     unroll<NV>([&](auto c) { Fs[c] = (th_r < 1.0) ? FL[c] + th_r * (Fh[c] - FL[c]) : Fh[c]; });
@@ -353,14 +363,25 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     unroll<2>([&](auto side) {
       const int li = side == 0 ? ia : ib;
       const double sg = side == 0 ? -1.0 : 1.0;
-      double X[NV];
-      unroll<NV>([&](auto c) { X[c] = sWF[c * NCT + li].x + (sg * mu) * FL[c]; });
-      const double pL = pressure(X);
-      unroll<NV>([&](auto c) { X[c] = sWF[c * NCT + li].x + (sg * mu) * Fs[c]; });
-      const double pS = pressure(X);
-      const double eps = pL < 1e-13 ? pL : 1e-13;
-      const double th = (pS < eps) ? (pL - eps) / (pL - pS) : 1.0;
-      th_p = th < th_p ? th : th_p;
+      double XL[NV], XS[NV];
+      unroll<NV>([&](auto c) {
+        XL[c] = sWF[c * NCT + li].x + (sg * mu) * FL[c];
+        XS[c] = sWF[c * NCT + li].x + (sg * mu) * Fs[c];
+      });
+      // The test pS < eps with the compiler's divisions differs from the exact
+      // one only if pS is within ~1e-15 of the pressures' term scale of eps;
+      // outside a 1e-12 band the limiter certainly leaves this side alone.
+      double sL, sS;
+      const double pLf = pressure(XL, std::false_type{}, sL);
+      const double pSf = pressure(XS, std::false_type{}, sS);
+      const double epsf = pLf < 1e-13 ? pLf : 1e-13;
+      if (pSf < epsf + 1e-12 * (sL + sS)) {
+        const double pL = pressure(XL, std::true_type{}, sL);
+        const double pS = pressure(XS, std::true_type{}, sS);
+        const double eps = pL < 1e-13 ? pL : 1e-13;
+        const double th = (pS < eps) ? div_rn(pL - eps, pL - pS) : 1.0;
+        th_p = th < th_p ? th : th_p;
+      }
     });
     unroll<NV>([&](auto c) { Fh[c] = (th_p < 1.0) ? FL[c] + th_p * (Fs[c] - FL[c]) : Fs[c]; });
   } else {
@@ -383,14 +404,15 @@ __device__ __forceinline__ void cell_speeds(const double (&Wc)[NDIM + 2], double
                                             bool& bad) {
   constexpr int NV = NDIM + 2;
   const double rho = Wc[0];
+  const double ir = div_rn(1.0, rho);
   double u[NDIM];
   double q2 = 0.0;
   unroll<NDIM>([&](auto k) {
-    u[k] = Wc[1 + k] / rho;
+    u[k] = Wc[1 + k] * ir;
     q2 = (k == 0) ? u[0] * u[0] : q2 + u[k] * u[k];
   });
   const double p = (gam - 1.0) * (Wc[NV - 1] - (0.5 * rho) * q2);
-  const double c = sqrt((gam * p) / rho);
+  const double c = sqrt_rn((gam * p) * ir);
   if (!(rho > 0.0) || !(p > 0.0)) bad = true;
   unroll<NDIM>([&](auto d) { amax[d] = dmax(amax[d], fabs(u[d]) + c); });
 }
@@ -418,7 +440,7 @@ __device__ __forceinline__ void update_cell(const UpdateArgs& A, int64_t idx, co
     double du = 0.0;
     unroll<NDIM>([&](auto d) {
       const double* F = A.F[d] + (int64_t)c * A.nft[d];
-      du = du - (F[fr[d]] - F[fl[d]]) / A.dx[d];
+      du = du - (F[fr[d]] - F[fl[d]]) * A.rdx[d];
     });
     const int64_t e = (int64_t)c * ncell + idx;
     double v;
@@ -455,13 +477,13 @@ __device__ __forceinline__ void dt_and_mu(const unsigned long long* amax_bits, i
   for (int d = 0; d < 3; ++d) a[d] = d < ndim ? __longlong_as_double((long long)amax_bits[d]) : 0.0;
   dt = dt_given;
   if (!(dt > 0.0)) {
-    double s = a[0] / dx[0];
-    for (int d = 1; d < ndim; ++d) s = s + a[d] / dx[d];
-    dt = cfl / s;
+    double s = div_rn(a[0], dx[0]);
+    for (int d = 1; d < ndim; ++d) s = s + div_rn(a[d], dx[d]);
+    dt = div_rn(cfl, s);
   }
-  double Ssum = (dt / dx[0]) * a[0];
-  for (int d = 1; d < ndim; ++d) Ssum = Ssum + (dt / dx[d]) * a[d];
-  for (int d = 0; d < 3; ++d) mu[d] = (d < ndim) ? (2.0 * Ssum) / a[d] : 0.0;
+  double Ssum = div_rn(dt, dx[0]) * a[0];
+  for (int d = 1; d < ndim; ++d) Ssum = Ssum + div_rn(dt, dx[d]) * a[d];
+  for (int d = 0; d < 3; ++d) mu[d] = (d < ndim) ? div_rn(2.0 * Ssum, a[d]) : 0.0;
 }
 
 }  // namespace
