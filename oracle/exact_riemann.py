@@ -3,7 +3,10 @@ ideal gas: TEST INFRASTRUCTURE ONLY (the reference for the shock-tube
 validation cases of the paper's Sec. 5, whose figures compare with the
 theoretical Riemann solutions).  Only tests/ may import it.
 
-The solution is self-similar in xi = (x - x0)/t.  The star pressure p* solves
+The solution is self-similar in xi = (x - x0)/t.  When the two rarefactions
+cannot meet (2 (c_L + c_R) / (gamma - 1) <= u_R - u_L) a vacuum opens between
+their fronts u_L + 2 c_L / (gamma - 1) and u_R - 2 c_R / (gamma - 1).
+Otherwise the star pressure p* solves
 f_L(p*) + f_R(p*) + (u_R - u_L) = 0, where f_K is the velocity jump across the
 K wave: a shock (Rankine-Hugoniot) when p* > p_K, a rarefaction (isentropic,
 Riemann invariant) otherwise.  Newton's method on p with a positive starting
@@ -52,10 +55,47 @@ def star_state(left, right, g=1.4, tol=1e-14, maxit=100):
     return p, u
 
 
-def sample(left, right, xi, g=1.4):
-    """Primitive (rho, u, p) arrays of the exact solution at xi = (x - x0)/t."""
+def _sample_vacuum(left, right, xi, g):
     rl, ul, pl = left
     rr, ur, pr = right
+    cl, cr = math.sqrt(g * pl / rl), math.sqrt(g * pr / rr)
+    rho = np.zeros_like(xi)
+    u = np.zeros_like(xi)
+    p = np.zeros_like(xi)
+    sl, sr = ul + 2.0 * cl / (g - 1.0), ur - 2.0 * cr / (g - 1.0)
+    # left state, left fan up to the vacuum front
+    a = xi < ul - cl
+    rho[a], u[a], p[a] = rl, ul, pl
+    f = (xi >= ul - cl) & (xi < sl)
+    uf = 2.0 / (g + 1.0) * (cl + (g - 1.0) / 2.0 * ul + xi[f])
+    cf = uf - xi[f]
+    rho[f] = rl * (cf / cl) ** (2.0 / (g - 1.0))
+    p[f] = pl * (cf / cl) ** (2.0 * g / (g - 1.0))
+    u[f] = uf
+    # right fan from the vacuum front, right state
+    f = (xi > sr) & (xi <= ur + cr)
+    uf = 2.0 / (g + 1.0) * (-cr + (g - 1.0) / 2.0 * ur + xi[f])
+    cf = xi[f] - uf
+    rho[f] = rr * (cf / cr) ** (2.0 / (g - 1.0))
+    p[f] = pr * (cf / cr) ** (2.0 * g / (g - 1.0))
+    u[f] = uf
+    b = xi > ur + cr
+    rho[b], u[b], p[b] = rr, ur, pr
+    return rho, u, p
+
+
+def generates_vacuum(left, right, g=1.4):
+    cl, cr = math.sqrt(g * left[2] / left[0]), math.sqrt(g * right[2] / right[0])
+    return 2.0 * (cl + cr) / (g - 1.0) <= right[1] - left[1]
+
+
+def sample(left, right, xi, g=1.4):
+    """Primitive (rho, u, p) arrays of the exact solution at xi = (x - x0)/t
+    (zero density and pressure, and u = 0, in a vacuum)."""
+    rl, ul, pl = left
+    rr, ur, pr = right
+    if generates_vacuum(left, right, g):
+        return _sample_vacuum(left, right, np.asarray(xi, dtype=np.float64), g)
     ps, us = star_state(left, right, g)
     xi = np.asarray(xi, dtype=np.float64)
     rho = np.empty_like(xi)

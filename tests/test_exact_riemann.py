@@ -80,3 +80,23 @@ def test_equal_states_give_a_uniform_solution():
     s = (1.3, 0.4, 2.0)
     ps, us = er.star_state(s, s, G)
     assert abs(ps - 2.0) <= 1e-13 and abs(us - 0.4) <= 1e-13
+
+
+def test_double_rarefaction_vacuum():
+    """Sec. 5's double rarefaction opens a vacuum: the fans end at the fronts
+    u_L + 2 c_L/(gamma-1) and u_R - 2 c_R/(gamma-1), with the Riemann
+    invariants carried through them, and mass is conserved."""
+    left, right = (1.0, -2.0, 0.1), (1.0, 2.0, 0.1)
+    assert er.generates_vacuum(left, right, G)
+    c = math.sqrt(G * 0.1)
+    front = -2.0 + 2 * c / (G - 1)
+    xi = np.linspace(-2.0 - c, front - 1e-9, 51)
+    rho, u, p = er.sample(left, right, xi, G)
+    cs = np.sqrt(G * p / rho)
+    assert np.allclose(u + 2 * cs / (G - 1), -2.0 + 2 * c / (G - 1), rtol=1e-12)
+    assert np.allclose(p / rho ** G, 0.1, rtol=1e-10)
+    rho0, _, p0 = er.sample(left, right, np.array([0.0, front + 1e-9]), G)
+    assert np.all(rho0 == 0.0) and np.all(p0 == 0.0)
+    # mass of the exact solution on [0, 1] at t = 0.1: 1 - t (flux_R - flux_L) = 1 - 0.1 * (2 + 2)
+    U = er.cell_averages(left, right, 0.5, 0.1, 2000, G, sub=256).sum(axis=1) / 2000
+    assert abs(U[0] - (1.0 - 0.1 * 4.0)) <= 2e-5
