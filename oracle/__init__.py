@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tenoaa_oracle.cpp")
 _LIB = os.path.join(_HERE, "libtenoaa_oracle.so")
 
-BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP = 0, 1, 2, 3
+BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP, BC_DIRICHLET = 0, 1, 2, 3, 4
 LLF, RUSANOV = 0, 1
 
 
@@ -33,9 +33,10 @@ def build():
 
 
 class OrGrid(ctypes.Structure):
-    _fields_ = [("ndim", ctypes.c_int32), ("pad", ctypes.c_int32),
+    _fields_ = [("ndim", ctypes.c_int32), ("bc_sets", ctypes.c_int32),
                 ("n", ctypes.c_int64 * 3), ("dx", ctypes.c_double * 3),
-                ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3)]
+                ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3),
+                ("bc_values", (ctypes.c_void_p * 2) * 3)]
 
 
 _lib = None
@@ -94,11 +95,18 @@ def _u8(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if a is not None else None
 
 
-def make_grid(shape, dx, bc_lo, bc_hi=None):
-    """shape = (nx,) / (nx, ny) / (nx, ny, nz) in axis order; bc per axis."""
+def make_grid(shape, dx, bc_lo, bc_hi=None, bc_values=None):
+    """shape = (nx,) / (nx, ny) / (nx, ny, nz) in axis order; bc per axis.
+
+    bc_values: {(d, side): array} for the Dirichlet sides (side 0 low, 1 high),
+    each of shape (sets, nvar, plane) or (nvar, plane) with the primitives
+    (rho, u_x, [u_y], [u_z], p) over the face plane of direction d (the grid
+    without axis d, lower remaining axis fastest); sets is 1 or 3 (one per
+    SSP-RK3 stage) and the same for every side."""
     ndim = len(shape)
     g = OrGrid()
     g.ndim = ndim
+    g.bc_sets = 1
     for d in range(3):
         g.n[d] = shape[d] if d < ndim else 1
         g.dx[d] = (dx[d] if d < ndim else 1.0)
@@ -106,6 +114,13 @@ def make_grid(shape, dx, bc_lo, bc_hi=None):
         hi = (bc_hi if bc_hi is not None else bc_lo)[d] if d < ndim else 0
         g.bc_lo[d] = lo
         g.bc_hi[d] = hi
+    g._keep = []
+    for (d, side), v in (bc_values or {}).items():
+        plane = int(np.prod([g.n[k] for k in range(3) if k != d]))
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, ndim + 2, plane)
+        g.bc_sets = v.shape[0]
+        g._keep.append(v)
+        g.bc_values[d][side] = v.ctypes.data
     return g
 
 

@@ -343,8 +343,12 @@ struct Grid {
   int64_t n[3];
   double dx[3];
   int bc_lo[3], bc_hi[3];
+  // Dirichlet face values of side (d, 0 = low / 1 = high): bc_sets sets of
+  // nv planes of primitives (rho, u_x, [u_y], [u_z], p) over the face plane
+  int bc_sets;
+  const double* bc_values[3][2];
 };
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_SYMMETRY = 2, BC_NOSLIP = 3 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_SYMMETRY = 2, BC_NOSLIP = 3, BC_DIRICHLET = 4 };
 
 template <class T>
 struct CellQ {
@@ -550,9 +554,40 @@ int64_t flag_offset(const Grid& g, int d) {
   return off;
 }
 
-// Ghost cells in conserved variables along one pencil (Appendix A).
+// Dirichlet ghost cell (Appendix A): in primitive variables the ghost is the
+// mirror cell reflected through the prescribed face value,
+// (rho, u, p)_ghost = 2 (rho, u, p)_face - (rho, u, p)_mirror, which makes the
+// face value the second-order average of the two.  fv points at the face's
+// density; its velocities and pressure follow at strides of `plane`.
 template <class T>
-void fill_ghosts(int ndim, int d, int bc, bool low, int64_t n, int G, std::vector<T>& line) {
+void dirichlet_ghost(int ndim, double gam, const T* m, const double* fv, int64_t plane, T* out) {
+  const int nv = ndim + 2;
+  const T rho = m[0];
+  const T ir = 1.0 / rho;
+  T u[3];
+  T q2 = T(0.0);
+  for (int k = 0; k < ndim; ++k) {
+    u[k] = m[1 + k] * ir;
+    q2 = (k == 0) ? u[0] * u[0] : q2 + u[k] * u[k];
+  }
+  const T p = (gam - 1.0) * (m[nv - 1] - (0.5 * rho) * q2);
+  const T rg = 2.0 * fv[0] - rho;
+  T qg = T(0.0);
+  for (int k = 0; k < ndim; ++k) {
+    const T ug = 2.0 * fv[(1 + k) * plane] - u[k];
+    out[1 + k] = rg * ug;
+    qg = (k == 0) ? ug * ug : qg + ug * ug;
+  }
+  const T pg = 2.0 * fv[(nv - 1) * plane] - p;
+  out[0] = rg;
+  out[nv - 1] = pg / (gam - 1.0) + (0.5 * rg) * qg;
+}
+
+// Ghost cells in conserved variables along one pencil (Appendix A).  fv: the
+// Dirichlet face values of this pencil's side (used when bc is Dirichlet).
+template <class T>
+void fill_ghosts(int ndim, double gam, int d, int bc, bool low, int64_t n, int G, const double* fv, int64_t plane,
+                 std::vector<T>& line) {
   const int nv = ndim + 2;
   auto at = [&](int64_t l) -> T* { return &line[(size_t)(l + G) * nv]; };
   for (int r = 1; r <= G; ++r) {
@@ -561,11 +596,32 @@ void fill_ghosts(int ndim, int d, int bc, bool low, int64_t n, int G, std::vecto
     if (bc == BC_PERIODIC) src = low ? n - r : r - 1;
     else if (bc == BC_OUTFLOW) src = low ? 0 : n - 1;
     else src = low ? r - 1 : n - r;  // mirror
+    if (bc == BC_DIRICHLET) {
+      dirichlet_ghost<T>(ndim, gam, at(src), fv, plane, at(dst));
+      continue;
+    }
     for (int c = 0; c < nv; ++c) at(dst)[c] = at(src)[c];
     if (bc == BC_SYMMETRY) at(dst)[1 + d] = -at(dst)[1 + d];
     if (bc == BC_NOSLIP)
       for (int k = 0; k < ndim; ++k) at(dst)[1 + k] = -at(dst)[1 + k];
   }
+}
+
+// Cells of the face plane of direction d (the grid without axis d).
+int64_t plane_cells(const Grid& g, int d) {
+  int64_t t = 1;
+  for (int k = 0; k < 3; ++k)
+    if (k != d) t *= g.n[k];
+  return t;
+}
+
+// Dirichlet values of side (d, hi) in value set `set` at plane cell pidx
+// (remaining axes, the lower one fastest), or null if the side is not Dirichlet.
+const double* face_values(const Grid& g, int d, int hi, int set, int64_t pidx) {
+  const int bc = hi ? g.bc_hi[d] : g.bc_lo[d];
+  if (bc != BC_DIRICHLET) return nullptr;
+  const int64_t plane = plane_cells(g, d);
+  return g.bc_values[d][hi] + (int64_t)set * (g.ndim + 2) * plane + pidx;
 }
 
 // a_d = max over cells of |u_d| + c (used for dt and the limiter weights).
@@ -651,17 +707,19 @@ void face_flux(const Grid& g, const Scheme& sc, double gam, int d, const CellQ<T
 
 // Conserved pencil of direction d through (o0, o1) with G ghost cells per
 // side, and its cell records (cells[l + G] for l = -G .. n+G-1).
+// pidx: the pencil's cell of the face plane; set: the Dirichlet value set.
 template <class T>
-void load_pencil(const Grid& g, double gam, int d, int G, const T* U, int64_t base, std::vector<T>& line,
-                 std::vector<CellQ<T>>& cells) {
+void load_pencil(const Grid& g, double gam, int d, int G, const T* U, int64_t base, int64_t pidx, int set,
+                 std::vector<T>& line, std::vector<CellQ<T>>& cells) {
   const int nd = g.ndim, nv = nd + 2;
   const int64_t n = g.n[d];
   const int64_t nc = g.n[0] * g.n[1] * g.n[2];
   const int64_t stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
+  const int64_t plane = plane_cells(g, d);
   for (int64_t l = 0; l < n; ++l)
     for (int c = 0; c < nv; ++c) line[(size_t)(l + G) * nv + c] = U[c * nc + base + l * stride[d]];
-  fill_ghosts(nd, d, g.bc_lo[d], true, n, G, line);
-  fill_ghosts(nd, d, g.bc_hi[d], false, n, G, line);
+  fill_ghosts(nd, gam, d, g.bc_lo[d], true, n, G, face_values(g, d, 0, set, pidx), plane, line);
+  fill_ghosts(nd, gam, d, g.bc_hi[d], false, n, G, face_values(g, d, 1, set, pidx), plane, line);
   for (int64_t l = -G; l < n + G; ++l) cell_state(nd, gam, d, &line[(size_t)(l + G) * nv], cells[(size_t)(l + G)]);
 }
 
@@ -669,7 +727,7 @@ void load_pencil(const Grid& g, double gam, int d, int G, const T* U, int64_t ba
 // (Sec. 2, conservative finite-difference form), directions in order x, y, z.
 template <class T>
 int rhs_impl(const Grid& g, const Scheme& sc, double gam, const T* U, T* dU, double dt_lim, const double* amax,
-             uint8_t* flags, double* margins, const uint8_t* frozen) {
+             uint8_t* flags, double* margins, const uint8_t* frozen, int set = 0) {
   const int nd = g.ndim, nv = nd + 2, G = sc.order / 2;
   const int64_t nc = g.n[0] * g.n[1] * g.n[2];
   for (int64_t i = 0; i < nv * nc; ++i) dU[i] = T(0.0);
@@ -698,7 +756,7 @@ int rhs_impl(const Grid& g, const Scheme& sc, double gam, const T* U, T* dU, dou
     for (int64_t o1 = 0; o1 < g.n[oa[1]]; ++o1) {
       for (int64_t o0 = 0; o0 < g.n[oa[0]]; ++o0) {
         const int64_t base = o0 * stride[oa[0]] + o1 * stride[oa[1]];
-        load_pencil(g, gam, d, G, U, base, line, cells);
+        load_pencil(g, gam, d, G, U, base, o0 + g.n[oa[0]] * o1, set, line, cells);
         for (int64_t f = 0; f < nf; ++f) {
           // face linear index inside the flag array of direction d
           int64_t idx[3] = {0, 0, 0};
@@ -750,7 +808,11 @@ int check_grid(const Grid& g, const Scheme& s) {
     if (d < g.ndim) {
       if (g.n[d] < s.order / 2 || g.dx[d] <= 0.0) return -1;
       if ((g.bc_lo[d] == BC_PERIODIC) != (g.bc_hi[d] == BC_PERIODIC)) return -1;
-      if (g.bc_lo[d] < 0 || g.bc_lo[d] > 3 || g.bc_hi[d] < 0 || g.bc_hi[d] > 3) return -1;
+      if (g.bc_lo[d] < 0 || g.bc_lo[d] > 4 || g.bc_hi[d] < 0 || g.bc_hi[d] > 4) return -1;
+      for (int h = 0; h < 2; ++h)
+        if ((h ? g.bc_hi[d] : g.bc_lo[d]) == BC_DIRICHLET) {
+          if (!g.bc_values[d][h] || (g.bc_sets != 1 && g.bc_sets != 3)) return -1;
+        }
     } else if (g.n[d] != 1) {
       return -1;
     }
@@ -763,23 +825,31 @@ int check_grid(const Grid& g, const Scheme& s) {
 // ------------------------------------------------------------------ C API
 extern "C" {
 
+// bc_values[d][0/1]: host arrays of the Dirichlet face values of the low/high
+// side of direction d, bc_sets (1 or 3) sets of nv planes of primitives
+// (rho, u_x, [u_y], [u_z], p) over the face plane; or_step uses set s in
+// stage s when bc_sets is 3, every other call set 0.
 struct or_grid {
   int32_t ndim;
-  int32_t pad;
+  int32_t bc_sets;
   int64_t n[3];
   double dx[3];
   int32_t bc_lo[3];
   int32_t bc_hi[3];
+  const double* bc_values[3][2];
 };
 
 static Grid to_grid(const or_grid* g) {
   Grid r;
   r.ndim = g->ndim;
+  r.bc_sets = g->bc_sets;
   for (int d = 0; d < 3; ++d) {
     r.n[d] = g->n[d];
     r.dx[d] = g->dx[d];
     r.bc_lo[d] = g->bc_lo[d];
     r.bc_hi[d] = g->bc_hi[d];
+    r.bc_values[d][0] = g->bc_values[d][0];
+    r.bc_values[d][1] = g->bc_values[d][1];
   }
   return r;
 }
@@ -865,7 +935,10 @@ int or_rhs_cells(const or_grid* g, int order, int splitting, int positivity, dou
       std::vector<double> line((size_t)(n + 2 * Gh) * nv);
       std::vector<CellQ<double>> cq((size_t)(n + 2 * Gh));
       const int64_t base = cell - co[d] * stride[d];
-      load_pencil(G, gam, d, Gh, U, base, line, cq);
+      int oa[2], no = 0;
+      for (int k2 = 0; k2 < 3; ++k2)
+        if (k2 != d) oa[no++] = k2;
+      load_pencil(G, gam, d, Gh, U, base, co[oa[0]] + G.n[oa[0]] * co[oa[1]], 0, line, cq);
       double Fl[5], Fr[5];
       const int64_t i = co[d];
       const int64_t fr = periodic ? (i + 1) % n : i + 1;
@@ -915,10 +988,10 @@ int or_step_jvp(const or_grid* g, int order, int splitting, double gam, const do
   double a[3] = {0, 0, 0};
   rhs_impl<Dual>(G, s, gam, Un.data(), L.data(), 0.0, a, nullptr, nullptr, flags3);
   for (int64_t i = 0; i < N; ++i) U1[(size_t)i] = Un[(size_t)i] + dt * L[(size_t)i];
-  rhs_impl<Dual>(G, s, gam, U1.data(), L.data(), 0.0, a, nullptr, nullptr, flags3 + nfl);
+  rhs_impl<Dual>(G, s, gam, U1.data(), L.data(), 0.0, a, nullptr, nullptr, flags3 + nfl, G.bc_sets == 3 ? 1 : 0);
   for (int64_t i = 0; i < N; ++i)
     U2[(size_t)i] = 0.75 * Un[(size_t)i] + 0.25 * U1[(size_t)i] + (0.25 * dt) * L[(size_t)i];
-  rhs_impl<Dual>(G, s, gam, U2.data(), L.data(), 0.0, a, nullptr, nullptr, flags3 + 2 * nfl);
+  rhs_impl<Dual>(G, s, gam, U2.data(), L.data(), 0.0, a, nullptr, nullptr, flags3 + 2 * nfl, G.bc_sets == 3 ? 2 : 0);
   for (int64_t i = 0; i < N; ++i) {
     const Dual u3 = (1.0 / 3.0) * Un[(size_t)i] + (2.0 / 3.0) * U2[(size_t)i] + ((2.0 / 3.0) * dt) * L[(size_t)i];
     jvp[i] = u3.d;
@@ -943,7 +1016,7 @@ int or_step(const or_grid* g, int order, int splitting, int positivity, double g
   const double h = *dt;
   ssp_rk3(N, h, U, [&](int st, const double* in, double* out) {
     rhs_impl<double>(G, s, gam, in, out, h, a, flags3 ? flags3 + st * nfl : nullptr,
-                     margins3 ? margins3 + st * nfl : nullptr, nullptr);
+                     margins3 ? margins3 + st * nfl : nullptr, nullptr, G.bc_sets == 3 ? st : 0);
   });
   return 0;
 }

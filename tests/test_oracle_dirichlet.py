@@ -1,0 +1,145 @@
+"""Pins of the oracle's Dirichlet boundary (Appendix A: in primitive variables
+the ghost cell is the mirror cell reflected through the prescribed face value,
+which makes that face value the second-order average of the two).
+
+* A state whose primitives are linear in space, with face values taken from
+  the same linear functions, has ghost cells that continue it exactly: the
+  right-hand side on the grid equals, to rounding, the right-hand side of a
+  grid that is larger by the ghost width and holds those cells (a mirror
+  index off by one, a reflection of conserved instead of primitive variables,
+  or a wrong face-plane ordering each break it).
+* A uniform state with matching face values is steady.
+* Per-stage value sets: the stage-s set enters stage s of SSP-RK3, so values
+  at t, t + dt and t + dt/2 keep the scheme's accuracy at an inflow boundary
+  in time; a set order that does not match the stage times loses it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2109_14340_amd import inputs
+
+G_ = 1.4
+
+
+def _prims(X, nd):
+    """Primitives linear in the coordinates X[0..nd-1]."""
+    x = X[0]
+    y = X[1] if nd > 1 else 0.0 * x
+    z = X[2] if nd > 2 else 0.0 * x
+    rho = 1.0 + 0.3 * x + 0.2 * y - 0.1 * z
+    vel = [0.4 - 0.2 * x + 0.1 * y + 0.05 * z, -0.3 + 0.15 * x - 0.1 * y + 0.2 * z, 0.2 + 0.1 * x + 0.1 * y - 0.25 * z]
+    p = 1.0 + 0.25 * x - 0.15 * y + 0.1 * z
+    return rho, vel[:nd], p
+
+
+def _state(shape, dx, offset):
+    nd = len(shape)
+    ax = [(np.arange(shape[k]) + 0.5 - offset) * dx[k] for k in range(nd)]
+    X = np.meshgrid(*ax, indexing="ij")
+    rho, vel, p = _prims(X, nd)
+    return inputs._as_layout(inputs.conserved_from_primitive(rho, vel, p, G_), nd)
+
+
+def _face_planes(shape, dx):
+    """{(d, side): (nvar, plane)} primitives of the linear state at the boundary faces."""
+    nd = len(shape)
+    out = {}
+    for d in range(nd):
+        rest = [k for k in range(3) if k != d]
+        for side in (0, 1):
+            coords = []
+            for k in range(3):
+                if k >= nd:
+                    coords.append(np.zeros(1))
+                elif k == d:
+                    coords.append(np.array([0.0 if side == 0 else shape[d] * dx[d]]))
+                else:
+                    coords.append((np.arange(shape[k]) + 0.5) * dx[k])
+            # plane order: the lower remaining axis fastest
+            Xr = np.meshgrid(coords[rest[1]], coords[rest[0]], indexing="ij")
+            X = [None] * 3
+            X[rest[0]] = Xr[1].ravel()
+            X[rest[1]] = Xr[0].ravel()
+            X[d] = np.full(X[rest[0]].shape, coords[d][0])
+            rho, vel, p = _prims(X, nd)
+            out[(d, side)] = np.stack([rho] + list(vel) + [p])
+    return out
+
+
+@pytest.mark.parametrize("order", [8, 10])
+@pytest.mark.parametrize("shape", [(24,), (14, 11), (10, 9, 8)])
+def test_linear_state_continues_through_dirichlet_ghosts(order, shape):
+    nd = len(shape)
+    G = order // 2
+    dx = [1.0 / n for n in shape]
+    UA = _state(shape, dx, 0.0)
+    gA = oracle.make_grid(shape, dx, [oracle.BC_DIRICHLET] * nd, bc_values=_face_planes(shape, dx))
+    big = tuple(n + 2 * G for n in shape)
+    UB = _state(big, dx, G)
+    gB = oracle.make_grid(big, dx, [oracle.BC_OUTFLOW] * nd)
+    dA, fA, _ = oracle.rhs(gA, UA, order=order, gamma=G_)
+    dB, _, _ = oracle.rhs(gB, UB, order=order, gamma=G_)
+    sl = tuple(slice(G, G + shape[k]) if k < nd else slice(None) for k in reversed(range(3)))
+    inner = dB[(slice(None),) + sl]
+    scale = np.abs(inner).max()
+    assert scale > 0.1
+    assert np.abs(dA - inner).max() <= 1e-12 * scale
+    # the linear data takes the largest stencil everywhere
+    big_stencil = 3 if order == 10 else 2
+    assert np.all(fA & 3 == big_stencil)
+
+
+def test_uniform_state_with_matching_faces_is_steady():
+    shape = (12, 10, 8)
+    dx = [1.0 / n for n in shape]
+    rho, vel, p = 1.3, [0.4, -0.2, 0.3], 0.9
+    U = inputs._as_layout(inputs.conserved_from_primitive(np.full(shape, rho), [np.full(shape, v) for v in vel],
+                                                          np.full(shape, p), G_), 3)
+    fv = {}
+    for d in range(3):
+        plane = int(np.prod([shape[k] for k in range(3) if k != d]))
+        for side in (0, 1):
+            fv[(d, side)] = np.array([rho] + vel + [p])[:, None] * np.ones((1, plane))
+    g = oracle.make_grid(shape, dx, [oracle.BC_DIRICHLET] * 3, bc_values=fv)
+    dU, _, _ = oracle.rhs(g, U, order=10, gamma=G_)
+    assert np.abs(dU).max() <= 1e-12
+
+
+def _wave(x, t):
+    """Density wave carried by a uniform flow u = 1, p = 1."""
+    return 1.0 + 0.2 * np.sin(2 * np.pi * (x - t))
+
+
+def _advect_wave(n, set_times, tf=0.25, order=8):
+    """Advects the density wave on [0, 1] with Dirichlet faces at both ends
+    holding the exact solution at the stage times given by set_times(t, dt);
+    returns the max density error at tf."""
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    U = inputs._as_layout(inputs.conserved_from_primitive(_wave(x, 0.0), [np.ones(n)], np.ones(n), G_), 1)
+    t = 0.0
+    dt0 = 0.4 * dx / (1.0 + np.sqrt(G_ * 1.0 / 0.8))
+    while t < tf - 1e-14:
+        h = min(dt0, tf - t)
+        fv = {}
+        for side, xf in ((0, 0.0), (1, 1.0)):
+            sets = [np.array([_wave(xf, ts), 1.0, 1.0])[:, None] for ts in set_times(t, h)]
+            fv[(0, side)] = np.stack(sets)
+        g = oracle.make_grid((n,), [dx], [oracle.BC_DIRICHLET], bc_values=fv)
+        U, _, _, _ = oracle.step(g, U, order=order, dt=h, gamma=G_)
+        t += h
+    return np.abs(U[0, 0, 0] - _wave(x, tf)).max()
+
+
+def test_stage_value_sets_follow_the_stage_times():
+    right = lambda t, h: (t, t + h, t + 0.5 * h)  # noqa: E731  (the SSP-RK3 stage times)
+    wrong = lambda t, h: (t, t + 0.5 * h, t + h)  # noqa: E731
+    e_right = [_advect_wave(n, right) for n in (40, 80)]
+    e_wrong = [_advect_wave(n, wrong) for n in (40, 80)]
+    one = [_advect_wave(n, lambda t, h: (t,)) for n in (40, 80)]
+    rate = lambda e: np.log2(e[0] / e[1])  # noqa: E731
+    print("errors: stage times", e_right, "swapped", e_wrong, "t_n only", one)
+    assert rate(e_right) > 1.8
+    assert rate(e_wrong) < 1.5 and rate(one) < 1.5
+    assert e_right[1] < 0.5 * min(e_wrong[1], one[1])
