@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tenoaa_oracle.cpp")
 _LIB = os.path.join(_HERE, "libtenoaa_oracle.so")
 
-BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP, BC_DIRICHLET = 0, 1, 2, 3, 4
+BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP, BC_DIRICHLET, BC_INFLOW = 0, 1, 2, 3, 4, 5
 LLF, RUSANOV = 0, 1
 
 
@@ -98,11 +98,13 @@ def _u8(a):
 def make_grid(shape, dx, bc_lo, bc_hi=None, bc_values=None):
     """shape = (nx,) / (nx, ny) / (nx, ny, nz) in axis order; bc per axis.
 
-    bc_values: {(d, side): array} for the Dirichlet sides (side 0 low, 1 high),
-    each of shape (sets, nvar, plane) or (nvar, plane) with the primitives
-    (rho, u_x, [u_y], [u_z], p) over the face plane of direction d (the grid
-    without axis d, lower remaining axis fastest); sets is 1 or 3 (one per
-    SSP-RK3 stage) and the same for every side."""
+    bc_values: {(d, side): array} for the Dirichlet and inflow sides (side 0
+    low, 1 high).  Dirichlet: shape (sets, nvar, plane) or (nvar, plane), the
+    face primitives (rho, u_x, [u_y], [u_z], p) over the face plane of
+    direction d (the grid without axis d, lower remaining axis fastest).
+    Inflow: shape (sets, G, nvar, plane), the primitives of the G ghost cells
+    outward from the face (G = order / 2).  sets is 1 or 3 (one per SSP-RK3
+    stage) and the same for every side."""
     ndim = len(shape)
     g = OrGrid()
     g.ndim = ndim
@@ -117,8 +119,10 @@ def make_grid(shape, dx, bc_lo, bc_hi=None, bc_values=None):
     g._keep = []
     for (d, side), v in (bc_values or {}).items():
         plane = int(np.prod([g.n[k] for k in range(3) if k != d]))
-        v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, ndim + 2, plane)
-        g.bc_sets = v.shape[0]
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        inflow = (g.bc_hi[d] if side else g.bc_lo[d]) == BC_INFLOW
+        g.bc_sets = (v.shape[0] if v.ndim == 4 else 1) if inflow else (v.shape[0] if v.ndim == 3 else 1)
+        v = v.reshape(g.bc_sets, -1, ndim + 2, plane)
         g._keep.append(v)
         g.bc_values[d][side] = v.ctypes.data
     return g

@@ -343,12 +343,14 @@ struct Grid {
   int64_t n[3];
   double dx[3];
   int bc_lo[3], bc_hi[3];
-  // Dirichlet face values of side (d, 0 = low / 1 = high): bc_sets sets of
-  // nv planes of primitives (rho, u_x, [u_y], [u_z], p) over the face plane
+  // Boundary values of side (d, 0 = low / 1 = high), bc_sets sets each.
+  // Dirichlet: per set nv planes of face primitives (rho, u_x, [u_y], [u_z], p)
+  // over the face plane.  Inflow: per set G layers (ghost cell r = 1..G
+  // outward from the face) of nv planes of the ghost cells' primitives.
   int bc_sets;
   const double* bc_values[3][2];
 };
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_SYMMETRY = 2, BC_NOSLIP = 3, BC_DIRICHLET = 4 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_SYMMETRY = 2, BC_NOSLIP = 3, BC_DIRICHLET = 4, BC_INFLOW = 5 };
 
 template <class T>
 struct CellQ {
@@ -583,8 +585,24 @@ void dirichlet_ghost(int ndim, double gam, const T* m, const double* fv, int64_t
   out[nv - 1] = pg / (gam - 1.0) + (0.5 * rg) * qg;
 }
 
+// Prescribed ghost cell (supersonic inflow, where every characteristic
+// enters the domain): the conserved state of the given primitives.
+template <class T>
+void inflow_ghost(int ndim, double gam, const double* pv, int64_t plane, T* out) {
+  const int nv = ndim + 2;
+  const double rho = pv[0];
+  double q2 = 0.0;
+  for (int k = 0; k < ndim; ++k) {
+    const double u = pv[(1 + k) * plane];
+    out[1 + k] = T(rho * u);
+    q2 = (k == 0) ? u * u : q2 + u * u;
+  }
+  out[0] = T(rho);
+  out[nv - 1] = T(pv[(nv - 1) * plane] / (gam - 1.0) + (0.5 * rho) * q2);
+}
+
 // Ghost cells in conserved variables along one pencil (Appendix A).  fv: the
-// Dirichlet face values of this pencil's side (used when bc is Dirichlet).
+// boundary values of this pencil's side in its value set (Dirichlet, inflow).
 template <class T>
 void fill_ghosts(int ndim, double gam, int d, int bc, bool low, int64_t n, int G, const double* fv, int64_t plane,
                  std::vector<T>& line) {
@@ -598,6 +616,10 @@ void fill_ghosts(int ndim, double gam, int d, int bc, bool low, int64_t n, int G
     else src = low ? r - 1 : n - r;  // mirror
     if (bc == BC_DIRICHLET) {
       dirichlet_ghost<T>(ndim, gam, at(src), fv, plane, at(dst));
+      continue;
+    }
+    if (bc == BC_INFLOW) {
+      inflow_ghost<T>(ndim, gam, fv + (int64_t)(r - 1) * nv * plane, plane, at(dst));
       continue;
     }
     for (int c = 0; c < nv; ++c) at(dst)[c] = at(src)[c];
@@ -615,13 +637,15 @@ int64_t plane_cells(const Grid& g, int d) {
   return t;
 }
 
-// Dirichlet values of side (d, hi) in value set `set` at plane cell pidx
-// (remaining axes, the lower one fastest), or null if the side is not Dirichlet.
-const double* face_values(const Grid& g, int d, int hi, int set, int64_t pidx) {
+// Boundary values of side (d, hi) in value set `set` at plane cell pidx
+// (remaining axes, the lower one fastest), or null if the side takes none.
+// A set holds one layer of nv planes (Dirichlet) or G layers (inflow).
+const double* face_values(const Grid& g, int G, int d, int hi, int set, int64_t pidx) {
   const int bc = hi ? g.bc_hi[d] : g.bc_lo[d];
-  if (bc != BC_DIRICHLET) return nullptr;
+  if (bc != BC_DIRICHLET && bc != BC_INFLOW) return nullptr;
   const int64_t plane = plane_cells(g, d);
-  return g.bc_values[d][hi] + (int64_t)set * (g.ndim + 2) * plane + pidx;
+  const int64_t layers = bc == BC_INFLOW ? G : 1;
+  return g.bc_values[d][hi] + (int64_t)set * layers * (g.ndim + 2) * plane + pidx;
 }
 
 // a_d = max over cells of |u_d| + c (used for dt and the limiter weights).
@@ -718,8 +742,8 @@ void load_pencil(const Grid& g, double gam, int d, int G, const T* U, int64_t ba
   const int64_t plane = plane_cells(g, d);
   for (int64_t l = 0; l < n; ++l)
     for (int c = 0; c < nv; ++c) line[(size_t)(l + G) * nv + c] = U[c * nc + base + l * stride[d]];
-  fill_ghosts(nd, gam, d, g.bc_lo[d], true, n, G, face_values(g, d, 0, set, pidx), plane, line);
-  fill_ghosts(nd, gam, d, g.bc_hi[d], false, n, G, face_values(g, d, 1, set, pidx), plane, line);
+  fill_ghosts(nd, gam, d, g.bc_lo[d], true, n, G, face_values(g, G, d, 0, set, pidx), plane, line);
+  fill_ghosts(nd, gam, d, g.bc_hi[d], false, n, G, face_values(g, G, d, 1, set, pidx), plane, line);
   for (int64_t l = -G; l < n + G; ++l) cell_state(nd, gam, d, &line[(size_t)(l + G) * nv], cells[(size_t)(l + G)]);
 }
 
@@ -808,9 +832,9 @@ int check_grid(const Grid& g, const Scheme& s) {
     if (d < g.ndim) {
       if (g.n[d] < s.order / 2 || g.dx[d] <= 0.0) return -1;
       if ((g.bc_lo[d] == BC_PERIODIC) != (g.bc_hi[d] == BC_PERIODIC)) return -1;
-      if (g.bc_lo[d] < 0 || g.bc_lo[d] > 4 || g.bc_hi[d] < 0 || g.bc_hi[d] > 4) return -1;
+      if (g.bc_lo[d] < 0 || g.bc_lo[d] > 5 || g.bc_hi[d] < 0 || g.bc_hi[d] > 5) return -1;
       for (int h = 0; h < 2; ++h)
-        if ((h ? g.bc_hi[d] : g.bc_lo[d]) == BC_DIRICHLET) {
+        if ((h ? g.bc_hi[d] : g.bc_lo[d]) >= BC_DIRICHLET) {
           if (!g.bc_values[d][h] || (g.bc_sets != 1 && g.bc_sets != 3)) return -1;
         }
     } else if (g.n[d] != 1) {
@@ -825,10 +849,12 @@ int check_grid(const Grid& g, const Scheme& s) {
 // ------------------------------------------------------------------ C API
 extern "C" {
 
-// bc_values[d][0/1]: host arrays of the Dirichlet face values of the low/high
-// side of direction d, bc_sets (1 or 3) sets of nv planes of primitives
-// (rho, u_x, [u_y], [u_z], p) over the face plane; or_step uses set s in
-// stage s when bc_sets is 3, every other call set 0.
+// bc_values[d][0/1]: host arrays of the boundary values of the low/high side
+// of direction d, bc_sets (1 or 3) sets, each of nv planes of primitives
+// (rho, u_x, [u_y], [u_z], p) over the face plane (Dirichlet: the face
+// values; inflow: order/2 such layers, the ghost cells outward from the
+// face); or_step uses set s in stage s when bc_sets is 3, every other call
+// set 0.
 struct or_grid {
   int32_t ndim;
   int32_t bc_sets;

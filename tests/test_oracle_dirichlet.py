@@ -1,6 +1,8 @@
-"""Pins of the oracle's Dirichlet boundary (Appendix A: in primitive variables
-the ghost cell is the mirror cell reflected through the prescribed face value,
-which makes that face value the second-order average of the two).
+"""Pins of the oracle's prescribed-value boundaries: the Dirichlet boundary
+(Appendix A: in primitive variables the ghost cell is the mirror cell
+reflected through the prescribed face value, which makes that face value the
+second-order average of the two) and the supersonic inflow boundary (the
+ghost cells take prescribed states, as the Noh problem of Sec. 5 does).
 
 * A state whose primitives are linear in space, with face values taken from
   the same linear functions, has ghost cells that continue it exactly: the
@@ -8,6 +10,8 @@ which makes that face value the second-order average of the two).
   grid that is larger by the ghost width and holds those cells (a mirror
   index off by one, a reflection of conserved instead of primitive variables,
   or a wrong face-plane ordering each break it).
+* The same with inflow ghost cells holding the linear state at their centres
+  (a swapped layer order breaks it).
 * A uniform state with matching face values is steady.
 * Per-stage value sets: the stage-s set enters stage s of SSP-RK3, so values
   at t, t + dt and t + dt/2 keep the scheme's accuracy at an inflow boundary
@@ -143,3 +147,94 @@ def test_stage_value_sets_follow_the_stage_times():
     assert rate(e_right) > 1.8
     assert rate(e_wrong) < 1.5 and rate(one) < 1.5
     assert e_right[1] < 0.5 * min(e_wrong[1], one[1])
+
+
+def _ghost_layers(shape, dx, G):
+    """{(d, side): (1, G, nvar, plane)} primitives of the linear state at the
+    centres of the G ghost cells outward from each boundary face."""
+    nd = len(shape)
+    out = {}
+    for d in range(nd):
+        rest = [k for k in range(3) if k != d]
+        for side in (0, 1):
+            layers = []
+            for r in range(1, G + 1):
+                coords = []
+                for k in range(3):
+                    if k >= nd:
+                        coords.append(np.zeros(1))
+                    elif k == d:
+                        coords.append(np.array([(-r + 0.5) * dx[d] if side == 0 else (shape[d] + r - 0.5) * dx[d]]))
+                    else:
+                        coords.append((np.arange(shape[k]) + 0.5) * dx[k])
+                Xr = np.meshgrid(coords[rest[1]], coords[rest[0]], indexing="ij")
+                X = [None] * 3
+                X[rest[0]] = Xr[1].ravel()
+                X[rest[1]] = Xr[0].ravel()
+                X[d] = np.full(X[rest[0]].shape, coords[d][0])
+                rho, vel, p = _prims(X, nd)
+                layers.append(np.stack([rho] + list(vel) + [p]))
+            out[(d, side)] = np.stack(layers)[None]
+    return out
+
+
+@pytest.mark.parametrize("order", [8, 10])
+@pytest.mark.parametrize("shape", [(24,), (14, 11), (10, 9, 8)])
+def test_linear_state_continues_through_inflow_ghosts(order, shape):
+    nd = len(shape)
+    G = order // 2
+    dx = [1.0 / n for n in shape]
+    UA = _state(shape, dx, 0.0)
+    gA = oracle.make_grid(shape, dx, [oracle.BC_INFLOW] * nd, bc_values=_ghost_layers(shape, dx, G))
+    big = tuple(n + 2 * G for n in shape)
+    UB = _state(big, dx, G)
+    gB = oracle.make_grid(big, dx, [oracle.BC_OUTFLOW] * nd)
+    dA, _, _ = oracle.rhs(gA, UA, order=order, gamma=G_)
+    dB, _, _ = oracle.rhs(gB, UB, order=order, gamma=G_)
+    sl = tuple(slice(G, G + shape[k]) if k < nd else slice(None) for k in reversed(range(3)))
+    inner = dB[(slice(None),) + sl]
+    assert np.abs(dA - inner).max() <= 1e-12 * np.abs(inner).max()
+    # the layers in reverse order are a different boundary
+    rev = {k: v[:, ::-1].copy() for k, v in _ghost_layers(shape, dx, G).items()}
+    gR = oracle.make_grid(shape, dx, [oracle.BC_INFLOW] * nd, bc_values=rev)
+    dR, _, _ = oracle.rhs(gR, UA, order=order, gamma=G_)
+    assert np.abs(dR - inner).max() > 1e-6 * np.abs(inner).max()
+
+
+def _advect_wave_inflow(n, set_times, tf=0.25, order=8):
+    """The density wave of _advect_wave with inflow ghost cells holding the
+    exact solution at the stage times; returns the max density error at tf."""
+    dx = 1.0 / n
+    G = order // 2
+    x = (np.arange(n) + 0.5) * dx
+    U = inputs._as_layout(inputs.conserved_from_primitive(_wave(x, 0.0), [np.ones(n)], np.ones(n), G_), 1)
+    t = 0.0
+    dt0 = 0.4 * dx / (1.0 + np.sqrt(G_ * 1.0 / 0.8))
+    r = np.arange(1, G + 1)
+    xg = {0: (-r + 0.5) * dx, 1: 1.0 + (r - 0.5) * dx}
+    while t < tf - 1e-14:
+        h = min(dt0, tf - t)
+        fv = {}
+        for side in (0, 1):
+            sets = [np.stack([np.array([_wave(xx, ts), 1.0, 1.0])[:, None] for xx in xg[side]])
+                    for ts in set_times(t, h)]
+            fv[(0, side)] = np.stack(sets)
+        g = oracle.make_grid((n,), [dx], [oracle.BC_INFLOW], bc_values=fv)
+        U, _, _, _ = oracle.step(g, U, order=order, dt=h, gamma=G_)
+        t += h
+    return np.abs(U[0, 0, 0] - _wave(x, tf)).max()
+
+
+def test_inflow_stage_value_sets_follow_the_stage_times():
+    right = lambda t, h: (t, t + h, t + 0.5 * h)  # noqa: E731
+    wrong = lambda t, h: (t, t + 0.5 * h, t + h)  # noqa: E731
+    e_right = [_advect_wave_inflow(n, right) for n in (40, 80)]
+    e_wrong = [_advect_wave_inflow(n, wrong) for n in (40, 80)]
+    rate = lambda e: np.log2(e[0] / e[1])  # noqa: E731
+    print("errors: stage times", e_right, "swapped", e_wrong)
+    # exact stage values keep second order (the known order reduction of
+    # boundary data imposed at intermediate Runge-Kutta stages); a set order
+    # off the stage times is first order and far less accurate
+    assert rate(e_right) > 1.8
+    assert rate(e_wrong) < 1.3
+    assert e_right[1] < 0.01 * e_wrong[1]
