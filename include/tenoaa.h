@@ -64,8 +64,22 @@ enum {
 
 /* Boundary conditions (Appendix A of the paper; OUTFLOW copies the nearest
  * interior cell into every ghost layer).  A direction is either periodic on
- * both sides or on neither. */
-enum { TENOAA_BC_PERIODIC = 0, TENOAA_BC_OUTFLOW = 1, TENOAA_BC_SYMMETRY = 2, TENOAA_BC_NOSLIP = 3 };
+ * both sides or on neither.  DIRICHLET is the Appendix's second-order form:
+ * with prescribed face primitives (rho', u', p'), ghost cell r (r = 1, 2, ...)
+ * takes, in primitive variables, 2 (rho', u', p') minus the primitives of
+ * interior cell r - 1 counted from that face; the face values come from
+ * tenoaa_grid.bc_values.  INFLOW is a supersonic inflow (every
+ * characteristic enters the domain, as at the outer boundaries of the Noh
+ * problem in Sec. 5): the ghost cells take prescribed states, also from
+ * tenoaa_grid.bc_values. */
+enum {
+  TENOAA_BC_PERIODIC = 0,
+  TENOAA_BC_OUTFLOW = 1,
+  TENOAA_BC_SYMMETRY = 2,
+  TENOAA_BC_NOSLIP = 3,
+  TENOAA_BC_DIRICHLET = 4,
+  TENOAA_BC_INFLOW = 5
+};
 
 /* Flux splitting (Sec. 5): LLF uses, per characteristic field, the largest
  * |eigenvalue| over the reconstruction window; RUSANOV one max(|u_n| + c)
@@ -76,14 +90,31 @@ enum { TENOAA_LLF = 0, TENOAA_RUSANOV = 1 };
 enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1, TENOAA_WS_RHS_VJP = 2, TENOAA_WS_STEP_VJP = 3 };
 
 /* Uniform cell-centred grid: cell i of direction d has centre (i + 1/2) dx[d].
- * n[d] >= order/2 for d < ndim and n[d] == 1 otherwise; dx[d] > 0. */
+ * n[d] >= order/2 for d < ndim and n[d] == 1 otherwise; dx[d] > 0.
+ *
+ * Boundary values (read only where bc_lo[d] / bc_hi[d] is
+ * TENOAA_BC_DIRICHLET or TENOAA_BC_INFLOW, else ignored and may be NULL):
+ * bc_values[d][0] (low side) and bc_values[d][1] (high side) are DEVICE
+ * arrays owned by the caller.  With P = the product of n[k] over k != d (the
+ * face plane, the lower of the two remaining axes fastest), a "layer" is
+ * nvar x P doubles: the planes rho, u_x, [u_y], [u_z], p (primitives,
+ * velocities in axis order).  A Dirichlet side holds bc_sets layers (the face
+ * values); an inflow side bc_sets x (order / 2) layers, per set the ghost
+ * cells r = 1 .. order/2 counted outward from the face.  bc_sets is 1 or 3:
+ * with 3, stage s of an SSP-RK3 step reads set s (the caller supplies the
+ * values at t, t + dt and t + dt/2, the times the three stages approximate)
+ * and tenoaa_rhs reads set 0; with 1 every evaluation reads set 0.  A smaller
+ * array than this is undefined behaviour (the library cannot check device
+ * allocations).  Grids with such sides are rejected with
+ * TENOAA_EUNSUPPORTED by the adjoint entry points and the batch plan. */
 typedef struct {
   int32_t ndim;
-  int32_t pad;
+  int32_t bc_sets;
   int64_t n[3];
   double dx[3];
   int32_t bc_lo[3];
   int32_t bc_hi[3];
+  const double* bc_values[3][2];
 } tenoaa_grid;
 
 /* order: 8 (TENO8-AA) or 10 (TENO10-AA), Sec. 4; splitting: TENOAA_LLF or

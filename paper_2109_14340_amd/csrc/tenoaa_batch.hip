@@ -179,6 +179,8 @@ __device__ __forceinline__ void sweep_item(const BatchArgs& B, char* arena, int 
   A.splitting = B.splitting;
   A.pad = 0;
   A.gamma = B.gamma;
+  A.bcv[0] = nullptr;
+  A.bcv[1] = nullptr;
   A.mu = nullptr;
   A.status = B.status + p;
   const int64_t ntx = P.along[0] * P.across[0];
@@ -684,7 +686,7 @@ int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const teno
   int64_t total = 0;
   for (int q = 0; q < nprob; ++q) {
     if (!tenoaa::grid_ok(&grids[q], scheme)) return TENOAA_EINVAL;
-    if (grids[q].ndim != 2) return TENOAA_EUNSUPPORTED;
+    if (grids[q].ndim != 2 || tenoaa::has_boundary_values(&grids[q])) return TENOAA_EUNSUPPORTED;
     if (grids[q].n[0] * grids[q].n[1] >= ((int64_t)1 << 31)) return TENOAA_EINVAL;
     total += 4 * grids[q].n[0] * grids[q].n[1];
     if (total > ((int64_t)1 << 40)) return TENOAA_EINVAL;

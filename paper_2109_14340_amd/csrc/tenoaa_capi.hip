@@ -89,8 +89,12 @@ bool valid_grid(const tenoaa_grid* g, const tenoaa_scheme* s) {
   for (int d = 0; d < 3; ++d) {
     if (d < g->ndim) {
       if (g->n[d] < s->order / 2 || !(g->dx[d] > 0.0)) return false;
-      if (g->bc_lo[d] < 0 || g->bc_lo[d] > 3 || g->bc_hi[d] < 0 || g->bc_hi[d] > 3) return false;
+      if (g->bc_lo[d] < 0 || g->bc_lo[d] > 5 || g->bc_hi[d] < 0 || g->bc_hi[d] > 5) return false;
       if ((g->bc_lo[d] == TENOAA_BC_PERIODIC) != (g->bc_hi[d] == TENOAA_BC_PERIODIC)) return false;
+      for (int h = 0; h < 2; ++h)
+        if ((h ? g->bc_hi[d] : g->bc_lo[d]) >= TENOAA_BC_DIRICHLET) {
+          if (!g->bc_values[d][h] || (g->bc_sets != 1 && g->bc_sets != 3)) return false;
+        }
     } else if (g->n[d] != 1) {
       return false;
     }
@@ -164,9 +168,31 @@ struct Ctx {
   hipStream_t st;
 };
 
-// Face fluxes of every direction for state U; flags optional.
+// True if a side takes prescribed values (Dirichlet or inflow).
+bool boundary_values_any(const tenoaa_grid* g) {
+  for (int d = 0; d < g->ndim; ++d)
+    if (g->bc_lo[d] >= TENOAA_BC_DIRICHLET || g->bc_hi[d] >= TENOAA_BC_DIRICHLET) return true;
+  return false;
+}
+
+// Boundary values of side (d, h) for SSP-RK3 stage `stage` (0 outside a
+// step), or null: a set holds one layer of nvar face-plane arrays
+// (Dirichlet) or order/2 layers (inflow).
+const double* face_values(const tenoaa_grid* g, int order, int d, int h, int stage) {
+  const int bc = h ? g->bc_hi[d] : g->bc_lo[d];
+  if (bc != TENOAA_BC_DIRICHLET && bc != TENOAA_BC_INFLOW) return nullptr;
+  int64_t plane = 1;
+  for (int k = 0; k < 3; ++k)
+    if (k != d) plane *= g->n[k];
+  const int64_t layers = bc == TENOAA_BC_INFLOW ? order / 2 : 1;
+  const int set = g->bc_sets == 3 ? stage : 0;
+  return g->bc_values[d][h] + (int64_t)set * layers * (g->ndim + 2) * plane;
+}
+
+// Face fluxes of every direction for state U; flags optional.  `stage`
+// selects the Dirichlet value set.
 int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint8_t* frozen = nullptr,
-           int only_dir = -1, double* fh_out = nullptr) {
+           int only_dir = -1, double* fh_out = nullptr, int stage = 0) {
   const tenoaa_grid* g = c.g;
   const int nv = g->ndim + 2;
   int64_t flag_off = 0;
@@ -189,6 +215,8 @@ int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint
     a.nft = faces_total(g, d);
     a.bc_lo = g->bc_lo[d];
     a.bc_hi = g->bc_hi[d];
+    a.bcv[0] = face_values(g, c.s->order, d, 0, stage);
+    a.bcv[1] = face_values(g, c.s->order, d, 1, stage);
     a.splitting = c.s->splitting;
     a.gamma = c.gamma;
     a.mu = c.S->mu;
@@ -295,6 +323,7 @@ int begin(const Ctx&) { return TENOAA_OK; }
 
 namespace tenoaa {
 bool grid_ok(const tenoaa_grid* g, const tenoaa_scheme* s) { return valid_grid(g, s); }
+bool has_boundary_values(const tenoaa_grid* g) { return boundary_values_any(g); }
 void record_hip_error(hipError_t e) { g_last_hip_error = (int)e; }
 }  // namespace tenoaa
 
@@ -358,13 +387,13 @@ int tenoaa_step_flags(const tenoaa_grid* grid, const tenoaa_scheme* scheme, doub
   });
   if (e != hipSuccess) return hip_fail(e);
   // stage 1: U1 = Un + dt L(Un)            -> Us
-  if ((rc = sweeps(c, U, limit, rec(0), rep(0)))) return rc;
+  if ((rc = sweeps(c, U, limit, rec(0), rep(0), -1, nullptr, 0))) return rc;
   if ((rc = update(c, 1, U, nullptr, Us))) return rc;
   // stage 2: U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1)   -> Us (in place)
-  if ((rc = sweeps(c, Us, limit, rec(1), rep(1)))) return rc;
+  if ((rc = sweeps(c, Us, limit, rec(1), rep(1), -1, nullptr, 1))) return rc;
   if ((rc = update(c, 2, U, Us, Us))) return rc;
   // stage 3: U = 1/3 Un + 2/3 U2 + 2/3 dt L(U2)    -> U (in place)
-  if ((rc = sweeps(c, Us, limit, rec(2), rep(2)))) return rc;
+  if ((rc = sweeps(c, Us, limit, rec(2), rep(2), -1, nullptr, 2))) return rc;
   return update(c, 3, U, Us, U);
 }
 
@@ -375,6 +404,7 @@ int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double 
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_RHS_VJP);
   if (rc) return rc;
   if (!U || !dUdt_bar || !U_bar || U_bar == U || U_bar == dUdt_bar) return TENOAA_EINVAL;
+  if (boundary_values_any(grid)) return TENOAA_EUNSUPPORTED;
   if ((rc = begin(c))) return rc;
   if ((rc = recorded_sweeps(c, U, 0, flags))) return rc;
   return rhs_vjp(c, U, dUdt_bar, U_bar, 0);
@@ -387,7 +417,7 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP_VJP);
   if (rc) return rc;
   if (!Un || !dt_dev || !Unp1_bar || !Un_bar || Un_bar == Unp1_bar || Un_bar == Un) return TENOAA_EINVAL;
-  if (scheme->positivity) return TENOAA_EUNSUPPORTED;
+  if (scheme->positivity || boundary_values_any(grid)) return TENOAA_EUNSUPPORTED;
   if ((rc = begin(c))) return rc;
   const int64_t N = (int64_t)(grid->ndim + 2) * grid->n[0] * grid->n[1] * grid->n[2];
   double* S1 = reinterpret_cast<double*>(c.ws + c.L.stage);

@@ -30,6 +30,7 @@ struct SweepArgs {
   int splitting;
   int pad;
   double gamma;
+  const double* bcv[2];  // Dirichlet face values of the low/high side, this evaluation's set, or null
   const double* mu; // device: limiter factors
   int* status;      // device: status word
 };
@@ -66,6 +67,8 @@ struct AdjointArgs {
 
 // Argument check of a grid and scheme (shared by every entry point).
 bool grid_ok(const tenoaa_grid* g, const tenoaa_scheme* s);
+// True if a side of the grid takes prescribed values (Dirichlet or inflow).
+bool has_boundary_values(const tenoaa_grid* g);
 // Keeps e for tenoaa_last_hip_error().
 void record_hip_error(hipError_t e);
 

@@ -42,6 +42,53 @@ struct SweepShape {
   static constexpr int LDS_BYTES = NCT * (16 * NV + 8 * (4 + NT));
 };
 
+// Dirichlet ghost cell (Appendix A): in primitive variables the ghost is the
+// mirror cell reflected through the prescribed face value,
+// (rho, u, p)_ghost = 2 (rho, u, p)_face - (rho, u, p)_mirror.  W holds the
+// mirror cell's conserved state on entry and the ghost's on return; fv points
+// at the face density, its velocities and pressure following at strides of
+// `plane`.
+template <int NDIM>
+__device__ __forceinline__ void dirichlet_ghost(double* W, const double* fv, int64_t plane, double gm1) {
+  constexpr int NV = NDIM + 2;
+  const double rho = W[0];
+  const double ir = div_rn(1.0, rho);
+  double u[NDIM];
+  double q2 = 0.0;
+  unroll<NDIM>([&](auto k) {
+    u[k] = W[1 + k] * ir;
+    q2 = (k == 0) ? u[0] * u[0] : q2 + u[k] * u[k];
+  });
+  const double p = gm1 * (W[NV - 1] - (0.5 * rho) * q2);
+  const double rg = 2.0 * fv[0] - rho;
+  double qg = 0.0;
+  unroll<NDIM>([&](auto k) {
+    const double ug = 2.0 * fv[(1 + k) * plane] - u[k];
+    W[1 + k] = rg * ug;
+    qg = (k == 0) ? ug * ug : qg + ug * ug;
+  });
+  const double pg = 2.0 * fv[(NV - 1) * plane] - p;
+  W[0] = rg;
+  W[NV - 1] = div_rn(pg, gm1) + (0.5 * rg) * qg;
+}
+
+// Prescribed ghost cell (supersonic inflow, where every characteristic enters
+// the domain): the conserved state of the primitives at pv (density, then
+// velocities and pressure at strides of `plane`).
+template <int NDIM>
+__device__ __forceinline__ void inflow_ghost(double* W, const double* pv, int64_t plane, double gm1) {
+  constexpr int NV = NDIM + 2;
+  const double rho = pv[0];
+  double q2 = 0.0;
+  unroll<NDIM>([&](auto k) {
+    const double u = pv[(1 + k) * plane];
+    W[1 + k] = rho * u;
+    q2 = (k == 0) ? u * u : q2 + u * u;
+  });
+  W[0] = rho;
+  W[NV - 1] = div_rn(pv[(NV - 1) * plane], gm1) + (0.5 * rho) * q2;
+}
+
 // One tile of faces.  (bx, by, bz) = (tile index along the direction, tile
 // index across it, coordinate along the remaining axis).  `lds` holds at
 // least SweepShape::LDS_BYTES bytes, 16-byte aligned; the caller separates
@@ -93,17 +140,20 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     int64_t t = t0 + tt;
     if (t >= nA) t = nA - 1;
     int64_t l = f0 - G + nn;
-    bool mirror = false;
-    int bc = -1;
+    int bc = -1;  // the boundary that makes this a ghost cell, -1 for a domain cell
+    const int side = (l < 0) ? 0 : 1;
+    const int64_t layer = (l < 0) ? -l : l - nN + 1;  // ghost layer r = 1, 2, ... outward
     if (l < 0 || l >= nN) {
       bc = (l < 0) ? A.bc_lo : A.bc_hi;
       if (bc == TENOAA_BC_PERIODIC) {
         l = ((l % nN) + nN) % nN;
-      } else if (bc == TENOAA_BC_OUTFLOW) {
+        bc = -1;
+      } else if (bc == TENOAA_BC_OUTFLOW || layer > G) {
+        // outflow, or a cell beyond the G ghost layers that no face of the tile reads
         l = (l < 0) ? 0 : nN - 1;
+        bc = -1;
       } else {
-        l = (l < 0) ? -l - 1 : 2 * nN - 1 - l;
-        mirror = true;
+        l = (l < 0) ? -l - 1 : 2 * nN - 1 - l;  // mirror cell
       }
       if (l < 0) l = 0;
       if (l >= nN) l = nN - 1;
@@ -111,11 +161,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     const int64_t off = l * stride[DIR] + t * stride[AX_A] + bcoord * stride[AX_B];
     double Wc[NV];
     unroll<NV>([&](auto c) { Wc[c] = A.U[c * ncell + off]; });
-    if (mirror) {
+    if (bc >= 0) {
+      // values of this pencil's cell of the face plane: the transverse index
+      // t, then the remaining axis
+      const int64_t plane = nA * A.n[AX_B];
+      const double* fv = A.bcv[side] + t + nA * bcoord;
       if (bc == TENOAA_BC_SYMMETRY) {
         Wc[1 + DIR] = -Wc[1 + DIR];
-      } else {
+      } else if (bc == TENOAA_BC_NOSLIP) {
         unroll<NDIM>([&](auto k) { Wc[1 + k] = -Wc[1 + k]; });
+      } else if (bc == TENOAA_BC_DIRICHLET) {
+        dirichlet_ghost<NDIM>(Wc, fv, plane, gm1);
+      } else {
+        inflow_ghost<NDIM>(Wc, fv + (layer - 1) * NV * plane, plane, gm1);
       }
     }
     // cell primitives (Sec. 1), axis order

@@ -13,7 +13,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtenoaa.so")
 
-BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP = 0, 1, 2, 3
+BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP, BC_DIRICHLET, BC_INFLOW = 0, 1, 2, 3, 4, 5
 LLF, RUSANOV = 0, 1
 WS_RHS, WS_STEP, WS_RHS_VJP, WS_STEP_VJP = 0, 1, 2, 3
 ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENONPHYSICAL", -5: "EWORKSPACE", -6: "ETIMEOUT"}
@@ -29,8 +29,9 @@ KCLASS_VJP = (5, 6, 7)
 
 
 class Grid(ctypes.Structure):
-    _fields_ = [("ndim", ctypes.c_int32), ("pad", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
-                ("dx", ctypes.c_double * 3), ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3)]
+    _fields_ = [("ndim", ctypes.c_int32), ("bc_sets", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+                ("dx", ctypes.c_double * 3), ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3),
+                ("bc_values", (ctypes.c_void_p * 2) * 3)]
 
 
 class Scheme(ctypes.Structure):
@@ -93,11 +94,15 @@ def load():
     return _lib
 
 
-def make_grid(shape, dx=None, bc_lo=None, bc_hi=None):
-    """shape = (nx,), (nx, ny) or (nx, ny, nz) in axis order; bc per axis (default periodic)."""
+def make_grid(shape, dx=None, bc_lo=None, bc_hi=None, bc_values=None):
+    """shape = (nx,), (nx, ny) or (nx, ny, nz) in axis order; bc per axis (default periodic).
+
+    bc_values: {(d, side): tensor} for the Dirichlet and inflow sides (side 0
+    low, 1 high) as set_face_values takes them."""
     nd = len(shape)
     g = Grid()
     g.ndim = nd
+    g.bc_sets = 1
     dx = dx if dx is not None else [1.0 / n for n in shape]
     bc_lo = bc_lo if bc_lo is not None else [BC_PERIODIC] * nd
     bc_hi = bc_hi if bc_hi is not None else bc_lo
@@ -106,7 +111,67 @@ def make_grid(shape, dx=None, bc_lo=None, bc_hi=None):
         g.dx[d] = dx[d] if d < nd else 1.0
         g.bc_lo[d] = bc_lo[d] if d < nd else 0
         g.bc_hi[d] = bc_hi[d] if d < nd else 0
+    g._faces = {}
+    for (d, side), v in (bc_values or {}).items():
+        set_face_values(g, d, side, v)
     return g
+
+
+def face_plane(grid, d):
+    """Cells of the face plane of direction d (the grid without axis d)."""
+    return int(np.prod([grid.n[k] for k in range(3) if k != d]))
+
+
+def set_face_values(grid, d, side, values):
+    """Binds the boundary values of side (d, side) (0 low, 1 high): a
+    contiguous float64 device tensor of primitives (rho, u_x, [u_y], [u_z], p)
+    over the face plane (the grid without axis d, the lower remaining axis
+    fastest).  A Dirichlet side takes the face values, shape
+    (sets, nvar, plane) or (nvar, plane); an inflow side the ghost cells
+    r = 1 .. order/2 outward from the face, shape (sets, order/2, nvar, plane).
+    sets is 1, or 3 for the three SSP-RK3 stages (values at t, t + dt,
+    t + dt/2), and the same on every side.  The grid keeps a reference to the
+    tensor; its contents may be rewritten between calls."""
+    torch = _torch()
+    nv = grid.ndim + 2
+    plane = face_plane(grid, d)
+    bc = grid.bc_hi[d] if side else grid.bc_lo[d]
+    if bc not in (BC_DIRICHLET, BC_INFLOW):
+        raise TenoaaError("side (%d, %d) takes no boundary values" % (d, side))
+    if values.dtype != torch.float64 or not values.is_cuda or not values.is_contiguous():
+        raise TenoaaError("boundary values must be a contiguous float64 device tensor")
+    want_dims = 4 if bc == BC_INFLOW else 3
+    shape = tuple(values.shape) if values.dim() == want_dims else (1,) + tuple(values.shape)
+    if len(shape) != want_dims or shape[-2:] != (nv, plane) or shape[0] not in (1, 3):
+        raise TenoaaError("boundary values of side (%d, %d): shape %s, want (sets,%s %d, %d) with sets 1 or 3"
+                          % (d, side, tuple(values.shape), " layers," if bc == BC_INFLOW else "", nv, plane))
+    sets = shape[0]
+    others = [k for k in grid._faces if k != (d, side)]
+    if others and grid.bc_sets != sets:
+        raise TenoaaError("every side with boundary values needs the same number of value sets")
+    grid._faces[(d, side)] = values
+    grid._layers = getattr(grid, "_layers", {})
+    grid._layers[(d, side)] = shape[1] if bc == BC_INFLOW else 1
+    grid.bc_sets = sets
+    grid.bc_values[d][side] = values.data_ptr()
+
+
+def _check_boundary_values(grid, scheme):
+    """Every Dirichlet/inflow side is bound, and inflow sides hold order/2 layers."""
+    faces = getattr(grid, "_faces", {})
+    for d in range(grid.ndim):
+        for side, bc in ((0, grid.bc_lo[d]), (1, grid.bc_hi[d])):
+            if bc in (BC_DIRICHLET, BC_INFLOW):
+                if (d, side) not in faces:
+                    raise TenoaaError("side (%d, %d) has no boundary values bound" % (d, side))
+                if bc == BC_INFLOW and grid._layers[(d, side)] != scheme.order // 2:
+                    raise TenoaaError("inflow side (%d, %d) holds %d ghost layers, order %d needs %d"
+                                      % (d, side, grid._layers[(d, side)], scheme.order, scheme.order // 2))
+
+
+def _torch():
+    import torch
+    return torch
 
 
 def make_scheme(order=10, splitting=LLF, positivity=0):
@@ -169,6 +234,7 @@ def rhs(grid, scheme, U, gamma=1.4, dt_limiter=0.0, flags=None, out=None, ws=Non
     """dU/dt of U (device tensors); flags: optional uint8 device tensor of flags_size(grid)."""
     import torch
     _check_state(U, grid)
+    _check_boundary_values(grid, scheme)
     if out is None:
         out = torch.empty_like(U)
     if ws is None:
@@ -184,6 +250,7 @@ def rhs(grid, scheme, U, gamma=1.4, dt_limiter=0.0, flags=None, out=None, ws=Non
 def step(grid, scheme, U, dt_dev, gamma=1.4, cfl=0.4, ws=None):
     """One SSP-RK3 step of U in place; dt_dev is a 1-element float64 device tensor."""
     _check_state(U, grid)
+    _check_boundary_values(grid, scheme)
     if ws is None:
         ws = workspace(grid, scheme, WS_STEP, U.device)
     rc = load().tenoaa_step(ctypes.byref(grid), ctypes.byref(scheme), gamma, cfl, _ptr(U), _ptr(dt_dev),
@@ -232,6 +299,7 @@ def step_flags(grid, scheme, U, dt_dev, flags3, mode, gamma=1.4, cfl=0.4, ws=Non
     """tenoaa_step recording (mode FLAGS_RECORD) or replaying (FLAGS_REPLAY) the
     decisions of its three stages in flags3 (uint8, 3 * flags_size(grid))."""
     _check_state(U, grid)
+    _check_boundary_values(grid, scheme)
     if ws is None:
         ws = workspace(grid, scheme, WS_STEP, U.device)
     rc = load().tenoaa_step_flags(ctypes.byref(grid), ctypes.byref(scheme), gamma, cfl, _ptr(U), _ptr(dt_dev),

@@ -94,6 +94,38 @@ def test_bad_call_arguments_rejected():
                         None) == -1
 
 
+def test_dirichlet_arguments_checked():
+    """A Dirichlet or inflow side needs its value pointer and 1 or 3 value sets; the
+    adjoint entry points and the batch plan reject grids with such sides."""
+    L = _lib()
+    vp = ctypes.c_void_p
+    s = tenoaa.make_scheme(8)
+    D = tenoaa.BC_DIRICHLET
+
+    def grid(sets=1, ptr=4096, bc=D):
+        g = tenoaa.make_grid((32, 24), bc_lo=[D, 1], bc_hi=[bc, 1])
+        g.bc_sets = sets
+        g.bc_values[0][0] = ptr
+        g.bc_values[0][1] = ptr
+        return g
+
+    ok = grid()
+    assert L.tenoaa_workspace_bytes(ctypes.byref(ok), ctypes.byref(s), 0) > 0
+    assert L.tenoaa_workspace_bytes(ctypes.byref(grid(sets=3)), ctypes.byref(s), 0) > 0
+    assert L.tenoaa_workspace_bytes(ctypes.byref(grid(bc=tenoaa.BC_INFLOW)), ctypes.byref(s), 0) > 0
+    for bad in (grid(ptr=None), grid(sets=2), grid(sets=0), grid(bc=6)):
+        assert L.tenoaa_workspace_bytes(ctypes.byref(bad), ctypes.byref(s), 0) == 0
+    need = 1 << 30
+    assert L.tenoaa_rhs_vjp(ctypes.byref(ok), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), None, vp(1024),
+                            need, None) == -2
+    assert L.tenoaa_step_vjp(ctypes.byref(ok), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), vp(4096), None,
+                             vp(1024), need, None) == -2
+    h = vp(None)
+    arr = (tenoaa.Grid * 1)(ok)
+    assert L.tenoaa_batch_plan_create(arr, 1, ctypes.byref(s), 1.4, 0.4, 2, None, ctypes.byref(h)) == -2
+    assert h.value is None
+
+
 def test_batch_plan_rejects_bad_arguments():
     """Every check of tenoaa_batch_plan_create happens before any HIP call."""
     L = _lib()
