@@ -185,6 +185,15 @@ enum { TENOAA_FLAGS_NONE = 0, TENOAA_FLAGS_RECORD = 1, TENOAA_FLAGS_REPLAY = 2 }
 int tenoaa_step_flags(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,
                       double* dt_dev, uint8_t* flags3, int32_t mode, void* ws, size_t ws_bytes, void* stream);
 
+/* Scalar linear advection u_t + u_x = 0 on a periodic grid of n cells of
+ * width dx (Sec. 5.1, the paper's accuracy test): `nsteps` SSP-RK3 steps of
+ * size dt of du_i/dt = -(fhat_{i+1/2} - fhat_{i-1/2}) / dx, where fhat_{i+1/2}
+ * is the TENO-AA reconstruction (order 8 or 10) of the flux f = u from cells
+ * i - order/2 + 1 .. i + order/2 (the speed is +1, so no splitting).  u (device,
+ * n doubles) is advanced in place.  n in [order, 2048] (one workgroup holds
+ * the grid in LDS); dx > 0, dt > 0, nsteps >= 0; TENOAA_EINVAL otherwise.  Enqueued on `stream` as one launch. */
+int tenoaa_advect(int32_t order, int64_t n, double dx, double dt, int64_t nsteps, double* u, void* stream);
+
 /* Synchronises `stream`, reads and clears the workspace status word.
  * *out = 0 if every state read since the last call was physical, else 1.
  * Returns TENOAA_ENONPHYSICAL if *out != 0, otherwise 0 (or an error). */

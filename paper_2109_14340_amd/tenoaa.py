@@ -22,7 +22,7 @@ FLAGS_NONE, FLAGS_RECORD, FLAGS_REPLAY = 0, 1, 2
 EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_step_flags", "tenoaa_rhs_vjp", "tenoaa_step_vjp",
            "tenoaa_get_status", "tenoaa_last_hip_error", "tenoaa_timing_enable", "tenoaa_timing_read",
            "tenoaa_batch_plan_create", "tenoaa_batch_offsets", "tenoaa_batch_run", "tenoaa_batch_get_status",
-           "tenoaa_batch_plan_info", "tenoaa_batch_plan_destroy"]
+           "tenoaa_batch_plan_info", "tenoaa_batch_plan_destroy", "tenoaa_advect"]
 KCLASS_SWEEP = (0, 1, 2)
 KCLASS_UPDATE, KCLASS_WAVESPEED = 3, 4
 KCLASS_VJP = (5, 6, 7)
@@ -90,6 +90,9 @@ def load():
         L.tenoaa_batch_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
         L.tenoaa_batch_plan_destroy.restype = ctypes.c_int
         L.tenoaa_batch_plan_destroy.argtypes = [vp]
+        L.tenoaa_advect.restype = ctypes.c_int
+        L.tenoaa_advect.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int64, vp, vp]
         _lib = L
     return _lib
 
@@ -306,6 +309,16 @@ def step_flags(grid, scheme, U, dt_dev, flags3, mode, gamma=1.4, cfl=0.4, ws=Non
                                   _ptr(flags3), mode, _ptr(ws), ws.numel(), _stream())
     _check(rc, "tenoaa_step_flags")
     return U
+
+
+def advect(order, u, dx, dt, nsteps):
+    """nsteps SSP-RK3 steps of the periodic scalar advection u_t + u_x = 0 on
+    the 1D float64 device tensor u, in place."""
+    import torch
+    if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous() or u.dim() != 1:
+        raise TenoaaError("u must be a contiguous 1D float64 device tensor")
+    _check(load().tenoaa_advect(order, u.numel(), dx, dt, nsteps, _ptr(u), _stream()), "tenoaa_advect")
+    return u
 
 
 def get_status(ws):

@@ -126,6 +126,17 @@ def test_dirichlet_arguments_checked():
     assert h.value is None
 
 
+def test_advect_rejects_bad_arguments():
+    L = _lib()
+    vp = ctypes.c_void_p
+    for order, n, dx, dt, ns, u in [(9, 64, 0.1, 0.01, 1, 256), (10, 9, 0.1, 0.01, 1, 256),
+                                    (10, 4096, 0.1, 0.01, 1, 256), (8, 64, 0.0, 0.01, 1, 256),
+                                    (8, 64, 0.1, float("nan"), 1, 256), (8, 64, 0.1, 0.01, -1, 256),
+                                    (8, 64, 0.1, 0.01, 1, None)]:
+        assert L.tenoaa_advect(order, n, dx, dt, ns, vp(u) if u else None, None) == -1
+    assert L.tenoaa_advect(8, 64, 0.1, 0.01, 0, vp(256), None) == 0  # nothing to do, nothing enqueued
+
+
 def test_batch_plan_rejects_bad_arguments():
     """Every check of tenoaa_batch_plan_create happens before any HIP call."""
     L = _lib()
