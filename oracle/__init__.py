@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "tenoaa_oracle.cpp")
 _LIB = os.path.join(_HERE, "libtenoaa_oracle.so")
 
 BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP, BC_DIRICHLET, BC_INFLOW = 0, 1, 2, 3, 4, 5
-LLF, RUSANOV = 0, 1
+LLF, RUSANOV, ROE = 0, 1, 2
 
 
 def build():

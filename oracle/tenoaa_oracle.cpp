@@ -24,10 +24,13 @@
 //   * the adaptive cut-off C_T from the first-order undivided-difference
 //     measure eta, m, g(m), [beta] (Sec. 3.4);
 //   * the optimised linear schemes and candidate fluxes (Sec. 4.1, 4.2);
-//   * Roe-averaged characteristic projection, LLF or Rusanov splitting,
-//     SSP-RK3, dimension-by-dimension sweeps (Sec. 5 opening paragraph);
-//   * ghost cells for periodic, outflow, slip and no-slip walls (Appendix A;
-//     outflow is the zeroth-order copy reading);
+//   * Roe-averaged characteristic projection, LLF or Rusanov splitting, or
+//     the Roe flux with entropy fix (Sec. 5.2's blast waves and
+//     Rayleigh-Taylor runs), SSP-RK3, dimension-by-dimension sweeps (Sec. 5
+//     opening paragraph);
+//   * ghost cells for periodic, outflow, slip and no-slip walls, the
+//     second-order Dirichlet form (Appendix A; outflow is the zeroth-order
+//     copy reading) and prescribed supersonic-inflow states;
 //   * the positivity-preserving flux limiter of Hu, Adams & Shu 2013 that the
 //     paper applies in its extreme cases (Sec. 5.3 opening paragraph), in
 //     the reading stated at or_limit_face below.
@@ -696,16 +699,44 @@ void face_flux(const Grid& g, const Scheme& sc, double gam, int d, const CellQ<T
       v[j] = av;
       gch[j] = ag;
     }
-    // splitting speed over the window: LLF per field, Rusanov for all fields
+    // splitting speed over the window: LLF per field (also the Roe flux's
+    // fallback), Rusanov one for all fields
     T alpha = T(-1.0);
     for (int j = 0; j < 2 * G; ++j) {
       const T un = win[j].u[d];
-      const T lam = sc.splitting == 0 ? absT(char_speed(nv, s, un, win[j].c)) : absT(un) + win[j].c;
+      const T lam = sc.splitting != 1 ? absT(char_speed(nv, s, un, win[j].c)) : absT(un) + win[j].c;
       if (re(lam) > re(alpha)) alpha = lam;
     }
     for (int j = 0; j < 2 * G; ++j) {
       gp[j] = 0.5 * fmaT(alpha, v[j], gch[j]);
       gm[j] = 0.5 * fmaT(-alpha, v[j], gch[j]);
+    }
+    // Roe flux with entropy fix: where the field's eigenvalue has one strict
+    // sign at both cells of the face, the unsplit characteristic flux is
+    // reconstructed from the upwind side only; elsewhere (a sonic point, or
+    // a zero eigenvalue) the field falls back to the LLF split above.
+    int upwind = 0;  // 0: split, 1: + side only, 2: - side only
+    if (sc.splitting == 2) {
+      const double la = re(char_speed(nv, s, ca.u[d], ca.c));
+      const double lb = re(char_speed(nv, s, cb.u[d], cb.c));
+      upwind = (la > 0.0 && lb > 0.0) ? 1 : ((la < 0.0 && lb < 0.0) ? 2 : 0);
+    }
+    if (upwind) {
+      const int side = upwind - 1;
+      for (int k = 0; k < 2 * G; ++k) fv[k] = side == 0 ? gch[k] : gch[2 * G - 1 - k];
+      const int64_t fi = fbase + ((int64_t)s * 2 + side) * nft;
+      const int64_t fo = fbase + ((int64_t)s * 2 + (1 - side)) * nft;
+      Decision dec;
+      fhat[s] = teno_aa(sc.order, fv, &dec, frozen ? frozen + fi : nullptr);
+      if (flags && !frozen) {
+        flags[fi] = dec.flag;
+        flags[fo] = 0;  // the side not reconstructed (no real decision has this byte)
+      }
+      if (margins && !frozen) {
+        margins[fi] = dec.margin;
+        margins[fo] = 1.0;
+      }
+      continue;
     }
     T sum = T(0.0);
     for (int side = 0; side < 2; ++side) {
