@@ -83,8 +83,14 @@ enum {
 
 /* Flux splitting (Sec. 5): LLF uses, per characteristic field, the largest
  * |eigenvalue| over the reconstruction window; RUSANOV one max(|u_n| + c)
- * over the window for every field. */
-enum { TENOAA_LLF = 0, TENOAA_RUSANOV = 1 };
+ * over the window for every field.  ROE is the Roe flux with entropy fix
+ * that Sec. 5.2 uses for its blast waves and Rayleigh-Taylor runs: per field,
+ * where the eigenvalue has one strict sign at both cells of the face, the
+ * unsplit characteristic flux is reconstructed from the upwind side alone
+ * (the flag byte of the other side is 0, which no decision produces);
+ * elsewhere the field is split as with LLF.  The adjoint entry points and
+ * decision replay reject ROE with TENOAA_EUNSUPPORTED. */
+enum { TENOAA_LLF = 0, TENOAA_RUSANOV = 1, TENOAA_ROE = 2 };
 
 /* Workspace purposes for tenoaa_workspace_bytes. */
 enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1, TENOAA_WS_RHS_VJP = 2, TENOAA_WS_STEP_VJP = 3 };
@@ -117,8 +123,8 @@ typedef struct {
   const double* bc_values[3][2];
 } tenoaa_grid;
 
-/* order: 8 (TENO8-AA) or 10 (TENO10-AA), Sec. 4; splitting: TENOAA_LLF or
- * TENOAA_RUSANOV; positivity: 1 enables the flux limiter. */
+/* order: 8 (TENO8-AA) or 10 (TENO10-AA), Sec. 4; splitting: TENOAA_LLF,
+ * TENOAA_RUSANOV or TENOAA_ROE; positivity: 1 enables the flux limiter. */
 typedef struct {
   int32_t order;
   int32_t splitting;

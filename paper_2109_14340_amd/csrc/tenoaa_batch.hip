@@ -148,18 +148,18 @@ __device__ __forceinline__ void block_max2(char* arena, double a0, double a1, un
   }
 }
 
-template <int ORDER, int DIR, bool LIMIT>
+template <int ORDER, int DIR, bool LIMIT, bool ROE>
 __device__ __forceinline__ void run_sweep_tile(const SweepArgs& A, char* arena, int cand, int64_t k,
                                                int64_t along, double mu) {
   const int64_t bx = k % along, by = k / along;
   if (cand == 0) {
-    sweep_tile<ORDER, 2, DIR, Cand<DIR, 0>::TT, Cand<DIR, 0>::TN, LIMIT>(A, arena, bx, by, 0, mu);
+    sweep_tile<ORDER, 2, DIR, Cand<DIR, 0>::TT, Cand<DIR, 0>::TN, LIMIT, ROE>(A, arena, bx, by, 0, mu);
   } else {
-    sweep_tile<ORDER, 2, DIR, Cand<DIR, 1>::TT, Cand<DIR, 1>::TN, LIMIT>(A, arena, bx, by, 0, mu);
+    sweep_tile<ORDER, 2, DIR, Cand<DIR, 1>::TT, Cand<DIR, 1>::TN, LIMIT, ROE>(A, arena, bx, by, 0, mu);
   }
 }
 
-template <int ORDER, bool LIMIT>
+template <int ORDER, bool LIMIT, bool ROE>
 __device__ __forceinline__ void sweep_item(const BatchArgs& B, char* arena, int p, int64_t k, int n, int stage) {
   const BatchProblem& P = B.probs[p];
   const double* in = (stage == 1 ? B.U + P.u_off : B.S + P.s_off);
@@ -191,8 +191,8 @@ __device__ __forceinline__ void sweep_item(const BatchArgs& B, char* arena, int 
   A.nft = P.nft[dir];
   A.bc_lo = P.bc_lo[dir];
   A.bc_hi = P.bc_hi[dir];
-  if (dir == 0) run_sweep_tile<ORDER, 0, LIMIT>(A, arena, P.tile[0], k, P.along[0], mu[0]);
-  else run_sweep_tile<ORDER, 1, LIMIT>(A, arena, P.tile[1], k, P.along[1], mu[1]);
+  if (dir == 0) run_sweep_tile<ORDER, 0, LIMIT, ROE>(A, arena, P.tile[0], k, P.along[0], mu[0]);
+  else run_sweep_tile<ORDER, 1, LIMIT, ROE>(A, arena, P.tile[1], k, P.along[1], mu[1]);
 }
 
 template <int MODE>
@@ -288,7 +288,7 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs& B, unsigned long l
   return *s_flag != 0;
 }
 
-template <int ORDER, bool LIMIT>
+template <int ORDER, bool LIMIT, bool ROE>
 __global__ __launch_bounds__(BT)
 #if TENOAA_BATCH_WAVES_PER_EU > 0
 __attribute__((amdgpu_waves_per_eu(TENOAA_BATCH_WAVES_PER_EU)))
@@ -326,7 +326,7 @@ void batch_kernel(BatchArgs B) {
         if (kind == 0) {
           speeds_item(B, arena, p, k);
         } else if (kind == 1) {
-          sweep_item<ORDER, LIMIT>(B, arena, p, k, n, stage);
+          sweep_item<ORDER, LIMIT, ROE>(B, arena, p, k, n, stage);
         } else if (stage == 1) {
           update_item<1>(B, arena, p, k, n);
         } else if (stage == 2) {
@@ -358,9 +358,13 @@ __global__ __launch_bounds__(256) void batch_fill_kernel(double* U, const int64_
 
 using KernelFn = void (*)(BatchArgs);
 
-KernelFn pick_kernel(int order, bool limit) {
-  if (order == 8) return limit ? batch_kernel<8, true> : batch_kernel<8, false>;
-  return limit ? batch_kernel<10, true> : batch_kernel<10, false>;
+KernelFn pick_kernel(int order, bool limit, bool roe) {
+  if (roe) {
+    if (order == 8) return limit ? batch_kernel<8, true, true> : batch_kernel<8, false, true>;
+    return limit ? batch_kernel<10, true, true> : batch_kernel<10, false, true>;
+  }
+  if (order == 8) return limit ? batch_kernel<8, true, false> : batch_kernel<8, false, false>;
+  return limit ? batch_kernel<10, true, false> : batch_kernel<10, false, false>;
 }
 
 int64_t faces_along2(const tenoaa_grid& g, int d) {
@@ -706,7 +710,7 @@ int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const teno
   std::stable_sort(P->order.begin(), P->order.end(), [&](int a, int b) {
     return grids[a].n[0] * grids[a].n[1] > grids[b].n[0] * grids[b].n[1];
   });
-  P->kernel = pick_kernel(scheme->order, scheme->positivity != 0);
+  P->kernel = pick_kernel(scheme->order, scheme->positivity != 0, scheme->splitting == TENOAA_ROE);
   P->cache_key = make_key(P);
 
   int dev = 0, rate_khz = 0, nblk = 0;

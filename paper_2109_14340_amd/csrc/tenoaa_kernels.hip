@@ -49,7 +49,7 @@ namespace tenoaa {
 namespace {
 
 // ------------------------------------------------------------ sweep kernel
-template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT>
+template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT, bool ROE>
 __global__ __launch_bounds__(TT* TN)
 #if TENOAA_WAVES_PER_EU > 0
 __attribute__((amdgpu_waves_per_eu(TENOAA_WAVES_PER_EU)))
@@ -57,7 +57,7 @@ __attribute__((amdgpu_waves_per_eu(TENOAA_WAVES_PER_EU)))
 void sweep_kernel(SweepArgs A) {
   __shared__ __align__(16) char arena[SweepShape<ORDER, NDIM, TT, TN>::LDS_BYTES];
   const double mu = LIMIT ? A.mu[DIR] : 0.0;
-  sweep_tile<ORDER, NDIM, DIR, TT, TN, LIMIT>(A, arena, blockIdx.x, blockIdx.y, blockIdx.z, mu);
+  sweep_tile<ORDER, NDIM, DIR, TT, TN, LIMIT, ROE>(A, arena, blockIdx.x, blockIdx.y, blockIdx.z, mu);
 }
 
 // --------------------------------------------------- flux difference / RK
@@ -141,20 +141,22 @@ __global__ void finalize_dt_kernel(Scalars* S, int ndim, double dx0, double dx1,
 }  // namespace
 
 // ------------------------------------------------------------ host launchers
-template <int ORDER, int NDIM, int DIR, bool LIMIT>
+template <int ORDER, int NDIM, int DIR, bool LIMIT, bool ROE>
 static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   constexpr int TT = (NDIM == 1) ? 1 : (DIR == 0 ? TENOAA_TT_X : TENOAA_TT_YZ);
   constexpr int TN = (DIR == 0) ? TENOAA_TN_X : TENOAA_TN_YZ;
   constexpr int AX_A = (DIR == 0) ? 1 : 0;
   constexpr int AX_B = (DIR == 2) ? 1 : 2;
   dim3 grid((unsigned)((a.nf + TN - 1) / TN), (unsigned)((a.n[AX_A] + TT - 1) / TT), (unsigned)a.n[AX_B]);
-  hipLaunchKernelGGL((sweep_kernel<ORDER, NDIM, DIR, TT, TN, LIMIT>), grid, dim3(TT * TN), 0, st, a);
+  hipLaunchKernelGGL((sweep_kernel<ORDER, NDIM, DIR, TT, TN, LIMIT, ROE>), grid, dim3(TT * TN), 0, st, a);
   return hipGetLastError();
 }
 
 template <int ORDER, int NDIM, int DIR>
 static hipError_t launch_sweep_o(const SweepArgs& a, bool limit, hipStream_t st) {
-  return limit ? launch_sweep_t<ORDER, NDIM, DIR, true>(a, st) : launch_sweep_t<ORDER, NDIM, DIR, false>(a, st);
+  if (a.splitting == TENOAA_ROE)
+    return limit ? launch_sweep_t<ORDER, NDIM, DIR, true, true>(a, st) : launch_sweep_t<ORDER, NDIM, DIR, false, true>(a, st);
+  return limit ? launch_sweep_t<ORDER, NDIM, DIR, true, false>(a, st) : launch_sweep_t<ORDER, NDIM, DIR, false, false>(a, st);
 }
 
 template <int ORDER>

@@ -93,8 +93,9 @@ __device__ __forceinline__ void inflow_ghost(double* W, const double* pv, int64_
 // index across it, coordinate along the remaining axis).  `lds` holds at
 // least SweepShape::LDS_BYTES bytes, 16-byte aligned; the caller separates
 // consecutive tiles that reuse it with a barrier.  `mu` is the limiter factor
-// of this direction (used when LIMIT).
-template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT>
+// of this direction (used when LIMIT).  ROE selects the Roe flux with entropy
+// fix; otherwise A.splitting chooses LLF or Rusanov.
+template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT, bool ROE = false>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_t bx, int64_t by, int64_t bz,
                                            double mu) {
   using Sh = SweepShape<ORDER, NDIM, TT, TN>;
@@ -252,7 +253,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
   unroll<W>([&](auto j) {
     const int li = lbase + j * LSTEP;
     const double u = sUn[li], c = sC[li];
-    if (A.splitting == TENOAA_LLF) {
+    if (ROE || A.splitting == TENOAA_LLF) {  // LLF, also the Roe flux's fallback
       am = dmax(am, fabs(u - c));
       a0 = dmax(a0, fabs(u));
       ap = dmax(ap, fabs(u + c));
@@ -260,7 +261,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
       a0 = dmax(a0, fabs(u) + c);
     }
   });
-  if (A.splitting != TENOAA_LLF) am = ap = a0;
+  if (!ROE && A.splitting != TENOAA_LLF) am = ap = a0;
 
   int64_t flin;
   {
@@ -300,6 +301,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
       mut = -ut[0];
     }
     const double alpha = (s == 0) ? am : (s == NV - 1 ? ap : a0);
+    // Roe flux with entropy fix: where the field's eigenvalue keeps one
+    // strict sign at both cells of the face, the unsplit characteristic flux
+    // is reconstructed from the upwind side alone; elsewhere LLF
+    int upwind = 0;  // 0: split, 1: + side only, 2: - side only
+    if constexpr (ROE) {
+      const double ka = (s == 0) ? -1.0 : (s == NV - 1 ? 1.0 : 0.0);
+      const double la = sUn[ia] + ka * sC[ia], lb = sUn[ib] + ka * sC[ib];
+      upwind = (la > 0.0 && lb > 0.0) ? 1 : ((la < 0.0 && lb < 0.0) ? 2 : 0);
+    }
     // projection of the window's state and flux on field s, then the split
     double gp[W], gm[W];
     unroll<W>([&](auto j) {
@@ -320,8 +330,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
         v = mut * w0.x + ws.x;
         g = mut * w0.y + ws.y;
       }
-      gp[j] = 0.5 * fma(alpha, v, g);
-      gm[W - 1 - j] = 0.5 * fma(-alpha, v, g);  // mirrored for the - side
+      if (!ROE || upwind == 0) {
+        gp[j] = 0.5 * fma(alpha, v, g);
+        gm[W - 1 - j] = 0.5 * fma(-alpha, v, g);  // mirrored for the - side
+      } else {
+        gp[j] = g;
+        gm[W - 1 - j] = g;
+      }
 #if TENOAA_CELL_BARRIER
       __builtin_amdgcn_sched_barrier(0);
 #endif
@@ -334,6 +349,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
       flm = frozen[(int64_t)(s * 2 + 1) * A.nft];
       hp = replay_recon<ORDER>(gp, flp);
       hm = replay_recon<ORDER>(gm, flm);
+    } else if constexpr (ROE) {
+      hp = 0.0;
+      hm = 0.0;
+      if (upwind != 2) hp = teno_aa<ORDER>(gp, flp);
+      __builtin_amdgcn_sched_barrier(0);
+      if (upwind != 1) hm = teno_aa<ORDER>(gm, flm);
     } else {
       hp = teno_aa<ORDER>(gp, flp);
       // keep the two reconstructions from being interleaved (register pressure)
@@ -344,7 +365,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
       flag_out[(int64_t)(s * 2 + 0) * A.nft] = flp;
       flag_out[(int64_t)(s * 2 + 1) * A.nft] = flm;
     }
-    const double fh = hp + hm;
+    const double fh = (!ROE || upwind == 0) ? hp + hm : (upwind == 1 ? hp : hm);
     if (A.fh_out) A.fh_out[(int64_t)s * A.nft + flin] = fh;
     // back-projection F = sum_s R[:, s] fh_s, accumulated over s in order
     double r1 = 0.0, re = 0.0;

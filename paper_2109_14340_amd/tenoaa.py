@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtenoaa.so")
 
 BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP, BC_DIRICHLET, BC_INFLOW = 0, 1, 2, 3, 4, 5
-LLF, RUSANOV = 0, 1
+LLF, RUSANOV, ROE = 0, 1, 2
 WS_RHS, WS_STEP, WS_RHS_VJP, WS_STEP_VJP = 0, 1, 2, 3
 ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENONPHYSICAL", -5: "EWORKSPACE", -6: "ETIMEOUT"}
 

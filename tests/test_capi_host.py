@@ -46,7 +46,7 @@ def test_workspace_sizes():
     assert rhs % 256 == 0 and step % 256 == 0
 
 
-@pytest.mark.parametrize("field,value", [("order", 9), ("splitting", 2), ("positivity", 3)])
+@pytest.mark.parametrize("field,value", [("order", 9), ("splitting", 3), ("positivity", 3)])
 def test_bad_scheme_rejected(field, value):
     L = _lib()
     g = tenoaa.make_grid((64,))
@@ -124,6 +124,25 @@ def test_dirichlet_arguments_checked():
     arr = (tenoaa.Grid * 1)(ok)
     assert L.tenoaa_batch_plan_create(arr, 1, ctypes.byref(s), 1.4, 0.4, 2, None, ctypes.byref(h)) == -2
     assert h.value is None
+
+
+def test_roe_flux_options():
+    """The Roe flux is a valid scheme; the adjoint entry points and decision
+    replay reject it before any device work."""
+    L = _lib()
+    vp = ctypes.c_void_p
+    g = tenoaa.make_grid((64, 48))
+    s = tenoaa.make_scheme(10, tenoaa.ROE)
+    assert L.tenoaa_workspace_bytes(ctypes.byref(g), ctypes.byref(s), 0) > 0
+    bad = tenoaa.make_scheme(10, 3)
+    assert L.tenoaa_workspace_bytes(ctypes.byref(g), ctypes.byref(bad), 0) == 0
+    need = 1 << 30
+    assert L.tenoaa_rhs_vjp(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), None, vp(1024),
+                            need, None) == -2
+    assert L.tenoaa_step_vjp(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), vp(4096), None,
+                             vp(1024), need, None) == -2
+    assert L.tenoaa_step_flags(ctypes.byref(g), ctypes.byref(s), 1.4, 0.4, vp(256), vp(512), vp(4096),
+                               tenoaa.FLAGS_REPLAY, vp(1024), need, None) == -2
 
 
 def test_advect_rejects_bad_arguments():
