@@ -254,11 +254,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     const int li = lbase + j * LSTEP;
     const double u = sUn[li], c = sC[li];
     if (ROE || A.splitting == TENOAA_LLF) {  // LLF, also the Roe flux's fallback
-      am = dmax(am, fabs(u - c));
-      a0 = dmax(a0, fabs(u));
-      ap = dmax(ap, fabs(u + c));
+      am = fmax(am, fabs(u - c));
+      a0 = fmax(a0, fabs(u));
+      ap = fmax(ap, fabs(u + c));
     } else {
-      a0 = dmax(a0, fabs(u) + c);
+      a0 = fmax(a0, fabs(u) + c);
     }
   });
   if (!ROE && A.splitting != TENOAA_LLF) am = ap = a0;
