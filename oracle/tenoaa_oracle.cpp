@@ -651,17 +651,49 @@ const double* face_values(const Grid& g, int G, int d, int hi, int set, int64_t 
   return g.bc_values[d][hi] + (int64_t)set * layers * (g.ndim + 2) * plane + pidx;
 }
 
-// a_d = max over cells of |u_d| + c (used for dt and the limiter weights).
+// a_d = max of |u_d| + c over the cells and over the ghost cells next to the
+// faces of every side with prescribed values (Dirichlet, inflow; value set 0),
+// whose states the boundary faces see; the ghosts of the other boundaries
+// copy domain cells.  Used for dt and the limiter weights.
 void wave_speeds(const Grid& g, double gam, const double* U, double* amax) {
   const int nv = g.ndim + 2;
   const int64_t nc = g.n[0] * g.n[1] * g.n[2];
   for (int d = 0; d < 3; ++d) amax[d] = 0.0;
   double W[5];
   CellQ<double> q;
+  auto fold = [&](const double* w) {
+    cell_state(g.ndim, gam, 0, w, q);
+    for (int d = 0; d < g.ndim; ++d) amax[d] = std::max(amax[d], std::fabs(q.u[d]) + q.c);
+  };
   for (int64_t i = 0; i < nc; ++i) {
     for (int c = 0; c < nv; ++c) W[c] = U[c * nc + i];
-    cell_state(g.ndim, gam, 0, W, q);
-    for (int d = 0; d < g.ndim; ++d) amax[d] = std::max(amax[d], std::fabs(q.u[d]) + q.c);
+    fold(W);
+  }
+  const int64_t stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
+  double Gh[5];
+  for (int d = 0; d < g.ndim; ++d) {
+    int oa[2], no = 0;
+    for (int k = 0; k < 3; ++k)
+      if (k != d) oa[no++] = k;
+    const int64_t plane = plane_cells(g, d);
+    for (int hi = 0; hi < 2; ++hi) {
+      const int bc = hi ? g.bc_hi[d] : g.bc_lo[d];
+      if (bc != BC_DIRICHLET && bc != BC_INFLOW) continue;
+      for (int64_t o1 = 0; o1 < g.n[oa[1]]; ++o1)
+        for (int64_t o0 = 0; o0 < g.n[oa[0]]; ++o0) {
+          const int64_t pidx = o0 + g.n[oa[0]] * o1;
+          const int64_t cell = (hi ? g.n[d] - 1 : 0) * stride[d] + o0 * stride[oa[0]] + o1 * stride[oa[1]];
+          // the G argument only places inflow layers, and layer 1 is first in either case
+          const double* fv = face_values(g, 1, d, hi, 0, pidx);
+          if (bc == BC_DIRICHLET) {
+            for (int c = 0; c < nv; ++c) W[c] = U[c * nc + cell];
+            dirichlet_ghost<double>(g.ndim, gam, W, fv, plane, Gh);
+          } else {
+            inflow_ghost<double>(g.ndim, gam, fv, plane, Gh);
+          }
+          fold(Gh);
+        }
+    }
   }
 }
 

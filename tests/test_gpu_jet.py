@@ -1,0 +1,86 @@
+"""The high Mach number astrophysical jets of the paper's Sec. 5.3 on the GPU
+(gamma = 5/3, ambient gas (rho, u, v, p) = (0.5, 0, 0, 0.4127); the left side
+holds (5, u_jet, 0, 0.4127) for |y| <= 0.05 and (5, 0, 0, 0.4127) elsewhere,
+given as prescribed inflow ghost cells; outflow on the other sides; LLF with
+the positivity limiter).  Mach 80: [0, 2] x [-0.5, 0.5], 448 x 224, u_jet = 30;
+Mach 2000: [0, 1] x [-0.25, 0.25], 800 x 400, u_jet = 800.  The final times
+are not stated; reading: t = 0.07 and t = 0.001, when the jet head has crossed
+most of the domain.  The GPU steps bit for bit as the oracle does for the
+first steps; the runs stay physical (no non-physical state is ever read)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2109_14340_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2109_14340_amd import tenoaa  # noqa: E402
+
+GAMMA = 5.0 / 3.0
+CASES = {"mach80": (448, 224, 2.0, 1.0, 30.0, 0.07), "mach2000": (800, 400, 1.0, 0.5, 800.0, 0.001)}
+
+
+def _setup(case, order):
+    nx, ny, Lx, Ly, ujet, tf = CASES[case]
+    dx, dy = Lx / nx, Ly / ny
+    U0 = inputs._as_layout(inputs.conserved_from_primitive(np.full((nx, ny), 0.5), [np.zeros((nx, ny))] * 2,
+                                                           np.full((nx, ny), 0.4127), GAMMA), 2)
+    y = -0.5 * Ly + (np.arange(ny) + 0.5) * dy
+    inside = np.abs(y) <= 0.05
+    G = order // 2
+    layer = np.stack([np.full(ny, 5.0), np.where(inside, ujet, 0.0), np.zeros(ny), np.full(ny, 0.4127)])
+    left = np.ascontiguousarray(np.broadcast_to(layer, (1, G, 4, ny)))
+    bc_lo, bc_hi = [tenoaa.BC_INFLOW, tenoaa.BC_OUTFLOW], [tenoaa.BC_OUTFLOW, tenoaa.BC_OUTFLOW]
+    g = tenoaa.make_grid((nx, ny), dx=[dx, dy], bc_lo=bc_lo, bc_hi=bc_hi,
+                         bc_values={(0, 0): torch.from_numpy(left).cuda()})
+    g_or = oracle.make_grid((nx, ny), [dx, dy], bc_lo, bc_hi, bc_values={(0, 0): left})
+    return U0, g, g_or, dx, dy, tf
+
+
+def _host_dt(U, dx, dy, cfl=0.4):
+    rho = U[0, 0]
+    u, v = U[1, 0] / rho, U[2, 0] / rho
+    p = (GAMMA - 1.0) * (U[3, 0] - 0.5 * rho * (u * u + v * v))
+    c = np.sqrt(GAMMA * p / rho)
+    return cfl / ((np.abs(u) + c).max() / dx + (np.abs(v) + c).max() / dy)
+
+
+@pytest.mark.parametrize("order", [8, 10])
+@pytest.mark.parametrize("case", list(CASES))
+def test_astrophysical_jet(case, order):
+    U0, g, g_or, dx, dy, tf = _setup(case, order)
+    sch = tenoaa.make_scheme(order, tenoaa.LLF, 1)
+    ws = tenoaa.workspace(g, sch, tenoaa.WS_STEP)
+    U = torch.from_numpy(U0).cuda()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Uo, t, k, h = U0, 0.0, 0, 0.0
+    while t < tf * (1 - 1e-12):
+        if t + 2.0 * h >= tf:
+            dt.fill_(min(_host_dt(U.cpu().numpy(), dx, dy), tf - t))
+        else:
+            dt.zero_()
+        tenoaa.step(g, sch, U, dt, gamma=GAMMA, ws=ws)
+        h = float(dt.item())
+        if k < 2:
+            Uo, _, _, _ = oracle.step(g_or, Uo, order=order, splitting=0, positivity=1, dt=h, gamma=GAMMA)
+            if k == 1:
+                assert np.array_equal(U.cpu().numpy(), Uo), "GPU and oracle differ after 2 steps"
+        t += h
+        k += 1
+    assert tenoaa.get_status(ws) == 0, "a non-physical state was read"
+    Uh = U.cpu().numpy()
+    rho = Uh[0, 0]
+    p = (GAMMA - 1.0) * (Uh[3, 0] - 0.5 * (Uh[1, 0] ** 2 + Uh[2, 0] ** 2) / rho)
+    assert rho.min() > 0 and p.min() > 0
+    nx = rho.shape[1]
+    x = (np.arange(nx) + 0.5) * dx
+    # the bow shock: the furthest column whose density departs from the ambient 0.5
+    disturbed = np.nonzero(np.abs(rho - 0.5).max(axis=0) > 1e-3)[0]
+    front = x[disturbed.max()] if len(disturbed) else 0.0
+    print(case, "order", order, "steps", k, "front at x = %.3f" % front, "rho %.3e .. %.3e" % (rho.min(), rho.max()),
+          "p %.3e .. %.3e" % (p.min(), p.max()))

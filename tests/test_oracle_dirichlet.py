@@ -238,3 +238,29 @@ def test_inflow_stage_value_sets_follow_the_stage_times():
     assert rate(e_right) > 1.8
     assert rate(e_wrong) < 1.3
     assert e_right[1] < 0.01 * e_wrong[1]
+
+
+def test_wave_speeds_include_prescribed_ghosts():
+    """The CFL speeds a_d take in the ghost cell next to each face of a side
+    with prescribed values (value set 0): a fast inflow raises a_x to its
+    |u| + c, a Dirichlet side its reflected ghost's speed."""
+    nx, ny = 20, 16
+    dx, dy = 1.0 / nx, 1.0 / ny
+    g5 = 5.0 / 3.0
+    U = inputs._as_layout(inputs.conserved_from_primitive(np.full((nx, ny), 0.5), [np.zeros((nx, ny))] * 2,
+                                                          np.full((nx, ny), 0.4127), g5), 2)
+    c_amb = np.sqrt(g5 * 0.4127 / 0.5)
+    layer = np.stack([np.full(ny, 5.0), np.where(np.arange(ny) == 7, 30.0, 0.0), np.zeros(ny), np.full(ny, 0.4127)])
+    fv = {(0, 0): np.broadcast_to(layer, (1, 4, 4, ny)).copy()}
+    g = oracle.make_grid((nx, ny), [dx, dy], [oracle.BC_INFLOW, oracle.BC_OUTFLOW], [oracle.BC_OUTFLOW] * 2,
+                         bc_values=fv)
+    a = oracle.wave_speeds(g, g5, U)
+    c_jet = np.sqrt(g5 * 0.4127 / 5.0)
+    assert abs(a[0] - (30.0 + c_jet)) <= 1e-14 * 30 and abs(a[1] - c_amb) <= 1e-15
+    assert abs(oracle.dt(g, g5, 0.4, U) - 0.4 / (a[0] / dx + a[1] / dy)) <= 1e-18
+    # Dirichlet: the ghost next to the face is 2 face - boundary cell
+    face = np.stack([np.full(ny, 0.5), np.full(ny, 2.0), np.zeros(ny), np.full(ny, 0.4127)])[None]
+    gd = oracle.make_grid((nx, ny), [dx, dy], [oracle.BC_DIRICHLET, oracle.BC_OUTFLOW], [oracle.BC_OUTFLOW] * 2,
+                          bc_values={(0, 0): face})
+    ad = oracle.wave_speeds(gd, g5, U)
+    assert abs(ad[0] - (4.0 + c_amb)) <= 1e-14 * 4  # u_ghost = 2 * 2 - 0, rho and p unchanged
