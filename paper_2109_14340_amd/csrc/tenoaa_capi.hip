@@ -189,6 +189,30 @@ const double* face_values(const tenoaa_grid* g, int order, int d, int h, int sta
   return g->bc_values[d][h] + (int64_t)set * layers * (g->ndim + 2) * plane;
 }
 
+// a_d over the cells of U and over the ghost cells next to the faces of every
+// side with prescribed values (value set 0), which the boundary faces see.
+hipError_t wave_speeds(const Ctx& c, const double* U) {
+  const tenoaa_grid* g = c.g;
+  const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
+  hipError_t e = tenoaa::launch_wave_speeds(g->ndim, U, ncell, c.gamma, c.S, &c.S->status, c.st);
+  for (int d = 0; d < g->ndim && e == hipSuccess; ++d)
+    for (int h = 0; h < 2 && e == hipSuccess; ++h) {
+      const double* fv = face_values(g, c.s->order, d, h, 0);
+      if (!fv) continue;
+      tenoaa::GhostSpeedArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.U = U;
+      a.fv = fv;
+      for (int k = 0; k < 3; ++k) a.n[k] = g->n[k];
+      a.dir = d;
+      a.hi = h;
+      a.bc = h ? g->bc_hi[d] : g->bc_lo[d];
+      a.gamma = c.gamma;
+      e = tenoaa::launch_ghost_speeds(g->ndim, a, c.S, &c.S->status, c.st);
+    }
+  return e;
+}
+
 // Face fluxes of every direction for state U; flags optional.  `stage`
 // selects the Dirichlet value set.
 int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint8_t* frozen = nullptr,
@@ -346,7 +370,7 @@ int tenoaa_rhs(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamm
   const int64_t ncell = grid->n[0] * grid->n[1] * grid->n[2];
   if (limit) {
     hipError_t e = timed(TENOAA_KCLASS_WAVESPEED, c.st, [&] {
-      hipError_t r = tenoaa::launch_wave_speeds(grid->ndim, U, ncell, gamma, c.S, &c.S->status, c.st);
+      hipError_t r = wave_speeds(c, U);
       if (r == hipSuccess) r = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, 1.0, nullptr, dt_limiter, c.st);
       return r;
     });
@@ -382,7 +406,7 @@ int tenoaa_step_flags(const tenoaa_grid* grid, const tenoaa_scheme* scheme, doub
   auto rep = [&](int st) { return mode == TENOAA_FLAGS_REPLAY ? (const uint8_t*)flags3 + st * nfl : nullptr; };
   const bool limit = scheme->positivity != 0;
   hipError_t e = timed(TENOAA_KCLASS_WAVESPEED, c.st, [&] {
-    hipError_t r = tenoaa::launch_wave_speeds(grid->ndim, U, ncell, gamma, c.S, &c.S->status, c.st);
+    hipError_t r = wave_speeds(c, U);
     if (r == hipSuccess) r = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, cfl, dt_dev, 0.0, c.st);
     return r;
   });

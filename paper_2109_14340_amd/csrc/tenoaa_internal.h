@@ -49,6 +49,15 @@ struct UpdateArgs {
   const double* dt;  // device
 };
 
+// One side with prescribed values, for the ghost-cell wave speeds.
+struct GhostSpeedArgs {
+  const double* U;
+  const double* fv;  // the side's values, set 0 (face values or the first inflow layer)
+  int64_t n[3];
+  int dir, hi, bc, pad;
+  double gamma;
+};
+
 struct AdjointArgs {
   const double* U;   // state at which the right-hand side is differentiated
   const double* R;   // seed: adjoint of dU/dt, layout of U
@@ -82,6 +91,7 @@ hipError_t launch_sweep(int order, int ndim, int dir, const SweepArgs& a, bool l
 hipError_t launch_update(int ndim, int mode, const UpdateArgs& a, hipStream_t st);
 hipError_t launch_wave_speeds(int ndim, const double* U, int64_t ncell, double gam, Scalars* S, int* status,
                               hipStream_t st);
+hipError_t launch_ghost_speeds(int ndim, const GhostSpeedArgs& a, Scalars* S, int* status, hipStream_t st);
 hipError_t launch_finalize_dt(Scalars* S, int ndim, const double* dx, double cfl, double* dt_dev, double dt_fixed,
                               hipStream_t st);
 

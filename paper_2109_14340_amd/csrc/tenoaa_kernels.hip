@@ -124,6 +124,47 @@ __global__ __launch_bounds__(256) void wave_speed_kernel(const double* U, int64_
   }
 }
 
+// The ghost cells next to the faces of one side with prescribed values
+// (Dirichlet: the boundary cell reflected through the face values; inflow:
+// the first prescribed layer) folded into the wave speeds, as the boundary
+// faces see them.  One thread per cell of the face plane.
+template <int NDIM>
+__global__ __launch_bounds__(256) void ghost_speed_kernel(GhostSpeedArgs A, Scalars* S, int* status) {
+  constexpr int NV = NDIM + 2;
+  double amax[NDIM];
+  unroll<NDIM>([&](auto d) { amax[d] = 0.0; });
+  bool bad = false;
+  const int64_t ncell = A.n[0] * A.n[1] * A.n[2];
+  const int64_t stride[3] = {1, A.n[0], A.n[0] * A.n[1]};
+  const int a0 = (A.dir == 0) ? 1 : 0, a1 = (A.dir == 2) ? 1 : 2;
+  const int64_t plane = A.n[a0] * A.n[a1];
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < plane; p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o0 = p % A.n[a0], o1 = p / A.n[a0];
+    const int64_t cell = (A.hi ? A.n[A.dir] - 1 : 0) * stride[A.dir] + o0 * stride[a0] + o1 * stride[a1];
+    double Wc[NV];
+    if (A.bc == TENOAA_BC_DIRICHLET) {
+      unroll<NV>([&](auto c) { Wc[c] = A.U[c * ncell + cell]; });
+      dirichlet_ghost<NDIM>(Wc, A.fv + p, plane, A.gamma - 1.0);
+    } else {
+      inflow_ghost<NDIM>(Wc, A.fv + p, plane, A.gamma - 1.0);
+    }
+    cell_speeds<NDIM>(Wc, A.gamma, amax, bad);
+  }
+  if (bad) atomicOr(status, 1);
+  __shared__ double red[NDIM][256];
+  unroll<NDIM>([&](auto d) { red[d][threadIdx.x] = amax[d]; });
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      unroll<NDIM>([&](auto d) { red[d][threadIdx.x] = dmax(red[d][threadIdx.x], red[d][threadIdx.x + s]); });
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    unroll<NDIM>([&](auto d) { atomicMax(&S->amax_bits[d], (unsigned long long)__double_as_longlong(red[d][0])); });
+  }
+}
+
 // dt and the limiter factors from the wave speeds; dt is taken from dt_fixed
 // or *dt_dev when positive, else from the CFL condition, and stored back.
 __global__ void finalize_dt_kernel(Scalars* S, int ndim, double dx0, double dx1, double dx2, double cfl,
@@ -216,6 +257,17 @@ hipError_t launch_wave_speeds(int ndim, const double* U, int64_t ncell, double g
   if (ndim == 1) hipLaunchKernelGGL(wave_speed_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, U, ncell, gam, S, status);
   if (ndim == 2) hipLaunchKernelGGL(wave_speed_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, st, U, ncell, gam, S, status);
   if (ndim == 3) hipLaunchKernelGGL(wave_speed_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, st, U, ncell, gam, S, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_ghost_speeds(int ndim, const GhostSpeedArgs& a, Scalars* S, int* status, hipStream_t st) {
+  const int a0 = (a.dir == 0) ? 1 : 0, a1 = (a.dir == 2) ? 1 : 2;
+  const int64_t plane = a.n[a0] * a.n[a1];
+  int64_t blocks = (plane + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (ndim == 1) hipLaunchKernelGGL(ghost_speed_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, a, S, status);
+  if (ndim == 2) hipLaunchKernelGGL(ghost_speed_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, st, a, S, status);
+  if (ndim == 3) hipLaunchKernelGGL(ghost_speed_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, st, a, S, status);
   return hipGetLastError();
 }
 

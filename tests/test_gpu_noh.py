@@ -135,8 +135,8 @@ def test_noh_64_against_analytic_density(order):
           err_pre.mean()), "post-shock mean %.3f min %.3f max %.3f" % (post_mean, rho[post].min(), rho[post].max()),
           "shock radius %.4f (exact 0.2)" % r_shock, "rho at origin %.2f" % rho[0, 0, 0],
           "axis-permutation asymmetry %.2e" % sym, "max rho %.2f" % rho.max())
-    # measured on MI355X: pre-shock mean error 0.042 (AA8) / 0.041 (AA10),
-    # post-shock mean 61.4 / 61.5, shock radius 0.2028 for both, peak 73 / 70
+    # measured on MI355X: pre-shock mean error 0.041 (AA8) / 0.041 (AA10),
+    # post-shock mean 61.4 / 61.5, shock radius 0.2028 for both, peak 73.0 / 69.4
     assert err_pre.mean() < 0.06
     assert abs(post_mean / 64.0 - 1.0) < 0.08
     assert abs(r_shock - 0.2) < L / n
