@@ -269,6 +269,11 @@ def eigen(ndim, gamma, d, Wa, Wb):
 
 
 def decode_flag(flag):
-    """(large stencil chosen: 0 none / 3 / 4 / 5, (delta0, delta1, delta2), K)."""
+    """(large stencil chosen: 0 none / 3 / 4 / 5 / 6, (delta0, delta1, delta2), K).
+    S6 (TENO12-AA only) is bits 0-1 = 3 with bit 2 set; the deltas are those of
+    the fallback and (0, 0, 0) when a large stencil is chosen."""
     sel = flag & 3
-    return (sel + 2 if sel else 0), ((flag >> 2) & 1, (flag >> 3) & 1, (flag >> 4) & 1), 7 + (flag >> 5)
+    K = 7 + (flag >> 5)
+    if sel == 3 and (flag & 4):
+        return 6, (0, 0, 0), K
+    return (sel + 2 if sel else 0), ((flag >> 2) & 1, (flag >> 3) & 1, (flag >> 4) & 1), K

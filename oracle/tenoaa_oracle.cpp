@@ -111,9 +111,17 @@ const double LIN10[10] = {0.001911786299492748, -0.0170332977472532,  0.07339445
                           -0.2145617624175796,  0.07053731329146805,  -0.01631901203296621,
                           0.001832421220128962};
 
+// TENO12-AA (the framework of Sec. 3.1 with one more symmetric large
+// stencil, S6 = cells i-5 .. i+6): the paper prints no optimised scheme for
+// it, so S6 takes the maximum-order (12th) reconstruction, written by
+// gen_teno12.py in exact arithmetic and rounded once.
+const double LIN12[12] = {-0.00018037518037518038, 0.002417027417027417, -0.01544011544011544, 0.06392496392496393,
+                          -0.20393217893217894,    0.6532106782106782,   0.6532106782106782,   -0.20393217893217894,
+                          0.06392496392496393,     -0.01544011544011544, 0.002417027417027417, -0.00018037518037518038};
+
 // Candidate stencils of Sec. 3.1 / 4.2, as (leftmost cell offset from i, width).
-const int ST_LO[6] = {-1, 0, -2, -2, -3, -4};
-const int ST_R[6] = {3, 3, 3, 6, 8, 10};
+const int ST_LO[7] = {-1, 0, -2, -2, -3, -4, -5};
+const int ST_R[7] = {3, 3, 3, 6, 8, 10, 12};
 
 // ---------------------------------------------- smoothness indicator tables
 // beta_{k,r} = sum_{j=1}^{r-1} dx^{2j-1} int_{cell i} (d^j p_k/dx^j)^2 dx.
@@ -127,10 +135,10 @@ const int ST_R[6] = {3, 3, 3, 6, 8, 10};
 // polynomial of degree r-1-j is exact with (r-1)-point Gauss-Legendre.
 struct BetaTable {
   int r = 0, lo = 0, nq = 0;
-  double w[9];
-  double M[9][9][9];  // M[j-1][q][m-1] = omega_{m+1}^{(j+1)}(x_q) / (m+1)!
+  double w[11];
+  double M[11][11][11];  // M[j-1][q][m-1] = omega_{m+1}^{(j+1)}(x_q) / (m+1)!
 };
-BetaTable g_beta[6];
+BetaTable g_beta[7];
 bool g_beta_ready = false;
 
 void gauss_legendre(int n, double* x, double* w) {
@@ -164,24 +172,24 @@ void gauss_legendre(int n, double* x, double* w) {
 
 void build_beta_tables() {
   if (g_beta_ready) return;
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < 7; ++k) {
     BetaTable& T = g_beta[k];
     T.r = ST_R[k];
     T.lo = ST_LO[k];
     T.nq = T.r - 1;
-    double gx[9], gw[9];
+    double gx[11], gw[11];
     gauss_legendre(T.nq, gx, gw);
     const double e = -T.lo;  // local index of cell i inside the stencil
     for (int q = 0; q < T.nq; ++q) T.w[q] = 0.5 * gw[q];
     std::memset(T.M, 0, sizeof(T.M));
     for (int m = 1; m <= T.r - 1; ++m) {
       // omega_{m+1}(e + t) as a polynomial in t (coefficients are dyadic, exact).
-      double c[12] = {0};
+      double c[14] = {0};
       c[0] = 1.0;
       int deg = 0;
       for (int b = 0; b <= m; ++b) {
         const double root = (b - 0.5) - e;  // factor (t - root)
-        double nc[12] = {0};
+        double nc[14] = {0};
         for (int a = 0; a <= deg; ++a) {
           nc[a + 1] += c[a];
           nc[a] -= root * c[a];
@@ -193,7 +201,7 @@ void build_beta_tables() {
       for (int a = 2; a <= m + 1; ++a) fact *= a;
       for (int j = 1; j <= m; ++j) {
         // (j+1)-th derivative of the t-polynomial
-        double dc[12] = {0};
+        double dc[14] = {0};
         for (int a = j + 1; a <= deg; ++a) {
           double f = 1.0;
           for (int s = 0; s <= j; ++s) f *= (a - s);
@@ -214,7 +222,7 @@ void build_beta_tables() {
 // f points at the stencil's leftmost value; returns beta for candidate k.
 double beta_of(int k, const double* f) {
   const BetaTable& T = g_beta[k];
-  double tab[10], dif[9];
+  double tab[12], dif[11];
   for (int l = 0; l < T.r; ++l) tab[l] = f[l];
   for (int m = 1; m <= T.r - 1; ++m) {
     for (int l = 0; l + m < T.r; ++l) tab[l] = tab[l + 1] - tab[l];
@@ -232,8 +240,9 @@ double beta_of(int k, const double* f) {
 }
 
 // ------------------------------------------------- scalar TENO-AA reconstruction
-// Flag byte: bits 0-1 = chosen large stencil (0 none, 1 S3, 2 S4, 3 S5),
-// bits 2-4 = delta_0..delta_2 of the fallback, bits 5-7 = [beta] - 7.
+// Flag byte: bits 0-1 = chosen large stencil (0 none, 1 S3, 2 S4, 3 S5 or,
+// with bit 2 set, S6), bits 2-4 = delta_0..delta_2 of the fallback (free when
+// a large stencil is chosen), bits 5-7 = [beta] - 7.
 struct Decision {
   uint8_t flag = 0;
   double margin = INFINITY;  // min relative distance of any decision to its threshold
@@ -249,7 +258,7 @@ T small_flux(int k, const T* fi) {
 
 template <class T>
 T large_flux(int k, const T* fi) {
-  const double* c = (k == 3) ? LIN6 : (k == 4) ? LIN8 : LIN10;
+  const double* c = (k == 3) ? LIN6 : (k == 4) ? LIN8 : (k == 5) ? LIN10 : LIN12;
   const int lo = ST_LO[k], r = ST_R[k];
   T acc = c[0] * fi[lo];
   for (int m = 1; m < r; ++m) acc = fmaT(T(c[m]), fi[lo + m], acc);
@@ -268,8 +277,11 @@ T fallback_flux(uint8_t dmask, const T* fi) {
 
 double rel_margin(double chi, double ct) { return std::fabs(chi / ct - 1.0); }
 
-// fv = f_{-G+1..G} (r = 2G values); i sits at index G-1.  order is 8 or 10.
-// If frozen is non-null the decisions are taken from *frozen instead.
+// Large stencil p (3..6) as a flag byte's bits 0-2.
+int sel_bits(int p) { return p == 6 ? (3 | 4) : p - 2; }
+
+// fv = f_{-G+1..G} (r = 2G values); i sits at index G-1.  order is 8, 10 or
+// 12.  If frozen is non-null the decisions are taken from *frozen instead.
 template <class T>
 T teno_aa(int order, const T* fv, Decision* dec, const uint8_t* frozen) {
   const int G = order / 2;
@@ -277,10 +289,11 @@ T teno_aa(int order, const T* fv, Decision* dec, const uint8_t* frozen) {
   if (frozen) {
     const uint8_t fl = *frozen;
     const int sel = fl & 3;
+    if (sel == 3 && (fl & 4)) return large_flux(6, fi);
     if (sel) return large_flux(sel + 2, fi);
     return fallback_flux<T>((fl >> 2) & 7, fi);
   }
-  double f[10];
+  double f[12];
   for (int l = 0; l < order; ++l) f[l] = re(fv[l]);
   const double* x = f + (G - 1);  // x[k] = f_{i+k}
 
@@ -307,14 +320,14 @@ T teno_aa(int order, const T* fv, Decision* dec, const uint8_t* frozen) {
   if (m > 0.0) d.margin = std::min(d.margin, std::fabs(B - std::nearbyint(B)) / B);
 
   // Sec. 3.2: scale separation on the three small stencils.
-  double gam[6];
+  double gam[7];
   for (int k = 0; k < 3; ++k) {
     const double xb = beta_of(k, x + ST_LO[k]) + EPS;
     const double x2 = xb * xb, x4 = x2 * x2;
     gam[k] = 1.0 / ((x4 * x2) * xb);
   }
   // Sec. 3.3: groups (S0,S1,S2,Sp), largest p first.
-  const int pmax = (order == 10) ? 5 : 4;
+  const int pmax = order / 2;
   for (int p = pmax; p >= 3; --p) {
     const double xb = beta_of(p, x + ST_LO[p]) + EPS;
     const double x2 = xb * xb, x4 = x2 * x2;
@@ -322,7 +335,7 @@ T teno_aa(int order, const T* fv, Decision* dec, const uint8_t* frozen) {
     const double chi = gam[p] / (((gam[0] + gam[1]) + gam[2]) + gam[p]);
     d.margin = std::min(d.margin, rel_margin(chi, CT));
     if (chi >= CT) {
-      d.flag = (uint8_t)((p - 2) | ((K - 7) << 5));
+      d.flag = (uint8_t)(sel_bits(p) | ((K - 7) << 5));
       if (dec) *dec = d;
       return large_flux(p, fi);
     }
@@ -717,7 +730,7 @@ void face_flux(const Grid& g, const Scheme& sc, double gam, int d, const CellQ<T
   const CellQ<T>& cb = cl[f];
   Eigen<T> e;
   roe_eigen(nd, gam, d, ca, cb, e);
-  T v[10], gch[10], gp[10], gm[10], fv[10];
+  T v[12], gch[12], gp[12], gm[12], fv[12];
   T fhat[5];
   for (int s = 0; s < nv; ++s) {
     // projection onto field s of the conserved state and physical flux
@@ -889,7 +902,7 @@ void ssp_rk3(int64_t N, double dt, double* U, RHS&& L) {
 
 int check_grid(const Grid& g, const Scheme& s) {
   if (g.ndim < 1 || g.ndim > 3) return -1;
-  if (s.order != 8 && s.order != 10) return -1;
+  if (s.order != 8 && s.order != 10 && s.order != 12) return -1;
   for (int d = 0; d < 3; ++d) {
     if (g.n[d] < 1) return -1;
     if (d < g.ndim) {
@@ -943,10 +956,10 @@ static Grid to_grid(const or_grid* g) {
   return r;
 }
 
-// beta of candidate k (0..5) for the values of its stencil, leftmost first.
+// beta of candidate k (0..6) for the values of its stencil, leftmost first.
 double or_beta(int k, const double* f) {
   build_beta_tables();
-  if (k < 0 || k > 5) return NAN;
+  if (k < 0 || k > 6) return NAN;
   return beta_of(k, f);
 }
 
@@ -960,7 +973,7 @@ double or_teno(int order, const double* fv, uint8_t* flag, double* margin) {
   return h;
 }
 
-// Candidate flux k (0..5) at i+1/2; fi points at f_i inside a long enough array.
+// Candidate flux k (0..6) at i+1/2; fi points at f_i inside a long enough array.
 double or_candidate_flux(int k, const double* fi) {
   if (k < 3) return small_flux(k, fi);
   return large_flux(k, fi);
@@ -1115,7 +1128,7 @@ int or_step(const or_grid* g, int order, int splitting, int positivity, double g
 // enters.  dudt = -(fhat_{i+1/2} - fhat_{i-1/2})/dx.
 int or_advect_rhs(int order, int64_t n, double dx, const double* u, double* dudt, uint8_t* flags) {
   build_beta_tables();
-  if ((order != 8 && order != 10) || n < order) return -1;
+  if ((order != 8 && order != 10 && order != 12) || n < order) return -1;
   const int G = order / 2;
   std::vector<double> fh((size_t)n), fv((size_t)(2 * G));
   for (int64_t i = 0; i < n; ++i) {
@@ -1130,7 +1143,7 @@ int or_advect_rhs(int order, int64_t n, double dx, const double* u, double* dudt
 
 // One SSP-RK3 step of the periodic scalar advection problem with time step dt.
 int or_advect_step(int order, int64_t n, double dx, double dt, double* u, uint8_t* flags3) {
-  if ((order != 8 && order != 10) || n < order) return -1;
+  if ((order != 8 && order != 10 && order != 12) || n < order) return -1;
   ssp_rk3(n, dt, u, [&](int st, const double* in, double* out) {
     or_advect_rhs(order, n, dx, in, out, flags3 ? flags3 + st * n : nullptr);
   });
