@@ -27,9 +27,10 @@
  *    split side, face), laid out [d][field][side][face array of d] with the
  *    directions concatenated in order x, y, z.  Fields are ordered
  *    (u-c, u, shear..., u+c); side 0 is the upwind-biased (+) side.  Bits
- *    0-1: large stencil chosen (0 none, 1 S3, 2 S4, 3 S5); bits 2-4: the
- *    cut-off deltas of the three small stencils when none was chosen;
- *    bits 5-7: [beta] - 7 of the adaptive C_T = 10^-[beta] (Sec. 3.4).
+ *    0-1: large stencil chosen (0 none, 1 S3, 2 S4, 3 S5, or S6 of TENO12-AA
+ *    when bit 2 is also set); bits 2-4: the cut-off deltas of the three
+ *    small stencils when none was chosen; bits 5-7: [beta] - 7 of the
+ *    adaptive C_T = 10^-[beta] (Sec. 3.4).
  *  - Streams: `stream` is a hipStream_t passed as void*; NULL is the null
  *    stream.  Calls enqueue work and return without synchronising, except
  *    where stated.  Calls on distinct (stream, workspace) pairs are
@@ -123,7 +124,11 @@ typedef struct {
   const double* bc_values[3][2];
 } tenoaa_grid;
 
-/* order: 8 (TENO8-AA) or 10 (TENO10-AA), Sec. 4; splitting: TENOAA_LLF,
+/* order: 8 (TENO8-AA) or 10 (TENO10-AA), Sec. 4, or 12 (TENO12-AA: the
+ * Sec. 3.1 framework with one more symmetric large stencil S6 = cells
+ * i-5 .. i+6 tried before S5; the paper prints no optimised scheme for it, so
+ * S6 uses the maximum-order (12th) reconstruction; not supported by the
+ * adjoint entry points and the batch plan); splitting: TENOAA_LLF,
  * TENOAA_RUSANOV or TENOAA_ROE; positivity: 1 enables the flux limiter. */
 typedef struct {
   int32_t order;
@@ -194,7 +199,7 @@ int tenoaa_step_flags(const tenoaa_grid* grid, const tenoaa_scheme* scheme, doub
 /* Scalar linear advection u_t + u_x = 0 on a periodic grid of n cells of
  * width dx (Sec. 5.1, the paper's accuracy test): `nsteps` SSP-RK3 steps of
  * size dt of du_i/dt = -(fhat_{i+1/2} - fhat_{i-1/2}) / dx, where fhat_{i+1/2}
- * is the TENO-AA reconstruction (order 8 or 10) of the flux f = u from cells
+ * is the TENO-AA reconstruction (order 8, 10 or 12) of the flux f = u from cells
  * i - order/2 + 1 .. i + order/2 (the speed is +1, so no splitting).  u (device,
  * n doubles) is advanced in place.  n in [order, 2048] (one workgroup holds
  * the grid in LDS); dx > 0, dt > 0, nsteps >= 0; TENOAA_EINVAL otherwise.  Enqueued on `stream` as one launch. */

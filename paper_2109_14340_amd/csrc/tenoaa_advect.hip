@@ -71,13 +71,16 @@ __global__ __launch_bounds__(ADV_THREADS) void advect_kernel(double* u, int n, d
 
 extern "C" int tenoaa_advect(int32_t order, int64_t n, double dx, double dt, int64_t nsteps, double* u,
                              void* stream) {
-  if (order != 8 && order != 10) return TENOAA_EINVAL;
+  if (order != 8 && order != 10 && order != 12) return TENOAA_EINVAL;
   if (n < order || n > tenoaa::ADV_MAX_CELLS || !u || nsteps < 0) return TENOAA_EINVAL;
   if (!(dx > 0.0) || !(dt > 0.0) || dx > 1e300 || dt > 1e300) return TENOAA_EINVAL;
   if (nsteps == 0) return TENOAA_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t lds = 3 * (size_t)n * sizeof(double);
-  if (order == 10)
+  if (order == 12)
+    hipLaunchKernelGGL(tenoaa::advect_kernel<12>, dim3(1), dim3(tenoaa::ADV_THREADS), lds, st, u, (int)n, dx, dt,
+                       nsteps);
+  else if (order == 10)
     hipLaunchKernelGGL(tenoaa::advect_kernel<10>, dim3(1), dim3(tenoaa::ADV_THREADS), lds, st, u, (int)n, dx, dt,
                        nsteps);
   else

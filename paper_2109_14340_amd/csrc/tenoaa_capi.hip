@@ -83,7 +83,7 @@ hipError_t collect_timing() {
 bool valid_grid(const tenoaa_grid* g, const tenoaa_scheme* s) {
   if (!g || !s) return false;
   if (g->ndim < 1 || g->ndim > 3) return false;
-  if (s->order != 8 && s->order != 10) return false;
+  if (s->order != 8 && s->order != 10 && s->order != 12) return false;
   if (s->splitting != TENOAA_LLF && s->splitting != TENOAA_RUSANOV && s->splitting != TENOAA_ROE) return false;
   if (s->positivity != 0 && s->positivity != 1) return false;
   for (int d = 0; d < 3; ++d) {
@@ -429,7 +429,7 @@ int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double 
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_RHS_VJP);
   if (rc) return rc;
   if (!U || !dUdt_bar || !U_bar || U_bar == U || U_bar == dUdt_bar) return TENOAA_EINVAL;
-  if (boundary_values_any(grid) || scheme->splitting == TENOAA_ROE) return TENOAA_EUNSUPPORTED;
+  if (boundary_values_any(grid) || scheme->splitting == TENOAA_ROE || scheme->order == 12) return TENOAA_EUNSUPPORTED;
   if ((rc = begin(c))) return rc;
   if ((rc = recorded_sweeps(c, U, 0, flags))) return rc;
   return rhs_vjp(c, U, dUdt_bar, U_bar, 0);
@@ -442,7 +442,8 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP_VJP);
   if (rc) return rc;
   if (!Un || !dt_dev || !Unp1_bar || !Un_bar || Un_bar == Unp1_bar || Un_bar == Un) return TENOAA_EINVAL;
-  if (scheme->positivity || boundary_values_any(grid) || scheme->splitting == TENOAA_ROE) return TENOAA_EUNSUPPORTED;
+  if (scheme->positivity || boundary_values_any(grid) || scheme->splitting == TENOAA_ROE || scheme->order == 12)
+    return TENOAA_EUNSUPPORTED;
   if ((rc = begin(c))) return rc;
   const int64_t N = (int64_t)(grid->ndim + 2) * grid->n[0] * grid->n[1] * grid->n[2];
   double* S1 = reinterpret_cast<double*>(c.ws + c.L.stage);

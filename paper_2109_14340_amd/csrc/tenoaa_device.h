@@ -136,7 +136,7 @@ __device__ __forceinline__ double gamma7(double beta) {
 // v[P]: the exact sum of squares in the forward-difference basis.
 template <int R, int P, int W>
 __device__ __forceinline__ double sos_beta(const double (&v)[W]) {
-  static_assert(R == 6 || R == 8 || R == 10, "large stencils only");
+  static_assert(R == 6 || R == 8 || R == 10 || R == 12, "large stencils only");
   double lev[R];
   unroll<R>([&](auto q) { lev[q] = v[P + q]; });
   double dif[R - 1];  // Delta^{m+1} f_P
@@ -150,17 +150,23 @@ __device__ __forceinline__ double sos_beta(const double (&v)[W]) {
     constexpr int k = decltype(kk)::value;
     // y_k = sum_{m >= k} L[m][k] dif[m]; L has a unit diagonal, so the sum
     // starts from dif[k] itself (no addition of a zero)
-    constexpr double lkk = (R == 10) ? SOS_S5_L[k][k] : (R == 8) ? SOS_S4_L[k][k] : SOS_S3_L[k][k];
+    constexpr double lkk = (R == 12)   ? SOS_S6_L[k][k]
+                           : (R == 10) ? SOS_S5_L[k][k]
+                           : (R == 8)  ? SOS_S4_L[k][k]
+                                       : SOS_S3_L[k][k];
     static_assert(lkk == 1.0, "the factor must have a unit diagonal");
     double y = dif[k];
     unroll<R - 1>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
       if constexpr (m > k) {
-        constexpr double l = (R == 10) ? SOS_S5_L[m][k] : (R == 8) ? SOS_S4_L[m][k] : SOS_S3_L[m][k];
+        constexpr double l = (R == 12)   ? SOS_S6_L[m][k]
+                             : (R == 10) ? SOS_S5_L[m][k]
+                             : (R == 8)  ? SOS_S4_L[m][k]
+                                         : SOS_S3_L[m][k];
         if constexpr (l != 0.0) y = fma(l, dif[m], y);
       }
     });
-    constexpr double dk = (R == 10) ? SOS_S5_D[k] : (R == 8) ? SOS_S4_D[k] : SOS_S3_D[k];
+    constexpr double dk = (R == 12) ? SOS_S6_D[k] : (R == 10) ? SOS_S5_D[k] : (R == 8) ? SOS_S4_D[k] : SOS_S3_D[k];
     beta = fma(dk, y * y, beta);
   });
   return beta;
@@ -168,7 +174,7 @@ __device__ __forceinline__ double sos_beta(const double (&v)[W]) {
 
 template <int R>
 __device__ __host__ constexpr double lin_coef(int q) {
-  return (R == 10) ? LIN10[q] : (R == 8) ? LIN8[q] : LIN6[q];
+  return (R == 12) ? LIN12[q] : (R == 10) ? LIN10[q] : (R == 8) ? LIN8[q] : LIN6[q];
 }
 
 // Linear scheme of width R on the values starting at v[P] (Sec. 4.1).
@@ -185,8 +191,10 @@ __device__ __forceinline__ double linear_flux(const double (&v)[W]) {
 }
 
 // ------------------------------------------------- scalar TENO-AA (Sec. 3-4)
-// v[0..W-1] = f_{i-G+1..i+G}.  Returns fhat_{i+1/2}; flag gets the decision
-// byte (bits 0-1 large stencil, 2-4 deltas, 5-7 K-7).
+// v[0..W-1] = f_{i-G+1..i+G}, ORDER = W = 8, 10 or 12 (TENO12-AA: the
+// framework with the twelve-point stencil S6 above S5).  Returns
+// fhat_{i+1/2}; flag gets the decision byte (bits 0-1 large stencil, with
+// bit 2 set for S6; 2-4 deltas of the fallback; 5-7 K-7).
 template <int ORDER>
 __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& flag) {
   constexpr int G = ORDER / 2;
@@ -235,16 +243,24 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   const double S = (g0 + g1) + g2;
 
   // Sec. 3.3: the groups (S0,S1,S2,Sp), largest p first; Sp is taken when
-  // chi_p = gamma_p / (S + gamma_p) >= C_T.
-  if constexpr (ORDER == 10) {
-    const double gp = gamma7(sos_beta<10, 0>(v));
+  // chi_p = gamma_p / (S + gamma_p) >= C_T.  Stencil Sp starts at v[G - p].
+  if constexpr (ORDER == 12) {
+    const double gp = gamma7(sos_beta<12, 0>(v));
+    if (gp >= CT * (S + gp)) {
+      flag = (uint8_t)(7 | kbits);
+      return linear_flux<12, 0>(v);
+    }
+  }
+  if constexpr (ORDER >= 10) {
+    constexpr int P = G - 5;
+    const double gp = gamma7(sos_beta<10, P>(v));
     if (gp >= CT * (S + gp)) {
       flag = (uint8_t)(3 | kbits);
-      return linear_flux<10, 0>(v);
+      return linear_flux<10, P>(v);
     }
   }
   {
-    constexpr int P = (ORDER == 10) ? 1 : 0;
+    constexpr int P = G - 4;
     const double gp = gamma7(sos_beta<8, P>(v));
     if (gp >= CT * (S + gp)) {
       flag = (uint8_t)(2 | kbits);
@@ -252,7 +268,7 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
     }
   }
   {
-    constexpr int P = (ORDER == 10) ? 2 : 1;
+    constexpr int P = G - 3;
     const double gp = gamma7(sos_beta<6, P>(v));
     if (gp >= CT * (S + gp)) {
       flag = (uint8_t)(1 | kbits);
@@ -277,11 +293,14 @@ __device__ __forceinline__ double replay_recon(const double (&v)[ORDER], uint8_t
   constexpr int G = ORDER / 2;
   constexpr int I = G - 1;
   const int sel = flag & 3;
-  if constexpr (ORDER == 10) {
-    if (sel == 3) return linear_flux<10, 0>(v);
+  if constexpr (ORDER == 12) {
+    if (sel == 3 && (flag & 4)) return linear_flux<12, 0>(v);
   }
-  if (sel == 2) return linear_flux<8, (ORDER == 10) ? 1 : 0>(v);
-  if (sel == 1) return linear_flux<6, (ORDER == 10) ? 2 : 1>(v);
+  if constexpr (ORDER >= 10) {
+    if (sel == 3) return linear_flux<10, G - 5>(v);
+  }
+  if (sel == 2) return linear_flux<8, G - 4>(v);
+  if (sel == 1) return linear_flux<6, G - 3>(v);
   const int dm = (flag >> 2) & 7;
   const double fm1 = v[I - 1], f0 = v[I], f1 = v[I + 1];
   const double h0 = div6((-fm1 + 5.0 * f0) + 2.0 * f1);

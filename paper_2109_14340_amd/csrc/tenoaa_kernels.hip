@@ -212,6 +212,7 @@ static hipError_t launch_sweep_ord(int ndim, int dir, const SweepArgs& a, bool l
 }
 
 hipError_t launch_sweep(int order, int ndim, int dir, const SweepArgs& a, bool limit, hipStream_t st) {
+  if (order == 12) return launch_sweep_ord<12>(ndim, dir, a, limit, st);
   return order == 10 ? launch_sweep_ord<10>(ndim, dir, a, limit, st) : launch_sweep_ord<8>(ndim, dir, a, limit, st);
 }
 

@@ -145,6 +145,26 @@ def test_roe_flux_options():
                                tenoaa.FLAGS_REPLAY, vp(1024), need, None) == -2
 
 
+def test_teno12_options():
+    """Order 12 (TENO12-AA) is a valid scheme; the adjoint entry points and the
+    batch plan reject it before any device work."""
+    L = _lib()
+    vp = ctypes.c_void_p
+    g = tenoaa.make_grid((64, 48))
+    s = tenoaa.make_scheme(12)
+    assert L.tenoaa_workspace_bytes(ctypes.byref(g), ctypes.byref(s), 0) > 0
+    assert L.tenoaa_workspace_bytes(ctypes.byref(tenoaa.make_grid((5, 48))), ctypes.byref(s), 0) == 0  # n < 6
+    need = 1 << 30
+    assert L.tenoaa_rhs_vjp(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), None, vp(1024),
+                            need, None) == -2
+    assert L.tenoaa_step_vjp(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), vp(4096), None,
+                             vp(1024), need, None) == -2
+    h = vp(None)
+    arr = (tenoaa.Grid * 1)(tenoaa.make_grid((64, 64), bc_lo=[1, 1]))
+    assert L.tenoaa_batch_plan_create(arr, 1, ctypes.byref(s), 1.4, 0.4, 2, None, ctypes.byref(h)) == -2
+    assert L.tenoaa_advect(12, 11, 0.1, 0.01, 1, vp(256), None) == -1  # n < order
+
+
 def test_advect_rejects_bad_arguments():
     L = _lib()
     vp = ctypes.c_void_p

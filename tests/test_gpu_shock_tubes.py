@@ -63,7 +63,7 @@ def _run_gpu(case, order, n):
     return U0, U.cpu().numpy(), dts
 
 
-@pytest.mark.parametrize("order", [8, 10])
+@pytest.mark.parametrize("order", [8, 10, 12])
 @pytest.mark.parametrize("case", ["sod", "lax"])
 def test_shock_tube(case, order):
     left, right, tf = CASES[case]
