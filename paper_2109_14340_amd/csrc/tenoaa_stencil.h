@@ -24,6 +24,12 @@
 #ifndef TENOAA_CELL_BARRIER
 #define TENOAA_CELL_BARRIER 0
 #endif
+// > 0: x-sweep waves take patches of this many faces by 64 / it pencils
+// instead of 64 faces of one pencil, so that a wave's lanes meet the deep
+// cascade together more often (tuning; 0 restores whole-pencil waves)
+#ifndef TENOAA_X_PATCH
+#define TENOAA_X_PATCH 16
+#endif
 
 namespace tenoaa {
 namespace {
@@ -211,8 +217,21 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
   // ---- one face per thread
   int tt, fn;
   if (DIR == 0) {
+#if TENOAA_X_PATCH > 0
+    // a wave takes TENOAA_X_PATCH faces of 64 / TENOAA_X_PATCH pencils
+    if constexpr (TT * TN % 64 == 0 && TN % TENOAA_X_PATCH == 0 && TT % (64 / TENOAA_X_PATCH) == 0 && TT > 1) {
+      constexpr int PW = TENOAA_X_PATCH, PH = 64 / TENOAA_X_PATCH, NPX = TN / PW;
+      const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+      tt = (w / NPX) * PH + l / PW;
+      fn = (w % NPX) * PW + l % PW;
+    } else {
+      tt = threadIdx.x / TN;
+      fn = threadIdx.x % TN;
+    }
+#else
     tt = threadIdx.x / TN;
     fn = threadIdx.x % TN;
+#endif
   } else {
     tt = threadIdx.x % TT;
     fn = threadIdx.x / TT;
