@@ -177,8 +177,11 @@ int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double 
  * double holding the dt the forward step used (> 0).  The three stage states
  * are recomputed from Un inside the call; each stage's decisions are frozen at
  * its own state, or, with flags3 non-NULL, taken from flags3 (the three
- * stages' decisions as recorded by tenoaa_step_flags).  TENOAA_EUNSUPPORTED
- * with the limiter on.  Un_bar must not alias Un or Unp1_bar. */
+ * stages' decisions as recorded by tenoaa_step_flags).  With the limiter on,
+ * the limiter acts as in tenoaa_step (its speeds from Un, the given dt) and
+ * its factors theta per face, F = F_LF + theta (F_H - F_LF), are frozen like
+ * the other decisions, as is the cell giving the Lax-Friedrichs speed of
+ * F_LF.  Un_bar must not alias Un or Unp1_bar. */
 int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* Un,
                     const double* dt_dev, const double* Unp1_bar, double* Un_bar, const uint8_t* flags3, void* ws,
                     size_t ws_bytes, void* stream);

@@ -72,7 +72,8 @@ def lib():
         L.or_rhs_jvp.restype = ctypes.c_int
         L.or_rhs_jvp.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, u8, dp, dp]
         L.or_step_jvp.restype = ctypes.c_int
-        L.or_step_jvp.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, ctypes.c_double, u8, dp]
+        L.or_step_jvp.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, ctypes.c_double,
+                                  u8, dp]
         L.or_step.restype = ctypes.c_int
         L.or_step.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, dp, dp, u8, dp]
@@ -209,13 +210,15 @@ def rhs_jvp(grid, U, V, flags, order=10, splitting=LLF, gamma=1.4):
     return out, jv
 
 
-def step_jvp(grid, U, V, dt, flags3, order=10, splitting=LLF, gamma=1.4):
-    """Exact derivative of one RK3 step along V (dt fixed, stage decisions frozen)."""
+def step_jvp(grid, U, V, dt, flags3, order=10, splitting=LLF, gamma=1.4, positivity=0):
+    """Exact derivative of one RK3 step along V (dt fixed, stage decisions frozen;
+    with positivity the limiter's factors frozen too)."""
     U = np.ascontiguousarray(U, dtype=np.float64)
     V = np.ascontiguousarray(V, dtype=np.float64)
     flags3 = np.ascontiguousarray(flags3, dtype=np.uint8)
     out = np.empty_like(U)
-    rc = lib().or_step_jvp(ctypes.byref(grid), order, splitting, gamma, _dp(U), _dp(V), dt, _u8(flags3), _dp(out))
+    rc = lib().or_step_jvp(ctypes.byref(grid), order, splitting, positivity, gamma, _dp(U), _dp(V), dt,
+                           _u8(flags3), _dp(out))
     if rc:
         raise ValueError("oracle step_jvp rejected its arguments (rc=%d)" % rc)
     return out

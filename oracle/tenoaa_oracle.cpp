@@ -1077,23 +1077,29 @@ int or_rhs_jvp(const or_grid* g, int order, int splitting, double gam, const dou
 // Directional derivative of one SSP-RK3 step along V with dt fixed and each
 // stage's decisions frozen to flags3 (stage-major, as written by or_step),
 // in forward mode through the three stages.  Limiter off.
-int or_step_jvp(const or_grid* g, int order, int splitting, double gam, const double* U, const double* V,
-                double dt, const uint8_t* flags3, double* jvp) {
+// With positivity the limiter acts in every stage as in or_step (its wave
+// speeds from U, dt the given one); its factors theta are evaluated from the
+// values and so enter as constants: F = F_LF + theta (F_H - F_LF) is
+// differentiated with theta frozen.
+int or_step_jvp(const or_grid* g, int order, int splitting, int positivity, double gam, const double* U,
+                const double* V, double dt, const uint8_t* flags3, double* jvp) {
   build_beta_tables();
   Grid G = to_grid(g);
-  Scheme s{order, splitting, 0};
+  Scheme s{order, splitting, positivity};
   if (check_grid(G, s) || !flags3 || !(dt > 0.0)) return -1;
   const int64_t N = (int64_t)(G.ndim + 2) * G.n[0] * G.n[1] * G.n[2];
   const int64_t nfl = flag_offset(G, G.ndim);
   std::vector<Dual> Un((size_t)N), U1((size_t)N), U2((size_t)N), L((size_t)N);
   for (int64_t i = 0; i < N; ++i) Un[(size_t)i] = Dual(U[i], V[i]);
   double a[3] = {0, 0, 0};
-  rhs_impl<Dual>(G, s, gam, Un.data(), L.data(), 0.0, a, nullptr, nullptr, flags3);
+  if (positivity) wave_speeds(G, gam, U, a);
+  const double dl = positivity ? dt : 0.0;
+  rhs_impl<Dual>(G, s, gam, Un.data(), L.data(), dl, a, nullptr, nullptr, flags3);
   for (int64_t i = 0; i < N; ++i) U1[(size_t)i] = Un[(size_t)i] + dt * L[(size_t)i];
-  rhs_impl<Dual>(G, s, gam, U1.data(), L.data(), 0.0, a, nullptr, nullptr, flags3 + nfl, G.bc_sets == 3 ? 1 : 0);
+  rhs_impl<Dual>(G, s, gam, U1.data(), L.data(), dl, a, nullptr, nullptr, flags3 + nfl, G.bc_sets == 3 ? 1 : 0);
   for (int64_t i = 0; i < N; ++i)
     U2[(size_t)i] = 0.75 * Un[(size_t)i] + 0.25 * U1[(size_t)i] + (0.25 * dt) * L[(size_t)i];
-  rhs_impl<Dual>(G, s, gam, U2.data(), L.data(), 0.0, a, nullptr, nullptr, flags3 + 2 * nfl, G.bc_sets == 3 ? 2 : 0);
+  rhs_impl<Dual>(G, s, gam, U2.data(), L.data(), dl, a, nullptr, nullptr, flags3 + 2 * nfl, G.bc_sets == 3 ? 2 : 0);
   for (int64_t i = 0; i < N; ++i) {
     const Dual u3 = (1.0 / 3.0) * Un[(size_t)i] + (2.0 / 3.0) * U2[(size_t)i] + ((2.0 / 3.0) * dt) * L[(size_t)i];
     jvp[i] = u3.d;

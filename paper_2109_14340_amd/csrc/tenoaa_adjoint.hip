@@ -7,8 +7,9 @@
 // reconstruction; the cell that attains each LLF/Rusanov splitting speed and
 // the sign of that speed.  Everything else - cell primitives, Roe average,
 // eigenvectors, projection, split, back-projection - is differentiated
-// exactly.  The positivity limiter is not differentiated (its callers reject
-// it).
+// exactly.  With the positivity limiter, its factor theta per face (recorded
+// by the forward sweep) is frozen as well, and the Lax-Friedrichs flux it
+// blends in is differentiated with its speed's cell frozen.
 //
 // The forward sweep of the same direction runs first and leaves, per face,
 // the decision bytes and the per-field fluxes fh_s.  Per block: the tile of
@@ -243,6 +244,32 @@ void sweep_vjp_kernel(AdjointArgs A) {
         else slot = 1 + Fr::slot_of_axis(c - 1);
         Fb[slot] = v;
       });
+    }
+
+    // positivity limiter with its factor frozen: F = F_LF + theta (F_H - F_LF),
+    // F_LF = (F_a + F_b - a_L (W_b - W_a)) / 2 with a_L = max(|u_n| + c) of the
+    // two cells (that cell frozen); F_H continues below with seed theta Fbar
+    if (A.theta) {
+      const double th = A.theta[flin];
+      if (th < 1.0) {
+        const double sA = fabs(sUn[ia]) + sC[ia], sB = fabs(sUn[ib]) + sC[ib];
+        const bool onA = sA >= sB;
+        const double aL = onA ? sA : sB;
+        double aLb = 0.0;
+        unroll<NV>([&](auto c) {
+          const double flb = (1.0 - th) * Fb[c];
+          const double2 wa = sWF[c][ia], wb = sWF[c][ib];
+          lds_add(&aF[c][ia], 0.5 * flb);
+          lds_add(&aF[c][ib], 0.5 * flb);
+          lds_add(&aW[c][ia], (0.5 * aL) * flb);
+          lds_add(&aW[c][ib], -(0.5 * aL) * flb);
+          aLb -= 0.5 * flb * (wb.x - wa.x);
+          Fb[c] *= th;
+        });
+        const int li = onA ? ia : ib;
+        lds_add(&aU[0][li], (sUn[li] < 0.0 ? -1.0 : 1.0) * aLb);
+        lds_add(&aC[li], aLb);
+      }
     }
 
     // ---- forward recompute: Roe average and eigenvectors

@@ -168,7 +168,7 @@ __device__ __forceinline__ void sweep_item(const BatchArgs& B, char* arena, int 
     double dt;
     dt_and_mu(B.amax + ((int64_t)p * B.nsteps + n) * 2, 2, P.dx, B.cfl, 0.0, dt, mu);
   }
-  SweepArgs A;
+  SweepArgs A{};  // every pointer the batch does not use stays null
   A.U = in;
   A.flags = nullptr;
   A.frozen = nullptr;
@@ -201,7 +201,7 @@ __device__ __forceinline__ void update_item(const BatchArgs& B, char* arena, int
   double dt, mu[3];
   dt_and_mu(B.amax + ((int64_t)p * B.nsteps + n) * 2, 2, P.dx, B.cfl, 0.0, dt, mu);
   if (MODE == 1 && k == 0 && threadIdx.x == 0 && B.dt_out) B.dt_out[(int64_t)P.orig * B.nsteps + n] = dt;
-  UpdateArgs A;
+  UpdateArgs A{};
   A.F[0] = B.F + P.f_off[0];
   A.F[1] = B.F + P.f_off[1];
   A.F[2] = nullptr;

@@ -121,12 +121,13 @@ struct Layout {
   size_t fbuf[3];       // face flux arrays per direction
   size_t vjp[3][3];     // adjoint calls: [stage][direction] decisions, then per-field fluxes
   size_t vjp_fh_rel[3]; // offset of a direction's per-field fluxes after its decisions
+  size_t vjp_th_rel[3]; // offset of a direction's limiter factors after its decisions (limiter only)
   size_t stage;         // RK stage state(s)
   size_t state_bytes;   // aligned size of one state
   size_t total;
 };
 
-Layout layout(const tenoaa_grid* g, int which) {
+Layout layout(const tenoaa_grid* g, int which, bool limiter = false) {
   Layout L;
   const int nv = g->ndim + 2;
   const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
@@ -144,8 +145,10 @@ Layout layout(const tenoaa_grid* g, int which) {
     for (int d = 0; d < 3; ++d) {
       L.vjp[st][d] = off;
       if (st < nstage && d < g->ndim) {
-        L.vjp_fh_rel[d] = align256((size_t)nv * 2 * (size_t)faces_total(g, d));
-        off += L.vjp_fh_rel[d] + align256((size_t)nv * (size_t)faces_total(g, d) * sizeof(double));
+        const size_t nft = (size_t)faces_total(g, d);
+        L.vjp_fh_rel[d] = align256((size_t)nv * 2 * nft);
+        L.vjp_th_rel[d] = L.vjp_fh_rel[d] + align256((size_t)nv * nft * sizeof(double));
+        off += L.vjp_th_rel[d] + (limiter ? align256(nft * sizeof(double)) : 0);
       }
     }
   }
@@ -216,7 +219,7 @@ hipError_t wave_speeds(const Ctx& c, const double* U) {
 // Face fluxes of every direction for state U; flags optional.  `stage`
 // selects the Dirichlet value set.
 int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint8_t* frozen = nullptr,
-           int only_dir = -1, double* fh_out = nullptr, int stage = 0) {
+           int only_dir = -1, double* fh_out = nullptr, int stage = 0, double* theta_out = nullptr) {
   const tenoaa_grid* g = c.g;
   const int nv = g->ndim + 2;
   int64_t flag_off = 0;
@@ -234,6 +237,7 @@ int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint
     a.flags = flags ? flags + fo : nullptr;
     a.frozen = frozen ? frozen + fo : nullptr;
     a.fh_out = fh_out;
+    a.theta_out = theta_out;
     for (int k = 0; k < 3; ++k) a.n[k] = g->n[k];
     a.nf = faces_along(g, d);
     a.nft = faces_total(g, d);
@@ -274,15 +278,16 @@ int update(const Ctx& c, int mode, const double* Un, const double* Us, double* o
 }
 
 // Forward sweeps of U in every direction that also leave the decisions and
-// per-field fluxes of adjoint stage slot `st` in the workspace.  With
-// `frozen` (a flag array in the layout of tenoaa_rhs) the sweeps replay those
-// decisions instead of taking them.
-int recorded_sweeps(const Ctx& c, const double* U, int st, const uint8_t* frozen) {
+// per-field fluxes (and with `limit` the limiter factors) of adjoint stage
+// slot `st` in the workspace.  With `frozen` (a flag array in the layout of
+// tenoaa_rhs) the sweeps replay those decisions instead of taking them.
+int recorded_sweeps(const Ctx& c, const double* U, int st, const uint8_t* frozen, bool limit = false) {
   int64_t off = 0;
   for (int d = 0; d < c.g->ndim; ++d) {
     uint8_t* flags = reinterpret_cast<uint8_t*>(c.ws + c.L.vjp[st][d]);
     double* fh = reinterpret_cast<double*>(c.ws + c.L.vjp[st][d] + c.L.vjp_fh_rel[d]);
-    int rc = sweeps(c, U, false, flags, frozen ? frozen + off : nullptr, d, fh);
+    double* th = limit ? reinterpret_cast<double*>(c.ws + c.L.vjp[st][d] + c.L.vjp_th_rel[d]) : nullptr;
+    int rc = sweeps(c, U, limit, flags, frozen ? frozen + off : nullptr, d, fh, 0, th);
     if (rc) return rc;
     off += (int64_t)(c.g->ndim + 2) * 2 * faces_total(c.g, d);
   }
@@ -297,7 +302,7 @@ int64_t flag_count(const tenoaa_grid* g) {
 
 // U_bar = (d(dU/dt)/dU)^T R at U, decisions frozen at U, from the decisions
 // and per-field fluxes that recorded_sweeps(U) left in stage slot `st`.
-int rhs_vjp(const Ctx& c, const double* U, const double* R, double* Ubar, int st) {
+int rhs_vjp(const Ctx& c, const double* U, const double* R, double* Ubar, int st, bool limit = false) {
   const tenoaa_grid* g = c.g;
   const int nv = g->ndim + 2;
   const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
@@ -311,6 +316,7 @@ int rhs_vjp(const Ctx& c, const double* U, const double* R, double* Ubar, int st
     a.Ubar = Ubar;
     a.flags = reinterpret_cast<const uint8_t*>(c.ws + c.L.vjp[st][d]);
     a.fh = reinterpret_cast<const double*>(c.ws + c.L.vjp[st][d] + c.L.vjp_fh_rel[d]);
+    a.theta = limit ? reinterpret_cast<const double*>(c.ws + c.L.vjp[st][d] + c.L.vjp_th_rel[d]) : nullptr;
     a.nft = faces_total(g, d);
     for (int k = 0; k < 3; ++k) a.n[k] = g->n[k];
     a.nf = faces_along(g, d);
@@ -333,7 +339,7 @@ int prepare(Ctx& c, const tenoaa_grid* g, const tenoaa_scheme* s, double gamma, 
   c.s = s;
   c.gamma = gamma;
   c.ws = static_cast<char*>(ws);
-  c.L = layout(g, which);
+  c.L = layout(g, which, s->positivity != 0);
   if (ws_bytes < c.L.total) return TENOAA_EWORKSPACE;
   c.S = reinterpret_cast<tenoaa::Scalars*>(c.ws + c.L.scalars);
   c.st = static_cast<hipStream_t>(stream);
@@ -356,7 +362,7 @@ extern "C" {
 size_t tenoaa_workspace_bytes(const tenoaa_grid* grid, const tenoaa_scheme* scheme, int32_t which) {
   if (!valid_grid(grid, scheme)) return 0;
   if (which < TENOAA_WS_RHS || which > TENOAA_WS_STEP_VJP) return 0;
-  return layout(grid, which).total;
+  return layout(grid, which, scheme->positivity != 0).total;
 }
 
 int tenoaa_rhs(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U, double* dUdt,
@@ -442,8 +448,8 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP_VJP);
   if (rc) return rc;
   if (!Un || !dt_dev || !Unp1_bar || !Un_bar || Un_bar == Unp1_bar || Un_bar == Un) return TENOAA_EINVAL;
-  if (scheme->positivity || boundary_values_any(grid) || scheme->splitting == TENOAA_ROE || scheme->order == 12)
-    return TENOAA_EUNSUPPORTED;
+  if (boundary_values_any(grid) || scheme->splitting == TENOAA_ROE || scheme->order == 12) return TENOAA_EUNSUPPORTED;
+  const bool limit = scheme->positivity != 0;
   if ((rc = begin(c))) return rc;
   const int64_t N = (int64_t)(grid->ndim + 2) * grid->n[0] * grid->n[1] * grid->n[2];
   double* S1 = reinterpret_cast<double*>(c.ws + c.L.stage);
@@ -455,23 +461,35 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
   // recompute the stages, recording each stage's decisions and per-field
   // fluxes: U1 = Un + dt L(Un), U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1), and the
   // sweeps of U2
-  hipLaunchKernelGGL(copy_dt_kernel, dim3(1), dim3(64), 0, c.st, c.S, dt_dev);
-  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
+  if (limit) {
+    // the limiter factors of every stage from the wave speeds of Un and the given dt, as in the forward step
+    const int64_t ncell = grid->n[0] * grid->n[1] * grid->n[2];
+    e = tenoaa::launch_wave_speeds(grid->ndim, Un, ncell, gamma, c.S, &c.S->status, c.st);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(copy_dt_kernel, dim3(1), dim3(64), 0, c.st, c.S, dt_dev);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, 1.0, &c.S->dt, 0.0, c.st);
+  } else {
+    hipLaunchKernelGGL(copy_dt_kernel, dim3(1), dim3(64), 0, c.st, c.S, dt_dev);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return hip_fail(e);
   const int64_t nfl = flag_count(grid);
   auto stage_flags = [&](int st) { return flags3 ? flags3 + st * nfl : nullptr; };
-  if ((rc = recorded_sweeps(c, Un, 0, stage_flags(0)))) return rc;
+  if ((rc = recorded_sweeps(c, Un, 0, stage_flags(0), limit))) return rc;
   if ((rc = update(c, 1, Un, nullptr, S1))) return rc;
-  if ((rc = recorded_sweeps(c, S1, 1, stage_flags(1)))) return rc;
+  if ((rc = recorded_sweeps(c, S1, 1, stage_flags(1), limit))) return rc;
   if ((rc = update(c, 2, Un, S1, S2))) return rc;
-  if ((rc = recorded_sweeps(c, S2, 2, stage_flags(2)))) return rc;
+  if ((rc = recorded_sweeps(c, S2, 2, stage_flags(2), limit))) return rc;
   // reverse: B2 = 2/3 B3 + 2/3 dt J(U2)^T B3
-  if ((rc = rhs_vjp(c, S2, Unp1_bar, V, 2))) return rc;
+  if ((rc = rhs_vjp(c, S2, Unp1_bar, V, 2, limit))) return rc;
   if ((e = tenoaa::launch_axpdtz(B2, 2.0 / 3.0, Unp1_bar, 2.0 / 3.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
   // B1 = 1/4 B2 + 1/4 dt J(U1)^T B2
-  if ((rc = rhs_vjp(c, S1, B2, V, 1))) return rc;
+  if ((rc = rhs_vjp(c, S1, B2, V, 1, limit))) return rc;
   if ((e = tenoaa::launch_axpdtz(B1, 0.25, B2, 0.25, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
   // Bn = 1/3 B3 + 3/4 B2 + B1 + dt J(Un)^T B1
-  if ((rc = rhs_vjp(c, Un, B1, V, 0))) return rc;
+  if ((rc = rhs_vjp(c, Un, B1, V, 0, limit))) return rc;
   if ((e = tenoaa::launch_axpbypcz(Un_bar, 1.0 / 3.0, Unp1_bar, 0.75, B2, 1.0, B1, N, c.st)) != hipSuccess)
     return hip_fail(e);
   if ((e = tenoaa::launch_axpdtz(Un_bar, 1.0, Un_bar, 1.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);

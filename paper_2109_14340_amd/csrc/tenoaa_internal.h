@@ -23,6 +23,7 @@ struct SweepArgs {
   uint8_t* flags;   // flags of this direction, [nvar][2][nft], or null
   const uint8_t* frozen;  // decisions to replay instead of taking them, or null
   double* fh_out;         // per-field reconstructed fluxes fh_s = f+_s + f-_s, [nvar][nft], or null
+  double* theta_out;      // per face: the limiter's theta_rho * theta_p (1 where it leaves the flux), or null
   int64_t n[3];
   int64_t nf;       // faces along the direction
   int64_t nft;      // faces of the direction in total
@@ -64,6 +65,7 @@ struct AdjointArgs {
   double* Ubar;      // accumulated with atomics (caller zeroes it)
   const uint8_t* flags;  // decisions of this direction's forward sweep at U, [nvar][2][nft]
   const double* fh;      // per-field fluxes of that sweep, [nvar][nft]
+  const double* theta;   // the sweep's limiter factors per face, or null (no limiter)
   int64_t nft;
   int64_t n[3];
   int64_t nf;

@@ -482,6 +482,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
       }
     });
     unroll<NV>([&](auto c) { Fh[c] = (th_p < 1.0) ? FL[c] + th_p * (Fs[c] - FL[c]) : Fs[c]; });
+    // for the adjoint: the flux is F_LF + theta (F_H - F_LF) with theta = theta_rho theta_p
+    if (A.theta_out) A.theta_out[flin] = th_r * th_p;
   } else {
     (void)mu;
   }

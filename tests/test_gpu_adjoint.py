@@ -114,13 +114,47 @@ def test_step_vjp_dot(case):
     assert abs(lhs - rhs) <= 1e-11 * scale
 
 
-def test_step_vjp_rejects_limiter():
-    g = tenoaa.make_grid((32,), bc_lo=[1])
-    sch = tenoaa.make_scheme(10, 0, 1)
-    U = _dev(inputs.shock_tube_1d(32))
-    dtd = torch.tensor([1e-3], dtype=torch.float64, device="cuda")
-    with pytest.raises(tenoaa.TenoaaError):
-        tenoaa.step_vjp(g, sch, U, dtd, U.clone())
+def _double_rarefaction_state(n=64, steps=15):
+    """The Sec. 5.3.1 double rarefaction after a few limited steps: near-vacuum
+    at the centre, where the positivity limiter acts."""
+    x = (np.arange(n) + 0.5) / n
+    U = inputs._as_layout(inputs.conserved_from_primitive(np.ones(n), [np.where(x < 0.5, -2.0, 2.0)],
+                                                          np.full(n, 0.1), 1.4), 1)
+    g = oracle.make_grid((n,), [1.0 / n], [1])
+    for _ in range(steps):
+        U, _, _, _ = oracle.step(g, U, order=10, positivity=1, cfl=0.4)
+    return U
+
+
+@pytest.mark.parametrize("case", ["1d_near_vacuum", "3d_blast_cavity"])
+def test_step_vjp_dot_with_limiter(case):
+    """With the positivity limiter: its factors theta (recorded by the forward
+    sweeps) and the Lax-Friedrichs speed's cell frozen, <w, J v> (oracle, dual
+    numbers with theta evaluated from the values) = <J^T w, v> (GPU); the
+    limiter does act on these states."""
+    if case == "1d_near_vacuum":
+        U, shape, bc, order = _double_rarefaction_state(), (64,), [1], 10
+    else:
+        U, shape, bc, order = inputs.blast_cavity_3d(12), (12, 12, 12), [0, 0, 0], 8
+    g_or, g_gpu = _grids(shape, bc)
+    Ul, dt, flags3, margins3 = oracle.step(g_or, U, order=order, positivity=1, cfl=0.4, want_flags=True)
+    Uu, _, _, _ = oracle.step(g_or, U, order=order, positivity=0, dt=dt)
+    assert not np.array_equal(Ul, Uu), "the limiter does not act on this state"
+    assert (margins3 <= 1e-12).sum() == 0
+    rng = np.random.default_rng(9)
+    V = rng.standard_normal(U.shape) * np.abs(U).reshape(U.shape[0], -1).max(axis=1)[:, None, None, None]
+    Wt = rng.standard_normal(U.shape)
+    jv = oracle.step_jvp(g_or, U, V, dt, flags3, order=order, positivity=1)
+    sch = tenoaa.make_scheme(order, 0, 1)
+    dtd = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    jtw = tenoaa.to_numpy(tenoaa.step_vjp(g_gpu, sch, _dev(U), dtd, _dev(Wt)))
+    lhs, rhs = float(np.sum(Wt * jv)), float(np.sum(jtw * V))
+    scale = float(np.sum(np.abs(Wt * jv)))
+    # without the limiter's terms the products would differ
+    jv0 = oracle.step_jvp(g_or, U, V, dt, flags3, order=order, positivity=0)
+    print(case, "limited step <w,Jv> %.15e  <J^T w,v> %.15e rel %.2e (unlimited <w,Jv> %.6e)"
+          % (lhs, rhs, abs(lhs - rhs) / scale, float(np.sum(Wt * jv0))))
+    assert abs(lhs - rhs) <= 1e-11 * scale
 
 
 def test_rhs_vjp_with_flags_of_another_state():
