@@ -89,8 +89,10 @@ enum {
  * where the eigenvalue has one strict sign at both cells of the face, the
  * unsplit characteristic flux is reconstructed from the upwind side alone
  * (the flag byte of the other side is 0, which no decision produces);
- * elsewhere the field is split as with LLF.  The adjoint entry points and
- * decision replay reject ROE with TENOAA_EUNSUPPORTED. */
+ * elsewhere the field is split as with LLF.  Decision replay
+ * (TENOAA_FLAGS_REPLAY, recorded flags given to the adjoint entry points)
+ * replays the side each field reconstructs with the other decisions: the side
+ * whose recorded byte is 0 is not reconstructed. */
 enum { TENOAA_LLF = 0, TENOAA_RUSANOV = 1, TENOAA_ROE = 2 };
 
 /* Workspace purposes for tenoaa_workspace_bytes. */
@@ -113,7 +115,10 @@ enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1, TENOAA_WS_RHS_VJP = 2, TENOAA_WS_S
  * and tenoaa_rhs reads set 0; with 1 every evaluation reads set 0.  A smaller
  * array than this is undefined behaviour (the library cannot check device
  * allocations).  Grids with such sides are rejected with
- * TENOAA_EUNSUPPORTED by the adjoint entry points and the batch plan. */
+ * TENOAA_EUNSUPPORTED by the batch plan.  The adjoint entry points
+ * differentiate a Dirichlet ghost through its reflection rule (the face
+ * values are constants), take inflow ghosts as constants, and read set s in
+ * stage s as the step does. */
 typedef struct {
   int32_t ndim;
   int32_t bc_sets;
@@ -128,7 +133,7 @@ typedef struct {
  * Sec. 3.1 framework with one more symmetric large stencil S6 = cells
  * i-5 .. i+6 tried before S5; the paper prints no optimised scheme for it, so
  * S6 uses the maximum-order (12th) reconstruction; not supported by the
- * adjoint entry points and the batch plan); splitting: TENOAA_LLF,
+ * batch plan); splitting: TENOAA_LLF,
  * TENOAA_RUSANOV or TENOAA_ROE; positivity: 1 enables the flux limiter. */
 typedef struct {
   int32_t order;
@@ -162,7 +167,8 @@ int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gam
  * formula of the paper).  U_bar (overwritten) = (d dUdt / dU)^T dUdt_bar at
  * U, with every threshold decision frozen: the stencil chosen by the cascade
  * and the small-stencil deltas (Sec. 3.3), i.e. the linear weights of each
- * reconstruction, and the cell and sign that attain each splitting speed.
+ * reconstruction, and the cell and sign that attain each splitting speed
+ * (with TENOAA_ROE also the side each field reconstructs).
  * flags: NULL to freeze the decisions taken at U, or a flag array (layout
  * above, e.g. recorded by tenoaa_rhs at another state) whose decisions are
  * used instead.  The limiter is not part of the differentiated map (it acts

@@ -760,8 +760,14 @@ void face_flux(const Grid& g, const Scheme& sc, double gam, int d, const CellQ<T
     // sign at both cells of the face, the unsplit characteristic flux is
     // reconstructed from the upwind side only; elsewhere (a sonic point, or
     // a zero eigenvalue) the field falls back to the LLF split above.
+    // With recorded decisions the side is replayed too: the side whose byte
+    // is 0 was not reconstructed.
     int upwind = 0;  // 0: split, 1: + side only, 2: - side only
-    if (sc.splitting == 2) {
+    if (sc.splitting == 2 && frozen) {
+      const uint8_t bp = frozen[fbase + ((int64_t)s * 2) * nft];
+      const uint8_t bm = frozen[fbase + ((int64_t)s * 2 + 1) * nft];
+      upwind = bm == 0 ? 1 : (bp == 0 ? 2 : 0);
+    } else if (sc.splitting == 2) {
       const double la = re(char_speed(nv, s, ca.u[d], ca.c));
       const double lb = re(char_speed(nv, s, cb.u[d], cb.c));
       upwind = (la > 0.0 && lb > 0.0) ? 1 : ((la < 0.0 && lb < 0.0) ? 2 : 0);

@@ -5,7 +5,8 @@
 // the method frozen at U: the stencil chosen by the cascade and the cut-off
 // deltas (Sec. 3.3 of the paper), hence the linear weights of each
 // reconstruction; the cell that attains each LLF/Rusanov splitting speed and
-// the sign of that speed.  Everything else - cell primitives, Roe average,
+// the sign of that speed; with the Roe flux, which side each field
+// reconstructs.  Everything else - cell primitives, Roe average,
 // eigenvectors, projection, split, back-projection - is differentiated
 // exactly.  With the positivity limiter, its factor theta per face (recorded
 // by the forward sweep) is frozen as well, and the Lax-Friedrichs flux it
@@ -20,7 +21,9 @@
 // accumulators (ds_add_f64).  After a barrier the cell-level reverse
 // pass turns those into conserved-state adjoints, maps ghost cells back to
 // their interior source (with the momentum sign flips of wall conditions) and
-// adds them to U_bar with global FP64 atomics, so the summation order - and
+// adds them to U_bar with global FP64 atomics (a Dirichlet ghost through the
+// Jacobian of its reflection rule; an inflow ghost is a constant), so the
+// summation order - and
 // the last bits of U_bar - can vary between runs.
 #include <hip/hip_runtime.h>
 
@@ -28,6 +31,7 @@
 
 #include "tenoaa_device.h"
 #include "tenoaa_internal.h"
+#include "tenoaa_stencil.h"
 
 #ifndef TENOAA_ADJ_TN_X
 #define TENOAA_ADJ_TN_X 64
@@ -51,21 +55,20 @@ namespace {
 // Derivatives of the frozen reconstructions with respect to the window values
 // f_{-G+1..G}: one row per outcome of the cascade.  Rows 0-7: the TENO5
 // fallback with delta mask 0-7 (weights d_k delta_k / sum, Sec. 3.3, times the
-// three third-order candidates); rows 8, 9, 10: the linear schemes on S3, S4,
-// S5 (Sec. 4.1).
-constexpr int NROW = 11;
+// three third-order candidates); rows 8, 9, 10, 11: the linear schemes on S3,
+// S4, S5 (Sec. 4.1) and S6 (TENO12-AA), stencil S_p starting at v[G - p].
+// Row 0 (no small stencil kept) is all zeros: the byte of a side the Roe flux
+// does not reconstruct selects it.
+constexpr int NROW = 12;
 template <int ORDER>
 __device__ __forceinline__ double weight_entry(int row, int q) {
   constexpr int G = ORDER / 2;
   constexpr int I = G - 1;
-  if (row == 10) return ORDER == 10 ? lin_coef<10>(q) : 0.0;
-  if (row == 9) {
-    constexpr int P = (ORDER == 10) ? 1 : 0;
-    return (q >= P && q < P + 8) ? lin_coef<8>(q - P) : 0.0;
-  }
-  if (row == 8) {
-    constexpr int P = (ORDER == 10) ? 2 : 1;
-    return (q >= P && q < P + 6) ? lin_coef<6>(q - P) : 0.0;
+  if (row >= 8) {
+    const int p = row - 5;
+    const int P = G - p;
+    if (p > G || q < P || q >= P + 2 * p) return 0.0;
+    return p == 3 ? lin_coef<6>(q - P) : (p == 4 ? lin_coef<8>(q - P) : (p == 5 ? lin_coef<10>(q - P) : lin_coef<12>(q - P)));
   }
   const double w0 = WFALL.w[row][0], w1 = WFALL.w[row][1], w2 = WFALL.w[row][2];
   constexpr double s6 = 1.0 / 6.0;
@@ -77,10 +80,12 @@ __device__ __forceinline__ double weight_entry(int row, int q) {
   return 0.0;
 }
 
-// Row of the weight table selected by a decision byte.
+// Row of the weight table selected by a decision byte (S6: selector 3 with
+// bit 2 set).
 __device__ __forceinline__ int weight_row(uint8_t flag) {
   const int sel = flag & 3;
-  return sel == 0 ? (flag >> 2) & 7 : 7 + sel;
+  if (sel == 0) return (flag >> 2) & 7;
+  return (sel == 3 && (flag & 4)) ? 11 : 7 + sel;
 }
 
 __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
@@ -128,8 +133,11 @@ void sweep_vjp_kernel(AdjointArgs A) {
   const double gam = A.gamma;
   const double gm1 = gam - 1.0;
 
-  // ghost mapping of tile cell ct: source cell along the normal and wall kind
-  auto map_cell = [&](int ct, int64_t& t, int64_t& l, int& mirror_bc) {
+  // ghost mapping of tile cell ct, as in the forward sweep: the source cell
+  // along the normal, the boundary kind that makes it a ghost (-1 for a
+  // domain cell, a periodic or outflow copy, or a cell beyond the G ghost
+  // layers that no face reads), the side and the ghost layer 1..G
+  auto map_cell = [&](int ct, int64_t& t, int64_t& l, int& gbc, int& side, int64_t& layer) {
     int tt, nn;
     if (DIR == 0) {
       tt = ct / NC;
@@ -140,32 +148,44 @@ void sweep_vjp_kernel(AdjointArgs A) {
     }
     t = t0 + tt;
     l = f0 - G + nn;
-    mirror_bc = -1;
+    gbc = -1;
+    side = (l < 0) ? 0 : 1;
+    layer = (l < 0) ? -l : l - nN + 1;
     if (l < 0 || l >= nN) {
       const int bc = (l < 0) ? A.bc_lo : A.bc_hi;
       if (bc == TENOAA_BC_PERIODIC) {
         l = ((l % nN) + nN) % nN;
-      } else if (bc == TENOAA_BC_OUTFLOW) {
+      } else if (bc == TENOAA_BC_OUTFLOW || layer > G) {
         l = (l < 0) ? 0 : nN - 1;
       } else {
         l = (l < 0) ? -l - 1 : 2 * nN - 1 - l;
-        mirror_bc = bc;
+        gbc = bc;
       }
       if (l < 0) l = 0;
       if (l >= nN) l = nN - 1;
     }
   };
+  // boundary values of pencil t's cell of the face plane on side `side`
+  const int64_t plane = nA * A.n[AX_B];
+  auto face_vals = [&](int side, int64_t t) { return A.bcv[side] + t + nA * bcoord; };
 
   for (int ct = threadIdx.x; ct < NCT; ct += NTH) {
-    int64_t t, l;
-    int mbc;
-    map_cell(ct, t, l, mbc);
+    int64_t t, l, layer;
+    int gbc, side;
+    map_cell(ct, t, l, gbc, side, layer);
     if (t >= nA) t = nA - 1;
     const int64_t off = l * stride[DIR] + t * stride[AX_A] + bcoord * stride[AX_B];
     double Wc[NV];
     unroll<NV>([&](auto c) { Wc[c] = A.U[c * ncell + off]; });
-    if (mbc == TENOAA_BC_SYMMETRY) Wc[1 + DIR] = -Wc[1 + DIR];
-    if (mbc == TENOAA_BC_NOSLIP) unroll<NDIM>([&](auto k) { Wc[1 + k] = -Wc[1 + k]; });
+    if (gbc == TENOAA_BC_SYMMETRY) {
+      Wc[1 + DIR] = -Wc[1 + DIR];
+    } else if (gbc == TENOAA_BC_NOSLIP) {
+      unroll<NDIM>([&](auto k) { Wc[1 + k] = -Wc[1 + k]; });
+    } else if (gbc == TENOAA_BC_DIRICHLET) {
+      dirichlet_ghost<NDIM>(Wc, face_vals(side, t), plane, gm1);
+    } else if (gbc == TENOAA_BC_INFLOW) {
+      inflow_ghost<NDIM>(Wc, face_vals(side, t) + (layer - 1) * NV * plane, plane, gm1);
+    }
     // the same arithmetic as the forward sweep, so that the frozen splitting
     // speeds are attained by the same cells
     const double rho = Wc[0];
@@ -302,7 +322,7 @@ void sweep_vjp_kernel(AdjointArgs A) {
     unroll<W>([&](auto j) {
       const int li = lbase + j * LSTEP;
       const double u = sUn[li], c = sC[li];
-      if (A.splitting == TENOAA_LLF) {
+      if (A.splitting != TENOAA_RUSANOV) {  // LLF, also the Roe flux's fallback
         const double lm = fabs(u - c), l0 = fabs(u), lp = fabs(u + c);
         if (lm > am) { am = lm; jm = j; }
         if (l0 > a0) { a0 = l0; j0 = j; }
@@ -312,7 +332,7 @@ void sweep_vjp_kernel(AdjointArgs A) {
         if (lr > a0) { a0 = lr; j0 = j; }
       }
     });
-    if (A.splitting != TENOAA_LLF) {
+    if (A.splitting == TENOAA_RUSANOV) {
       am = ap = a0;
       jm = jp = j0;
     }
@@ -370,12 +390,19 @@ void sweep_vjp_kernel(AdjointArgs A) {
     L[1][1] = b1 * un;
     unroll<NDIM - 1>([&](auto k) { L[1][2 + k] = b1 * ut[k]; });
     L[1][NV - 1] = -b1;
-    // frozen reconstructions: row of the weight table per field and side
+    // frozen reconstructions: row of the weight table per field and side.
+    // The Roe flux reconstructs the unsplit characteristic flux g from one
+    // side only where the field's eigenvalue keeps one sign at the face; the
+    // other side's byte is then 0 (no real decision has it)
     int rowp[NV], rowm[NV];
+    bool one_side[NV];
     unroll<NV>([&](auto ss) {
       constexpr int s = decltype(ss)::value;
-      rowp[s] = weight_row(A.flags[(int64_t)(2 * s) * A.nft + flin]);
-      rowm[s] = weight_row(A.flags[(int64_t)(2 * s + 1) * A.nft + flin]);
+      const uint8_t bp = A.flags[(int64_t)(2 * s) * A.nft + flin];
+      const uint8_t bm = A.flags[(int64_t)(2 * s + 1) * A.nft + flin];
+      rowp[s] = weight_row(bp);
+      rowm[s] = weight_row(bm);
+      one_side[s] = A.splitting == TENOAA_ROE && (bp == 0 || bm == 0);
     });
     double Lb[3][NV], Lbs[NT];
     unroll<3>([&](auto r) { unroll<NV>([&](auto c) { Lb[r][c] = 0.0; }); });
@@ -408,9 +435,10 @@ void sweep_vjp_kernel(AdjointArgs A) {
         const double cm = sWT[rowm[s] * W + (W - 1 - j)] * fhb[s];
         const double alpha = (s == 0) ? am : (s == NV - 1 ? ap : a0);
         const double d = cp - cm;
-        vb[s] = (0.5 * alpha) * d;
-        gb[s] = 0.5 * (cp + cm);
-        const double ab = (0.5 * v) * d;
+        // split: f+- = (g +- alpha v) / 2; one-sided Roe: f = g (the unused side's row is zero)
+        vb[s] = one_side[s] ? 0.0 : (0.5 * alpha) * d;
+        gb[s] = one_side[s] ? cp + cm : 0.5 * (cp + cm);
+        const double ab = one_side[s] ? 0.0 : (0.5 * v) * d;
         if constexpr (s == 0) am_b += ab;
         else if constexpr (s == NV - 1) ap_b += ab;
         else a0_b += ab;
@@ -448,7 +476,7 @@ void sweep_vjp_kernel(AdjointArgs A) {
     });
 
     // splitting speeds: frozen argmax cells and signs
-    if (A.splitting == TENOAA_LLF) {
+    if (A.splitting != TENOAA_RUSANOV) {
       {
         const int li = lbase + jm * LSTEP;
         const double sg = (sUn[li] - sC[li]) < 0.0 ? -1.0 : 1.0;
@@ -538,10 +566,10 @@ void sweep_vjp_kernel(AdjointArgs A) {
 
   // ---- cell-level reverse pass and scatter to U_bar
   for (int ct = threadIdx.x; ct < NCT; ct += NTH) {
-    int64_t tc, l;
-    int mbc;
-    map_cell(ct, tc, l, mbc);
-    if (tc >= nA) continue;
+    int64_t tc, l, layer;
+    int gbc, side;
+    map_cell(ct, tc, l, gbc, side, layer);
+    if (tc >= nA || gbc == TENOAA_BC_INFLOW) continue;  // an inflow ghost does not depend on U
     const double2 w0 = sWF[0][ct];
     const double rho = w0.x;
     const double E = sWF[NV - 1][ct].x;
@@ -604,9 +632,41 @@ void sweep_vjp_kernel(AdjointArgs A) {
     Ub[0] = rho_b;
     Ub[NV - 1] = E_b;
     unroll<NDIM>([&](auto a) { Ub[1 + a] = m_b[Fr::slot_of_axis(decltype(a)::value)]; });
-    if (mbc == TENOAA_BC_SYMMETRY) Ub[1 + DIR] = -Ub[1 + DIR];
-    if (mbc == TENOAA_BC_NOSLIP) unroll<NDIM>([&](auto k) { Ub[1 + k] = -Ub[1 + k]; });
+    if (gbc == TENOAA_BC_SYMMETRY) Ub[1 + DIR] = -Ub[1 + DIR];
+    if (gbc == TENOAA_BC_NOSLIP) unroll<NDIM>([&](auto k) { Ub[1 + k] = -Ub[1 + k]; });
     const int64_t off = l * stride[DIR] + tc * stride[AX_A] + bcoord * stride[AX_B];
+    if (gbc == TENOAA_BC_DIRICHLET) {
+      // through the ghost rule (rho, u, p)_g = 2 (rho, u, p)_face - (rho, u, p)_m
+      // back to the mirror cell m: ghost conserved -> ghost primitives, the
+      // reflection (-1), mirror primitives -> mirror conserved
+      double Wm[NV];
+      unroll<NV>([&](auto cc) { Wm[cc] = A.U[cc * ncell + off]; });
+      const double* fv = face_vals(side, tc);
+      const double rm = Wm[0];
+      double um[NDIM], q2m = 0.0;
+      unroll<NDIM>([&](auto k) {
+        um[k] = Wm[1 + k] / rm;
+        q2m += um[k] * um[k];
+      });
+      const double rg = 2.0 * fv[0] - rm;
+      double ug[NDIM], qg = 0.0;
+      unroll<NDIM>([&](auto k) {
+        ug[k] = 2.0 * fv[(1 + k) * plane] - um[k];
+        qg += ug[k] * ug[k];
+      });
+      double rg_b = Ub[0] + Ub[NV - 1] * (0.5 * qg);
+      unroll<NDIM>([&](auto k) { rg_b += Ub[1 + k] * ug[k]; });
+      const double pm_b = -Ub[NV - 1] / gm1;
+      double Um[NV];
+      Um[NV - 1] = gm1 * pm_b;
+      Um[0] = -rg_b + gm1 * 0.5 * q2m * pm_b;
+      unroll<NDIM>([&](auto k) {
+        const double um_b = -(Ub[1 + k] * rg + Ub[NV - 1] * rg * ug[k]);
+        Um[1 + k] = um_b / rm - gm1 * um[k] * pm_b;
+        Um[0] -= um_b * um[k] / rm;
+      });
+      unroll<NV>([&](auto cc) { Ub[cc] = Um[cc]; });
+    }
     unroll<NV>([&](auto cc) { unsafeAtomicAdd(&A.Ubar[cc * ncell + off], Ub[cc]); });
   }
 }
@@ -658,6 +718,7 @@ static hipError_t launch_vjp_ord(int ndim, int dir, const AdjointArgs& a, hipStr
 }
 
 hipError_t launch_sweep_vjp(int order, int ndim, int dir, const AdjointArgs& a, hipStream_t st) {
+  if (order == 12) return launch_vjp_ord<12>(ndim, dir, a, st);
   return order == 10 ? launch_vjp_ord<10>(ndim, dir, a, st) : launch_vjp_ord<8>(ndim, dir, a, st);
 }
 

@@ -287,7 +287,7 @@ int recorded_sweeps(const Ctx& c, const double* U, int st, const uint8_t* frozen
     uint8_t* flags = reinterpret_cast<uint8_t*>(c.ws + c.L.vjp[st][d]);
     double* fh = reinterpret_cast<double*>(c.ws + c.L.vjp[st][d] + c.L.vjp_fh_rel[d]);
     double* th = limit ? reinterpret_cast<double*>(c.ws + c.L.vjp[st][d] + c.L.vjp_th_rel[d]) : nullptr;
-    int rc = sweeps(c, U, limit, flags, frozen ? frozen + off : nullptr, d, fh, 0, th);
+    int rc = sweeps(c, U, limit, flags, frozen ? frozen + off : nullptr, d, fh, st, th);
     if (rc) return rc;
     off += (int64_t)(c.g->ndim + 2) * 2 * faces_total(c.g, d);
   }
@@ -322,6 +322,8 @@ int rhs_vjp(const Ctx& c, const double* U, const double* R, double* Ubar, int st
     a.nf = faces_along(g, d);
     a.bc_lo = g->bc_lo[d];
     a.bc_hi = g->bc_hi[d];
+    a.bcv[0] = face_values(g, c.s->order, d, 0, st);
+    a.bcv[1] = face_values(g, c.s->order, d, 1, st);
     a.splitting = c.s->splitting;
     a.gamma = c.gamma;
     a.dx = g->dx[d];
@@ -402,7 +404,6 @@ int tenoaa_step_flags(const tenoaa_grid* grid, const tenoaa_scheme* scheme, doub
   if (scheme->positivity && cfl > 0.5) return TENOAA_EINVAL;
   if (mode < TENOAA_FLAGS_NONE || mode > TENOAA_FLAGS_REPLAY) return TENOAA_EINVAL;
   if (mode != TENOAA_FLAGS_NONE && !flags3) return TENOAA_EINVAL;
-  if (mode == TENOAA_FLAGS_REPLAY && scheme->splitting == TENOAA_ROE) return TENOAA_EUNSUPPORTED;
   if ((rc = begin(c))) return rc;
   const int64_t ncell = grid->n[0] * grid->n[1] * grid->n[2];
   double* Us = reinterpret_cast<double*>(c.ws + c.L.stage);
@@ -435,7 +436,6 @@ int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double 
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_RHS_VJP);
   if (rc) return rc;
   if (!U || !dUdt_bar || !U_bar || U_bar == U || U_bar == dUdt_bar) return TENOAA_EINVAL;
-  if (boundary_values_any(grid) || scheme->splitting == TENOAA_ROE || scheme->order == 12) return TENOAA_EUNSUPPORTED;
   if ((rc = begin(c))) return rc;
   if ((rc = recorded_sweeps(c, U, 0, flags))) return rc;
   return rhs_vjp(c, U, dUdt_bar, U_bar, 0);
@@ -448,7 +448,6 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP_VJP);
   if (rc) return rc;
   if (!Un || !dt_dev || !Unp1_bar || !Un_bar || Un_bar == Unp1_bar || Un_bar == Un) return TENOAA_EINVAL;
-  if (boundary_values_any(grid) || scheme->splitting == TENOAA_ROE || scheme->order == 12) return TENOAA_EUNSUPPORTED;
   const bool limit = scheme->positivity != 0;
   if ((rc = begin(c))) return rc;
   const int64_t N = (int64_t)(grid->ndim + 2) * grid->n[0] * grid->n[1] * grid->n[2];
@@ -462,9 +461,9 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
   // fluxes: U1 = Un + dt L(Un), U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1), and the
   // sweeps of U2
   if (limit) {
-    // the limiter factors of every stage from the wave speeds of Un and the given dt, as in the forward step
-    const int64_t ncell = grid->n[0] * grid->n[1] * grid->n[2];
-    e = tenoaa::launch_wave_speeds(grid->ndim, Un, ncell, gamma, c.S, &c.S->status, c.st);
+    // the limiter factors of every stage from the wave speeds of Un (and of the
+    // ghost cells of prescribed sides) and the given dt, as in the forward step
+    e = wave_speeds(c, Un);
     if (e == hipSuccess) {
       hipLaunchKernelGGL(copy_dt_kernel, dim3(1), dim3(64), 0, c.st, c.S, dt_dev);
       e = hipGetLastError();

@@ -66,6 +66,7 @@ struct AdjointArgs {
   const uint8_t* flags;  // decisions of this direction's forward sweep at U, [nvar][2][nft]
   const double* fh;      // per-field fluxes of that sweep, [nvar][nft]
   const double* theta;   // the sweep's limiter factors per face, or null (no limiter)
+  const double* bcv[2];  // boundary values of the low/high side (Dirichlet, inflow), else null
   int64_t nft;
   int64_t n[3];
   int64_t nf;

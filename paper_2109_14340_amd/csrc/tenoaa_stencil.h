@@ -325,9 +325,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     // is reconstructed from the upwind side alone; elsewhere LLF
     int upwind = 0;  // 0: split, 1: + side only, 2: - side only
     if constexpr (ROE) {
-      const double ka = (s == 0) ? -1.0 : (s == NV - 1 ? 1.0 : 0.0);
-      const double la = sUn[ia] + ka * sC[ia], lb = sUn[ib] + ka * sC[ib];
-      upwind = (la > 0.0 && lb > 0.0) ? 1 : ((la < 0.0 && lb < 0.0) ? 2 : 0);
+      if (frozen) {
+        // replay: the side the recorded decisions reconstruct (the other's byte is 0)
+        const uint8_t bp = frozen[(int64_t)(s * 2 + 0) * A.nft], bm = frozen[(int64_t)(s * 2 + 1) * A.nft];
+        upwind = bm == 0 ? 1 : (bp == 0 ? 2 : 0);
+      } else {
+        const double ka = (s == 0) ? -1.0 : (s == NV - 1 ? 1.0 : 0.0);
+        const double la = sUn[ia] + ka * sC[ia], lb = sUn[ib] + ka * sC[ib];
+        upwind = (la > 0.0 && lb > 0.0) ? 1 : ((la < 0.0 && lb < 0.0) ? 2 : 0);
+      }
     }
     // projection of the window's state and flux on field s, then the split
     double gp[W], gm[W];

@@ -268,6 +268,7 @@ def rhs_vjp(grid, scheme, U, dUdt_bar, gamma=1.4, out=None, ws=None, flags=None)
     import torch
     _check_state(U, grid)
     _check_state(dUdt_bar, grid)
+    _check_boundary_values(grid, scheme)
     if out is None:
         out = torch.empty_like(U)
     if ws is None:
@@ -286,6 +287,7 @@ def step_vjp(grid, scheme, Un, dt_dev, Unp1_bar, gamma=1.4, out=None, ws=None, f
     import torch
     _check_state(Un, grid)
     _check_state(Unp1_bar, grid)
+    _check_boundary_values(grid, scheme)
     if out is None:
         out = torch.empty_like(Un)
     if ws is None:

@@ -1,0 +1,260 @@
+"""The HIP adjoint with the scheme options beyond LLF/Rusanov on wall and
+periodic boundaries: the Roe flux with entropy fix (the side each field
+reconstructs frozen with the other decisions), TENO12-AA, and the prescribed
+boundaries (Dirichlet ghosts differentiated through their reflection rule,
+inflow ghosts constant).  Dot-product tests <w, J v> (oracle forward mode,
+dual numbers with the same frozen decisions) = <J^T w, v> (GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2109_14340_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2109_14340_amd import tenoaa  # noqa: E402
+from tests.test_gpu_dirichlet import _face_values, _smooth  # noqa: E402
+
+D = tenoaa.BC_DIRICHLET
+I = tenoaa.BC_INFLOW  # noqa: E741
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _grids(shape, lo, hi=None, faces=None):
+    dx = [1.0 / n for n in shape]
+    hi = lo if hi is None else hi
+    g_or = oracle.make_grid(shape, dx, lo, hi, bc_values=faces)
+    g_gpu = tenoaa.make_grid(shape, dx, lo, hi,
+                             bc_values=None if faces is None else {k: _dev(v) for k, v in faces.items()})
+    return g_or, g_gpu
+
+
+def _seeds(U, seed):
+    rng = np.random.default_rng(seed)
+    V = rng.standard_normal(U.shape) * np.abs(U).reshape(U.shape[0], -1).max(axis=1)[:, None, None, None]
+    return V, rng.standard_normal(U.shape)
+
+
+def _rhs_dot(g_or, g_gpu, U, order, splitting, seed):
+    V, Wt = _seeds(U, seed)
+    _, flags, margins = oracle.rhs(g_or, U, order=order, splitting=splitting)
+    assert (margins <= 1e-12).sum() == 0
+    _, jv = oracle.rhs_jvp(g_or, U, V, flags, order=order, splitting=splitting)
+    sch = tenoaa.make_scheme(order, splitting, 0)
+    jtw = tenoaa.to_numpy(tenoaa.rhs_vjp(g_gpu, sch, _dev(U), _dev(Wt)))
+    lhs, rhs = float(np.sum(Wt * jv)), float(np.sum(jtw * V))
+    scale = float(np.sum(np.abs(Wt * jv)))
+    print(U.shape, order, splitting, "<w,Jv> %.15e  <J^T w,v> %.15e  rel %.2e" % (lhs, rhs, abs(lhs - rhs) / scale))
+    assert abs(lhs - rhs) <= 1e-11 * scale
+    return flags
+
+
+def _step_dot(g_or, g_gpu, U, order, splitting, positivity, seed):
+    _, dt, flags3, margins3 = oracle.step(g_or, U, order=order, splitting=splitting, positivity=positivity, cfl=0.4,
+                                          want_flags=True)
+    assert (margins3 <= 1e-12).sum() == 0
+    V, Wt = _seeds(U, seed)
+    jv = oracle.step_jvp(g_or, U, V, dt, flags3, order=order, splitting=splitting, positivity=positivity)
+    sch = tenoaa.make_scheme(order, splitting, positivity)
+    dtd = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    jtw = tenoaa.to_numpy(tenoaa.step_vjp(g_gpu, sch, _dev(U), dtd, _dev(Wt)))
+    lhs, rhs = float(np.sum(Wt * jv)), float(np.sum(jtw * V))
+    scale = float(np.sum(np.abs(Wt * jv)))
+    print(U.shape, order, splitting, positivity, "step <w,Jv> %.15e  <J^T w,v> %.15e  rel %.2e"
+          % (lhs, rhs, abs(lhs - rhs) / scale))
+    assert abs(lhs - rhs) <= 1e-11 * scale
+    return flags3
+
+
+def _one_sided(flags):
+    """Number of (field, face) pairs the Roe flux reconstructs from one side."""
+    return int((flags == 0).sum())
+
+
+def _sonic_1d(n=64):
+    """A 1D state with flow in both directions and a jump (one-sided and split fields)."""
+    x = (np.arange(n) + 0.5) / n
+    rho = 1.0 + 0.3 * np.exp(-40 * (x - 0.4) ** 2)
+    u = 0.8 * np.sin(2 * np.pi * x) + 0.1
+    p = 1.0 + 0.5 * (x > 0.55)
+    return inputs._as_layout(inputs.conserved_from_primitive(rho, [u], p, 1.4), 1)
+
+
+@pytest.mark.parametrize("order", [8, 10])
+def test_roe_rhs_vjp_1d(order):
+    g_or, g_gpu = _grids((64,), [tenoaa.BC_PERIODIC])
+    flags = _rhs_dot(g_or, g_gpu, _sonic_1d(), order, tenoaa.ROE, 11)
+    assert _one_sided(flags) > 0 and (flags != 0).sum() > flags.size // 2
+
+
+def test_roe_rhs_vjp_2d_walls():
+    U = np.ascontiguousarray(inputs.grf_2d(36, seed=23)[:, :, :19, :23])
+    g_or, g_gpu = _grids((23, 19), [tenoaa.BC_SYMMETRY, tenoaa.BC_OUTFLOW])
+    flags = _rhs_dot(g_or, g_gpu, U, 10, tenoaa.ROE, 12)
+    assert _one_sided(flags) > 0
+
+
+def test_roe_rhs_vjp_3d():
+    U = np.ascontiguousarray(inputs.blast_cavity_3d(16)[:, :11, :13, :14])
+    g_or, g_gpu = _grids((14, 13, 11), [0, 1, 2])
+    flags = _rhs_dot(g_or, g_gpu, U, 10, tenoaa.ROE, 13)
+    assert _one_sided(flags) > 0
+
+
+def test_roe_step_vjp():
+    g_or, g_gpu = _grids((64,), [tenoaa.BC_OUTFLOW])
+    flags3 = _step_dot(g_or, g_gpu, inputs.shock_tube_1d(64), 10, tenoaa.ROE, 0, 14)
+    assert _one_sided(flags3) > 0
+
+
+def test_roe_step_vjp_limiter_acting():
+    """The Sec. 5.3.1 double rarefaction after 15 limited Roe steps: near
+    vacuum at the centre, where the positivity limiter acts in the next step."""
+    n = 64
+    x = (np.arange(n) + 0.5) / n
+    U = inputs._as_layout(inputs.conserved_from_primitive(np.ones(n), [np.where(x < 0.5, -2.0, 2.0)],
+                                                          np.full(n, 0.1), 1.4), 1)
+    g_or, g_gpu = _grids((n,), [tenoaa.BC_OUTFLOW])
+    for _ in range(15):
+        U, _, _, _ = oracle.step(g_or, U, order=10, splitting=tenoaa.ROE, positivity=1, cfl=0.4)
+    Ul, dt, _, _ = oracle.step(g_or, U, order=10, splitting=tenoaa.ROE, positivity=1, cfl=0.4)
+    Uu, _, _, _ = oracle.step(g_or, U, order=10, splitting=tenoaa.ROE, positivity=0, dt=dt)
+    assert not np.array_equal(Ul, Uu), "the limiter does not act on this state"
+    flags3 = _step_dot(g_or, g_gpu, U, 10, tenoaa.ROE, 1, 20)
+    assert _one_sided(flags3) > 0
+
+
+def test_teno12_rhs_vjp_1d():
+    g_or, g_gpu = _grids((64,), [tenoaa.BC_OUTFLOW])
+    flags = _rhs_dot(g_or, g_gpu, inputs.shock_tube_1d(64), 12, tenoaa.LLF, 15)
+    sel = flags & 7
+    assert (sel == 7).any() and ((flags & 3) == 0).any()  # S6 and the fallback both occur
+
+
+@pytest.mark.parametrize("splitting", [tenoaa.LLF, tenoaa.RUSANOV, tenoaa.ROE])
+def test_teno12_rhs_vjp_2d(splitting):
+    U = np.ascontiguousarray(inputs.grf_2d(32, seed=24)[:, :, :21, :26])
+    g_or, g_gpu = _grids((26, 21), [tenoaa.BC_NOSLIP, tenoaa.BC_PERIODIC])
+    _rhs_dot(g_or, g_gpu, U, 12, splitting, 16)
+
+
+def test_teno12_step_vjp_3d_limiter():
+    g_or, g_gpu = _grids((12, 12, 12), [0, 0, 0])
+    _step_dot(g_or, g_gpu, inputs.blast_cavity_3d(12), 12, tenoaa.LLF, 1, 17)
+
+
+BOUNDARY_CASES = {
+    "1d": ((64,), [D], [I], lambda: inputs.shock_tube_1d(64)),
+    "2d_mixed": ((37, 45), [D, tenoaa.BC_SYMMETRY], [I, D], lambda: _smooth((37, 45), 12)),
+    "3d_all": ((20, 18, 16), [D, I, D], [I, D, D], lambda: _smooth((20, 18, 16), 13)),
+}
+
+
+@pytest.mark.parametrize("case", list(BOUNDARY_CASES))
+@pytest.mark.parametrize("order,splitting", [(10, tenoaa.LLF), (8, tenoaa.RUSANOV)])
+def test_prescribed_boundaries_rhs_vjp(case, order, splitting):
+    shape, lo, hi, make = BOUNDARY_CASES[case]
+    U = make()
+    faces = _face_values(U, shape, lo, hi, 1.4, 1, seed=21, order=order)
+    g_or, g_gpu = _grids(shape, lo, hi, faces)
+    _rhs_dot(g_or, g_gpu, U, order, splitting, 18)
+
+
+def test_dirichlet_only_rhs_vjp_full_jacobian():
+    """Every column of the oracle's Jacobian on a small 1D grid with Dirichlet
+    sides: J^T w element by element (the mirror cells' entries carry the
+    reflection rule's Jacobian)."""
+    n = 16
+    U = _smooth((n,), 4)
+    faces = _face_values(U, (n,), [D], [D], 1.4, 1, seed=5, order=10)
+    g_or, g_gpu = _grids((n,), [D], [D], faces)
+    _, flags, margins = oracle.rhs(g_or, U, order=10)
+    assert (margins <= 1e-12).sum() == 0
+    N = U.size
+    J = np.empty((N, N))
+    for k in range(N):
+        e = np.zeros(N)
+        e[k] = 1.0
+        _, col = oracle.rhs_jvp(g_or, U, e.reshape(U.shape), flags, order=10)
+        J[:, k] = col.reshape(-1)
+    Wt = np.random.default_rng(6).standard_normal(N)
+    ref = J.T @ Wt
+    got = tenoaa.to_numpy(tenoaa.rhs_vjp(g_gpu, tenoaa.make_scheme(10), _dev(U),
+                                         _dev(Wt.reshape(U.shape)))).reshape(-1)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("Dirichlet 1D: max rel err of J^T w: %.2e" % err)
+    assert err <= 1e-11
+
+
+@pytest.mark.parametrize("sets,positivity", [(1, 0), (3, 1)])
+def test_prescribed_boundaries_step_vjp(sets, positivity):
+    """One step with Dirichlet and inflow sides (three per-stage value sets:
+    stage s of the recomputation and of the reverse pass reads set s)."""
+    shape, lo, hi = (40, 36), [D, tenoaa.BC_NOSLIP], [I, D]
+    U = _smooth(shape, 5)
+    faces = _face_values(U, shape, lo, hi, 1.4, sets, seed=3, order=10)
+    g_or, g_gpu = _grids(shape, lo, hi, faces)
+    _step_dot(g_or, g_gpu, U, 10, tenoaa.LLF, positivity, 19)
+
+
+def test_roe_rhs_vjp_with_flags_of_another_state():
+    """Roe decisions recorded at another state replay the side each field
+    reconstructs as well: dot test against the oracle's JVP with the same
+    flags, at a state whose own one-sided choices differ from the recorded."""
+    n = 64
+    g_or, g_gpu = _grids((n,), [tenoaa.BC_PERIODIC])
+    U = _sonic_1d(n)
+    x = (np.arange(n) + 0.5) / n
+    Up = inputs._as_layout(inputs.conserved_from_primitive(
+        1.0 + 0.3 * np.exp(-40 * (x - 0.4) ** 2), [0.8 * np.sin(2 * np.pi * x + 0.7) + 0.1],
+        1.0 + 0.5 * (x > 0.55), 1.4), 1)
+    _, fl_u, _ = oracle.rhs(g_or, U, order=10, splitting=tenoaa.ROE)
+    _, fl_p, _ = oracle.rhs(g_or, Up, order=10, splitting=tenoaa.ROE)
+    assert ((fl_p == 0) != (fl_u == 0)).sum() > 0  # the one-sided choices differ
+    V, Wt = _seeds(U, 21)
+    _, jv = oracle.rhs_jvp(g_or, U, V, fl_p, order=10, splitting=tenoaa.ROE)
+    sch = tenoaa.make_scheme(10, tenoaa.ROE, 0)
+    jtw = tenoaa.to_numpy(tenoaa.rhs_vjp(g_gpu, sch, _dev(U), _dev(Wt), flags=_dev(fl_p)))
+    lhs, rhs = float(np.sum(Wt * jv)), float(np.sum(jtw * V))
+    scale = float(np.sum(np.abs(Wt * jv)))
+    print("Roe flags of another state: <w,Jv> %.15e <J^T w,v> %.15e rel %.2e" % (lhs, rhs, abs(lhs - rhs) / scale))
+    assert abs(lhs - rhs) <= 1e-11 * scale
+
+
+def test_roe_step_replay():
+    """tenoaa_step_flags with the Roe flux: replaying the recorded decisions at
+    the same state reproduces the step bit for bit; replaying them at another
+    state equals the oracle's three stages with those decisions frozen."""
+    n = 64
+    g_or, g_gpu = _grids((n,), [tenoaa.BC_OUTFLOW])
+    U = inputs.shock_tube_1d(n)
+    sch = tenoaa.make_scheme(10, tenoaa.ROE, 0)
+    fl3 = torch.zeros(3 * tenoaa.flags_size(g_gpu), dtype=torch.uint8, device="cuda")
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Ua = tenoaa.step_flags(g_gpu, sch, _dev(U), dt, fl3, tenoaa.FLAGS_RECORD)
+    Ub = tenoaa.step_flags(g_gpu, sch, _dev(U), dt.clone(), fl3, tenoaa.FLAGS_REPLAY)
+    assert torch.equal(Ua, Ub)
+    rng = np.random.default_rng(22)
+    Up = U * (1.0 + 0.02 * rng.standard_normal(U.shape))
+    Uc = tenoaa.to_numpy(tenoaa.step_flags(g_gpu, sch, _dev(Up), dt.clone(), fl3, tenoaa.FLAGS_REPLAY))
+    f = fl3.cpu().numpy()
+    nfl = tenoaa.flags_size(g_gpu)
+    dtv = float(dt.item())
+    z = np.zeros_like(Up)
+    L0, _ = oracle.rhs_jvp(g_or, Up, z, f[:nfl], order=10, splitting=tenoaa.ROE)
+    U1 = Up + dtv * L0
+    L1, _ = oracle.rhs_jvp(g_or, U1, z, f[nfl:2 * nfl], order=10, splitting=tenoaa.ROE)
+    U2 = 0.75 * Up + 0.25 * U1 + (0.25 * dtv) * L1
+    L2, _ = oracle.rhs_jvp(g_or, U2, z, f[2 * nfl:], order=10, splitting=tenoaa.ROE)
+    U3 = (1.0 / 3.0) * Up + (2.0 / 3.0) * U2 + ((2.0 / 3.0) * dtv) * L2
+    _, flp, _ = oracle.rhs(g_or, Up, order=10, splitting=tenoaa.ROE)
+    print("replayed decisions differing from the state's own (stage 1): %d" % int((flp != f[:nfl]).sum()))
+    err = np.abs(Uc - U3).reshape(3, -1).max(axis=1) / np.abs(U3).reshape(3, -1).max(axis=1)
+    assert err.max() <= 1e-13, err

@@ -104,3 +104,40 @@ def test_mirror_symmetry_across_sonic_points(order):
     split = (f[1, 0] != 0) & (f[1, 1] != 0)
     assert 1 <= split.sum() <= 4
     assert np.all((f[0, 0] == 0) & (f[0, 1] != 0)) and np.all((f[2, 0] != 0) & (f[2, 1] == 0))
+
+
+@pytest.mark.parametrize("order", [8, 10])
+def test_replayed_decisions_replay_the_side(order):
+    """Recorded decisions fix the side each field reconstructs as well: the
+    decisions of supersonic flow to the right (every field one-sided from the
+    left, largest stencil), replayed on a subsonic state whose own decisions
+    take the left-going acoustic field from the right, give the upwind linear
+    scheme of the subsonic state's physical flux from the left (R L = I at
+    each face); the state's own decisions replay to its own right-hand side
+    bit for bit."""
+    n = 32
+    G = order // 2
+    big = 5 if order == 10 else 4
+    g = oracle.make_grid((n,), [1.0 / n], [oracle.BC_PERIODIC])
+    rho, u, p = _state_1d(n, 3.0)
+    UA = inputs._as_layout(inputs.conserved_from_primitive(rho, [u], p, G_), 1)
+    _, flA, _ = oracle.rhs(g, UA, order=order, splitting=oracle.ROE, gamma=G_)
+    assert np.all(flA.reshape(3, 2, n)[:, 1] == 0)
+    rho, u, p = _state_1d(n, 0.3)
+    UB = inputs._as_layout(inputs.conserved_from_primitive(rho, [u], p, G_), 1)
+    dB, flB, _ = oracle.rhs(g, UB, order=order, splitting=oracle.ROE, gamma=G_)
+    fB = flB.reshape(3, 2, n)
+    assert np.all((fB[0, 0] == 0) & (fB[0, 1] != 0))  # u - c < 0: from the right at this state
+    again, _ = oracle.rhs_jvp(g, UB, np.zeros_like(UB), flB, order=order, splitting=oracle.ROE, gamma=G_)
+    assert np.array_equal(again, dB)
+    got, _ = oracle.rhs_jvp(g, UB, np.zeros_like(UB), flA, order=order, splitting=oracle.ROE, gamma=G_)
+    F = _flux_1d(rho, u, p)
+    Fh = np.empty((3, n))
+    for c in range(3):
+        ext = np.concatenate([F[c, -G:], F[c], F[c, :G]])
+        for i in range(n):
+            Fh[c, i] = oracle.candidate_flux(big, ext, i + G)
+    want = -(Fh - np.roll(Fh, 1, axis=1)) * n
+    assert np.abs(got[:, 0, 0] - want).max() <= 1e-11 * np.abs(want).max()
+    # the state's own choice (field 0 from the right) gives a different result
+    assert np.abs(dB[:, 0, 0] - want).max() > 1e-9 * np.abs(want).max()
