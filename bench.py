@@ -127,6 +127,102 @@ def fwd_adj_leg(shape, steps, warmup, U0):
                     "copy of the input state is inside fwd_ms"}
 
 
+def slab_leg(U0, pieces=8, steps=5, warmup=1):
+    """One GPU's share of the same workload split into `pieces` z-slabs: each
+    slab is a grid n x n x n/pieces whose z sides are halo sides holding the
+    neighbour slabs' 5 cells next to the cut.  A split step is: halo refresh,
+    wave speeds per slab and their maximum, then per stage a halo refresh and
+    tenoaa_rk3_stage on every slab.  Checked once, untimed: the slabs' step
+    equals tenoaa_step on the whole grid bit for bit.  Timed: one slab's
+    share of a step (speeds + three stages) with its halos in place; the halo
+    exchanges and the maximum over GPUs are the communication a multi-GPU
+    run adds, reported as bytes."""
+    import torch
+
+    from paper_2109_14340_amd import tenoaa
+
+    dev = U0.device
+    n = U0.shape[-1]
+    nz = n // pieces
+    G = 5
+    sch = tenoaa.make_scheme(10, tenoaa.LLF, 1)
+    spans = [(k * nz, (k + 1) * nz) for k in range(pieces)]
+
+    def halos(full, lo, hi):
+        out = {}
+        for side in (0, 1):
+            idx = [(lo - r) % n if side == 0 else (hi - 1 + r) % n for r in range(1, G + 1)]
+            out[(2, side)] = full[:, idx].permute(1, 0, 2, 3).reshape(1, G, 5, n * n).contiguous()
+        return out
+
+    grids = [tenoaa.make_grid((n, n, nz), [1.0 / n] * 3, [0, 0, tenoaa.BC_HALO], [0, 0, tenoaa.BC_HALO],
+                              bc_values=halos(U0, lo, hi)) for lo, hi in spans]
+    wss = [tenoaa.workspace(g, sch, tenoaa.WS_RHS, dev) for g in grids]
+
+    def exchange(states):
+        full = torch.cat(states, dim=1)
+        for (lo, hi), g in zip(spans, grids):
+            for key, v in halos(full, lo, hi).items():
+                g._faces[key].copy_(v)
+
+    def split_step(slabs, stage_states, dt):
+        exchange(slabs)
+        amax = torch.stack([tenoaa.wave_speeds(g, sch, u, ws=w) for g, u, w in zip(grids, slabs, wss)])
+        amax = amax.max(dim=0).values.contiguous()
+        dt.zero_()
+        for stage in (1, 2, 3):
+            if stage > 1:
+                exchange(stage_states)
+            for k in range(pieces):
+                tenoaa.rk3_stage(grids[k], sch, stage, amax, dt, slabs[k], None if stage == 1 else stage_states[k],
+                                 slabs[k] if stage == 3 else stage_states[k], ws=wss[k])
+
+    # bitwise check of the split step against the whole grid's
+    slabs = [U0[:, lo:hi].contiguous() for lo, hi in spans]
+    stage_states = [torch.empty_like(u) for u in slabs]
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    split_step(slabs, stage_states, dt)
+    whole = U0.clone()
+    dtw = torch.zeros(1, dtype=torch.float64, device=dev)
+    g_whole = tenoaa.make_grid((n, n, n))
+    tenoaa.step(g_whole, sch, whole, dtw)
+    equal = bool(torch.equal(torch.cat(slabs, dim=1), whole)) and float(dt.item()) == float(dtw.item())
+    del whole, stage_states
+
+    # one slab's share, timed (halos of U0 in place, the speeds of the whole step)
+    g0, w0 = grids[0], wss[0]
+    exchange([U0[:, lo:hi].contiguous() for lo, hi in spans])
+    u = U0[:, :nz].contiguous()
+    us = torch.empty_like(u)
+    amax = torch.stack([tenoaa.wave_speeds(g, sch, U0[:, lo:hi].contiguous(), ws=w)
+                        for g, (lo, hi), w in zip(grids, spans, wss)]).max(dim=0).values.contiguous()
+
+    def share():
+        u.copy_(U0[:, :nz])
+        tenoaa.wave_speeds(g0, sch, u, ws=w0)
+        dt.zero_()
+        for stage in (1, 2, 3):
+            tenoaa.rk3_stage(g0, sch, stage, amax, dt, u, None if stage == 1 else us, u if stage == 3 else us, ws=w0)
+
+    for _ in range(warmup):
+        share()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        share()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    if any(tenoaa.get_status(w) != 0 for w in wss):
+        raise RuntimeError("non-physical state in the split step")
+    work = 9 * n * n * nz
+    return {"grid": [n, n, nz], "pieces": pieces, "ms_per_step": round(ms, 3),
+            "value": round(work / (ms * 1e-3) / 1e9, 4), "unit": "Gface-recon/s",
+            "halo_bytes_per_stage": 2 * G * 5 * n * n * 8,
+            "split_step_bitwise_equal_to_whole_grid": equal,
+            "note": "one slab's share of a step (wave speeds + three stages, the state copy inside); halo "
+                    "exchanges and the maximum of the speeds over the slabs excluded"}
+
+
 def batched_leg(nprob=512, nsteps=20, tune_cache=None):
     """The batched workload: nprob 2D problems with n_x, n_y ~ U{64..512},
     TENO8-AA, LLF, outflow, nsteps SSP-RK3 steps each with its own dt, in one
@@ -206,6 +302,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fwd-adj", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-slab", action="store_true")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain copy of the state (a kernel of known traffic) for counter runs")
@@ -308,6 +405,8 @@ def main():
         line["fwd_adj"] = {"3d": fwd_adj_leg((n, n, n), 3, 1, U3),
                            "2d_512_periodic": fwd_adj_leg((512, 512), 20, 3, U2)}
         del U3, U2
+    if not args.no_slab:
+        line["slab_share"] = slab_leg(torch.from_numpy(inputs.grf_3d(n)).to(dev))
     if not args.no_batched:
         line["batched"] = batched_leg(tune_cache=args.tune_cache)
     if not args.no_cpu_baseline:

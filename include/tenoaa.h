@@ -72,14 +72,20 @@ enum {
  * tenoaa_grid.bc_values.  INFLOW is a supersonic inflow (every
  * characteristic enters the domain, as at the outer boundaries of the Noh
  * problem in Sec. 5): the ghost cells take prescribed states, also from
- * tenoaa_grid.bc_values. */
+ * tenoaa_grid.bc_values.  HALO (not a boundary of the paper): the ghost
+ * cells take given CONSERVED states as they are, so that a grid split into
+ * pieces (one per GPU) computes on each piece exactly what the whole grid
+ * computes there when each side facing a neighbour piece holds the
+ * neighbour's order/2 cells next to that face (a halo exchange before every
+ * SSP-RK3 stage; see tenoaa_rk3_stage). */
 enum {
   TENOAA_BC_PERIODIC = 0,
   TENOAA_BC_OUTFLOW = 1,
   TENOAA_BC_SYMMETRY = 2,
   TENOAA_BC_NOSLIP = 3,
   TENOAA_BC_DIRICHLET = 4,
-  TENOAA_BC_INFLOW = 5
+  TENOAA_BC_INFLOW = 5,
+  TENOAA_BC_HALO = 6
 };
 
 /* Flux splitting (Sec. 5): LLF uses, per characteristic field, the largest
@@ -102,23 +108,26 @@ enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1, TENOAA_WS_RHS_VJP = 2, TENOAA_WS_S
  * n[d] >= order/2 for d < ndim and n[d] == 1 otherwise; dx[d] > 0.
  *
  * Boundary values (read only where bc_lo[d] / bc_hi[d] is
- * TENOAA_BC_DIRICHLET or TENOAA_BC_INFLOW, else ignored and may be NULL):
+ * TENOAA_BC_DIRICHLET, TENOAA_BC_INFLOW or TENOAA_BC_HALO, else ignored and
+ * may be NULL):
  * bc_values[d][0] (low side) and bc_values[d][1] (high side) are DEVICE
  * arrays owned by the caller.  With P = the product of n[k] over k != d (the
  * face plane, the lower of the two remaining axes fastest), a "layer" is
  * nvar x P doubles: the planes rho, u_x, [u_y], [u_z], p (primitives,
  * velocities in axis order).  A Dirichlet side holds bc_sets layers (the face
  * values); an inflow side bc_sets x (order / 2) layers, per set the ghost
- * cells r = 1 .. order/2 counted outward from the face.  bc_sets is 1 or 3:
+ * cells r = 1 .. order/2 counted outward from the face.  A halo side has the
+ * inflow layout with conserved planes (rho, rho u_x, [rho u_y], [rho u_z], E)
+ * instead of primitives.  bc_sets is 1 or 3:
  * with 3, stage s of an SSP-RK3 step reads set s (the caller supplies the
  * values at t, t + dt and t + dt/2, the times the three stages approximate)
  * and tenoaa_rhs reads set 0; with 1 every evaluation reads set 0.  A smaller
  * array than this is undefined behaviour (the library cannot check device
  * allocations).  Grids with such sides are rejected with
- * TENOAA_EUNSUPPORTED by the batch plan.  The adjoint entry points
- * differentiate a Dirichlet ghost through its reflection rule (the face
- * values are constants), take inflow ghosts as constants, and read set s in
- * stage s as the step does. */
+ * TENOAA_EUNSUPPORTED by the batch plan, and grids with halo sides by the
+ * adjoint entry points.  The adjoint entry points differentiate a Dirichlet
+ * ghost through its reflection rule (the face values are constants), take
+ * inflow ghosts as constants, and read set s in stage s as the step does. */
 typedef struct {
   int32_t ndim;
   int32_t bc_sets;
@@ -191,6 +200,34 @@ int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double 
 int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* Un,
                     const double* dt_dev, const double* Unp1_bar, double* Un_bar, const uint8_t* flags3, void* ws,
                     size_t ws_bytes, void* stream);
+
+/* Wave speeds a_d = max (|u_d| + c) over the cells of U and the first ghost
+ * layer of every side with prescribed or halo values (value set 0), d <
+ * ndim, written to amax_dev (device, ndim doubles; the CFL condition of
+ * Sec. 5 and the limiter's weights use them).  For a grid split into pieces
+ * the step's speeds are the maxima over the pieces.  Workspace: RHS. */
+int tenoaa_wave_speeds(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
+                       double* amax_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* Stage `stage` (1, 2, 3) of the SSP-RK3 step (Sec. 5, Shu-Osher form):
+ *   1: out = Un + dt L(Un)
+ *   2: out = 3/4 Un + 1/4 Us + 1/4 dt L(Us)
+ *   3: out = 1/3 Un + 2/3 Us + 2/3 dt L(Us)
+ * with the arithmetic of tenoaa_step, so the three stages with the same dt
+ * and speeds give tenoaa_step's result bit for bit.  amax_dev (device, ndim
+ * doubles): the wave speeds of Un (tenoaa_wave_speeds; for a split grid the
+ * maxima over the pieces), which the limiter's weights use; dt_dev (device
+ * double): if it holds a value <= 0 on entry, dt = cfl / sum_d (a_d / dx_d)
+ * from amax_dev is computed and stored there (pass the same dt_dev to the
+ * later stages).  Sides with boundary or halo values read set stage - 1 when
+ * bc_sets is 3, else set 0: a split grid refreshes its halo sides from the
+ * neighbours' stage state before each stage.  Us is ignored in stage 1 and
+ * required in stages 2 and 3; out may alias Un or Us (each cell's update
+ * reads only its own Un, Us values after the sweeps).  0 < cfl <= 1, with
+ * the limiter cfl <= 0.5.  Workspace: RHS. */
+int tenoaa_rk3_stage(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, int32_t stage,
+                     const double* amax_dev, double* dt_dev, const double* Un, const double* Us, double* out,
+                     void* ws, size_t ws_bytes, void* stream);
 
 /* Decision modes of tenoaa_step_flags. */
 enum { TENOAA_FLAGS_NONE = 0, TENOAA_FLAGS_RECORD = 1, TENOAA_FLAGS_REPLAY = 2 };

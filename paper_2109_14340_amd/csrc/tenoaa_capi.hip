@@ -89,7 +89,8 @@ bool valid_grid(const tenoaa_grid* g, const tenoaa_scheme* s) {
   for (int d = 0; d < 3; ++d) {
     if (d < g->ndim) {
       if (g->n[d] < s->order / 2 || !(g->dx[d] > 0.0)) return false;
-      if (g->bc_lo[d] < 0 || g->bc_lo[d] > 5 || g->bc_hi[d] < 0 || g->bc_hi[d] > 5) return false;
+      if (g->bc_lo[d] < 0 || g->bc_lo[d] > TENOAA_BC_HALO || g->bc_hi[d] < 0 || g->bc_hi[d] > TENOAA_BC_HALO)
+        return false;
       if ((g->bc_lo[d] == TENOAA_BC_PERIODIC) != (g->bc_hi[d] == TENOAA_BC_PERIODIC)) return false;
       for (int h = 0; h < 2; ++h)
         if ((h ? g->bc_hi[d] : g->bc_lo[d]) >= TENOAA_BC_DIRICHLET) {
@@ -171,7 +172,7 @@ struct Ctx {
   hipStream_t st;
 };
 
-// True if a side takes prescribed values (Dirichlet or inflow).
+// True if a side takes prescribed or halo values.
 bool boundary_values_any(const tenoaa_grid* g) {
   for (int d = 0; d < g->ndim; ++d)
     if (g->bc_lo[d] >= TENOAA_BC_DIRICHLET || g->bc_hi[d] >= TENOAA_BC_DIRICHLET) return true;
@@ -180,14 +181,14 @@ bool boundary_values_any(const tenoaa_grid* g) {
 
 // Boundary values of side (d, h) for SSP-RK3 stage `stage` (0 outside a
 // step), or null: a set holds one layer of nvar face-plane arrays
-// (Dirichlet) or order/2 layers (inflow).
+// (Dirichlet) or order/2 layers (inflow, halo).
 const double* face_values(const tenoaa_grid* g, int order, int d, int h, int stage) {
   const int bc = h ? g->bc_hi[d] : g->bc_lo[d];
-  if (bc != TENOAA_BC_DIRICHLET && bc != TENOAA_BC_INFLOW) return nullptr;
+  if (bc != TENOAA_BC_DIRICHLET && bc != TENOAA_BC_INFLOW && bc != TENOAA_BC_HALO) return nullptr;
   int64_t plane = 1;
   for (int k = 0; k < 3; ++k)
     if (k != d) plane *= g->n[k];
-  const int64_t layers = bc == TENOAA_BC_INFLOW ? order / 2 : 1;
+  const int64_t layers = bc == TENOAA_BC_DIRICHLET ? 1 : order / 2;
   const int set = g->bc_sets == 3 ? stage : 0;
   return g->bc_values[d][h] + (int64_t)set * layers * (g->ndim + 2) * plane;
 }
@@ -356,6 +357,11 @@ int begin(const Ctx&) { return TENOAA_OK; }
 namespace tenoaa {
 bool grid_ok(const tenoaa_grid* g, const tenoaa_scheme* s) { return valid_grid(g, s); }
 bool has_boundary_values(const tenoaa_grid* g) { return boundary_values_any(g); }
+bool has_halo(const tenoaa_grid* g) {
+  for (int d = 0; d < g->ndim; ++d)
+    if (g->bc_lo[d] == TENOAA_BC_HALO || g->bc_hi[d] == TENOAA_BC_HALO) return true;
+  return false;
+}
 void record_hip_error(hipError_t e) { g_last_hip_error = (int)e; }
 }  // namespace tenoaa
 
@@ -436,6 +442,7 @@ int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double 
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_RHS_VJP);
   if (rc) return rc;
   if (!U || !dUdt_bar || !U_bar || U_bar == U || U_bar == dUdt_bar) return TENOAA_EINVAL;
+  if (tenoaa::has_halo(grid)) return TENOAA_EUNSUPPORTED;
   if ((rc = begin(c))) return rc;
   if ((rc = recorded_sweeps(c, U, 0, flags))) return rc;
   return rhs_vjp(c, U, dUdt_bar, U_bar, 0);
@@ -448,6 +455,7 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
   int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP_VJP);
   if (rc) return rc;
   if (!Un || !dt_dev || !Unp1_bar || !Un_bar || Un_bar == Unp1_bar || Un_bar == Un) return TENOAA_EINVAL;
+  if (tenoaa::has_halo(grid)) return TENOAA_EUNSUPPORTED;
   const bool limit = scheme->positivity != 0;
   if ((rc = begin(c))) return rc;
   const int64_t N = (int64_t)(grid->ndim + 2) * grid->n[0] * grid->n[1] * grid->n[2];
@@ -493,6 +501,37 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
     return hip_fail(e);
   if ((e = tenoaa::launch_axpdtz(Un_bar, 1.0, Un_bar, 1.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
   return TENOAA_OK;
+}
+
+int tenoaa_wave_speeds(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
+                       double* amax_dev, void* ws, size_t ws_bytes, void* stream) {
+  Ctx c;
+  int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_RHS);
+  if (rc) return rc;
+  if (!U || !amax_dev) return TENOAA_EINVAL;
+  if ((rc = begin(c))) return rc;
+  hipError_t e = timed(TENOAA_KCLASS_WAVESPEED, c.st, [&] { return wave_speeds(c, U); });
+  if (e == hipSuccess) e = tenoaa::launch_speeds_out(c.S, grid->ndim, amax_dev, c.st);
+  return e == hipSuccess ? TENOAA_OK : hip_fail(e);
+}
+
+int tenoaa_rk3_stage(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, int32_t stage,
+                     const double* amax_dev, double* dt_dev, const double* Un, const double* Us, double* out,
+                     void* ws, size_t ws_bytes, void* stream) {
+  Ctx c;
+  int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_RHS);
+  if (rc) return rc;
+  if (stage < 1 || stage > 3 || !amax_dev || !dt_dev || !Un || !out || (stage > 1 && !Us)) return TENOAA_EINVAL;
+  if (!(cfl > 0.0) || cfl > 1.0) return TENOAA_EINVAL;
+  if (scheme->positivity && cfl > 0.5) return TENOAA_EINVAL;
+  if ((rc = begin(c))) return rc;
+  // the step's speeds and dt (computed from the speeds if *dt_dev <= 0), and the limiter factors
+  hipError_t e = tenoaa::launch_speeds_in(c.S, grid->ndim, amax_dev, c.st);
+  if (e == hipSuccess) e = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, cfl, dt_dev, 0.0, c.st);
+  if (e != hipSuccess) return hip_fail(e);
+  const double* Ul = stage == 1 ? Un : Us;
+  if ((rc = sweeps(c, Ul, scheme->positivity != 0, nullptr, nullptr, -1, nullptr, stage - 1))) return rc;
+  return update(c, stage, Un, stage == 1 ? nullptr : Us, out);
 }
 
 int tenoaa_get_status(void* ws, void* stream, int32_t* out) {

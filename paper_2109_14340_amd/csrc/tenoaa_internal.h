@@ -79,8 +79,10 @@ struct AdjointArgs {
 
 // Argument check of a grid and scheme (shared by every entry point).
 bool grid_ok(const tenoaa_grid* g, const tenoaa_scheme* s);
-// True if a side of the grid takes prescribed values (Dirichlet or inflow).
+// True if a side of the grid takes prescribed or halo values.
 bool has_boundary_values(const tenoaa_grid* g);
+// True if a side of the grid takes halo values.
+bool has_halo(const tenoaa_grid* g);
 // Keeps e for tenoaa_last_hip_error().
 void record_hip_error(hipError_t e);
 
@@ -97,5 +99,8 @@ hipError_t launch_wave_speeds(int ndim, const double* U, int64_t ncell, double g
 hipError_t launch_ghost_speeds(int ndim, const GhostSpeedArgs& a, Scalars* S, int* status, hipStream_t st);
 hipError_t launch_finalize_dt(Scalars* S, int ndim, const double* dx, double cfl, double* dt_dev, double dt_fixed,
                               hipStream_t st);
+// The scalars' wave speeds to amax (ndim doubles), and from it.
+hipError_t launch_speeds_out(const Scalars* S, int ndim, double* amax, hipStream_t st);
+hipError_t launch_speeds_in(Scalars* S, int ndim, const double* amax, hipStream_t st);
 
 }  // namespace tenoaa

@@ -145,8 +145,10 @@ __global__ __launch_bounds__(256) void ghost_speed_kernel(GhostSpeedArgs A, Scal
     if (A.bc == TENOAA_BC_DIRICHLET) {
       unroll<NV>([&](auto c) { Wc[c] = A.U[c * ncell + cell]; });
       dirichlet_ghost<NDIM>(Wc, A.fv + p, plane, A.gamma - 1.0);
-    } else {
+    } else if (A.bc == TENOAA_BC_INFLOW) {
       inflow_ghost<NDIM>(Wc, A.fv + p, plane, A.gamma - 1.0);
+    } else {  // halo, first layer: the neighbour's cell next to the face
+      unroll<NV>([&](auto c) { Wc[c] = A.fv[c * plane + p]; });
     }
     cell_speeds<NDIM>(Wc, A.gamma, amax, bad);
   }
@@ -177,6 +179,20 @@ __global__ void finalize_dt_kernel(Scalars* S, int ndim, double dx0, double dx1,
   dt_and_mu(S->amax_bits, ndim, dx, cfl, given, dt, S->mu);
   if (dt_dev) *dt_dev = dt;
   S->dt = dt;
+}
+
+// The wave speeds of the scalars as doubles, and back (their bit patterns
+// order like the values: the speeds are non-negative).
+__global__ void speeds_out_kernel(const Scalars* S, int ndim, double* amax) {
+  if (threadIdx.x < (unsigned)ndim) amax[threadIdx.x] = __longlong_as_double((long long)S->amax_bits[threadIdx.x]);
+}
+
+// A speed that is negative or not a number marks the status word.
+__global__ void speeds_in_kernel(Scalars* S, int ndim, const double* amax) {
+  if (threadIdx.x >= 3) return;
+  const double a = threadIdx.x < (unsigned)ndim ? amax[threadIdx.x] : 0.0;
+  if (!(a >= 0.0)) atomicOr(&S->status, 1);
+  S->amax_bits[threadIdx.x] = (unsigned long long)__double_as_longlong(a >= 0.0 ? a : 0.0);
 }
 
 }  // namespace
@@ -269,6 +285,16 @@ hipError_t launch_ghost_speeds(int ndim, const GhostSpeedArgs& a, Scalars* S, in
   if (ndim == 1) hipLaunchKernelGGL(ghost_speed_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, a, S, status);
   if (ndim == 2) hipLaunchKernelGGL(ghost_speed_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, st, a, S, status);
   if (ndim == 3) hipLaunchKernelGGL(ghost_speed_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, st, a, S, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_speeds_out(const Scalars* S, int ndim, double* amax, hipStream_t st) {
+  hipLaunchKernelGGL(speeds_out_kernel, dim3(1), dim3(64), 0, st, S, ndim, amax);
+  return hipGetLastError();
+}
+
+hipError_t launch_speeds_in(Scalars* S, int ndim, const double* amax, hipStream_t st) {
+  hipLaunchKernelGGL(speeds_in_kernel, dim3(1), dim3(64), 0, st, S, ndim, amax);
   return hipGetLastError();
 }
 

@@ -179,8 +179,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
         unroll<NDIM>([&](auto k) { Wc[1 + k] = -Wc[1 + k]; });
       } else if (bc == TENOAA_BC_DIRICHLET) {
         dirichlet_ghost<NDIM>(Wc, fv, plane, gm1);
-      } else {
+      } else if (bc == TENOAA_BC_INFLOW) {
         inflow_ghost<NDIM>(Wc, fv + (layer - 1) * NV * plane, plane, gm1);
+      } else {  // halo: the neighbour piece's conserved state
+        unroll<NV>([&](auto c) { Wc[c] = fv[((layer - 1) * NV + c) * plane]; });
       }
     }
     // cell primitives (Sec. 1), axis order

@@ -13,7 +13,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtenoaa.so")
 
-BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP, BC_DIRICHLET, BC_INFLOW = 0, 1, 2, 3, 4, 5
+BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP, BC_DIRICHLET, BC_INFLOW, BC_HALO = 0, 1, 2, 3, 4, 5, 6
 LLF, RUSANOV, ROE = 0, 1, 2
 WS_RHS, WS_STEP, WS_RHS_VJP, WS_STEP_VJP = 0, 1, 2, 3
 ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENONPHYSICAL", -5: "EWORKSPACE", -6: "ETIMEOUT"}
@@ -22,7 +22,8 @@ FLAGS_NONE, FLAGS_RECORD, FLAGS_REPLAY = 0, 1, 2
 EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_step_flags", "tenoaa_rhs_vjp", "tenoaa_step_vjp",
            "tenoaa_get_status", "tenoaa_last_hip_error", "tenoaa_timing_enable", "tenoaa_timing_read",
            "tenoaa_batch_plan_create", "tenoaa_batch_offsets", "tenoaa_batch_run", "tenoaa_batch_get_status",
-           "tenoaa_batch_plan_info", "tenoaa_batch_plan_destroy", "tenoaa_advect"]
+           "tenoaa_batch_plan_info", "tenoaa_batch_plan_destroy", "tenoaa_advect", "tenoaa_wave_speeds",
+           "tenoaa_rk3_stage"]
 KCLASS_SWEEP = (0, 1, 2)
 KCLASS_UPDATE, KCLASS_WAVESPEED = 3, 4
 KCLASS_VJP = (5, 6, 7)
@@ -93,6 +94,11 @@ def load():
         L.tenoaa_advect.restype = ctypes.c_int
         L.tenoaa_advect.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_int64, vp, vp]
+        L.tenoaa_wave_speeds.restype = ctypes.c_int
+        L.tenoaa_wave_speeds.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tenoaa_rk3_stage.restype = ctypes.c_int
+        L.tenoaa_rk3_stage.argtypes = [gp, sp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp, vp, vp, vp,
+                                       vp, ctypes.c_size_t, vp]
         _lib = L
     return _lib
 
@@ -131,7 +137,9 @@ def set_face_values(grid, d, side, values):
     over the face plane (the grid without axis d, the lower remaining axis
     fastest).  A Dirichlet side takes the face values, shape
     (sets, nvar, plane) or (nvar, plane); an inflow side the ghost cells
-    r = 1 .. order/2 outward from the face, shape (sets, order/2, nvar, plane).
+    r = 1 .. order/2 outward from the face, shape (sets, order/2, nvar, plane);
+    a halo side the same layers as conserved states (rho, rho u_x, [rho u_y],
+    [rho u_z], E): a neighbour piece's cells next to the face.
     sets is 1, or 3 for the three SSP-RK3 stages (values at t, t + dt,
     t + dt/2), and the same on every side.  The grid keeps a reference to the
     tensor; its contents may be rewritten between calls."""
@@ -139,22 +147,23 @@ def set_face_values(grid, d, side, values):
     nv = grid.ndim + 2
     plane = face_plane(grid, d)
     bc = grid.bc_hi[d] if side else grid.bc_lo[d]
-    if bc not in (BC_DIRICHLET, BC_INFLOW):
+    if bc not in (BC_DIRICHLET, BC_INFLOW, BC_HALO):
         raise TenoaaError("side (%d, %d) takes no boundary values" % (d, side))
+    layered = bc in (BC_INFLOW, BC_HALO)
     if values.dtype != torch.float64 or not values.is_cuda or not values.is_contiguous():
         raise TenoaaError("boundary values must be a contiguous float64 device tensor")
-    want_dims = 4 if bc == BC_INFLOW else 3
+    want_dims = 4 if layered else 3
     shape = tuple(values.shape) if values.dim() == want_dims else (1,) + tuple(values.shape)
     if len(shape) != want_dims or shape[-2:] != (nv, plane) or shape[0] not in (1, 3):
         raise TenoaaError("boundary values of side (%d, %d): shape %s, want (sets,%s %d, %d) with sets 1 or 3"
-                          % (d, side, tuple(values.shape), " layers," if bc == BC_INFLOW else "", nv, plane))
+                          % (d, side, tuple(values.shape), " layers," if layered else "", nv, plane))
     sets = shape[0]
     others = [k for k in grid._faces if k != (d, side)]
     if others and grid.bc_sets != sets:
         raise TenoaaError("every side with boundary values needs the same number of value sets")
     grid._faces[(d, side)] = values
     grid._layers = getattr(grid, "_layers", {})
-    grid._layers[(d, side)] = shape[1] if bc == BC_INFLOW else 1
+    grid._layers[(d, side)] = shape[1] if layered else 1
     grid.bc_sets = sets
     grid.bc_values[d][side] = values.data_ptr()
 
@@ -164,11 +173,11 @@ def _check_boundary_values(grid, scheme):
     faces = getattr(grid, "_faces", {})
     for d in range(grid.ndim):
         for side, bc in ((0, grid.bc_lo[d]), (1, grid.bc_hi[d])):
-            if bc in (BC_DIRICHLET, BC_INFLOW):
+            if bc in (BC_DIRICHLET, BC_INFLOW, BC_HALO):
                 if (d, side) not in faces:
                     raise TenoaaError("side (%d, %d) has no boundary values bound" % (d, side))
-                if bc == BC_INFLOW and grid._layers[(d, side)] != scheme.order // 2:
-                    raise TenoaaError("inflow side (%d, %d) holds %d ghost layers, order %d needs %d"
+                if bc != BC_DIRICHLET and grid._layers[(d, side)] != scheme.order // 2:
+                    raise TenoaaError("inflow/halo side (%d, %d) holds %d ghost layers, order %d needs %d"
                                       % (d, side, grid._layers[(d, side)], scheme.order, scheme.order // 2))
 
 
@@ -321,6 +330,39 @@ def advect(order, u, dx, dt, nsteps):
         raise TenoaaError("u must be a contiguous 1D float64 device tensor")
     _check(load().tenoaa_advect(order, u.numel(), dx, dt, nsteps, _ptr(u), _stream()), "tenoaa_advect")
     return u
+
+
+def wave_speeds(grid, scheme, U, gamma=1.4, out=None, ws=None):
+    """a_d = max(|u_d| + c) over the cells of U and the first ghost layer of
+    sides with boundary or halo values: a float64 device tensor of ndim."""
+    import torch
+    _check_state(U, grid)
+    _check_boundary_values(grid, scheme)
+    if out is None:
+        out = torch.empty(grid.ndim, dtype=torch.float64, device=U.device)
+    if ws is None:
+        ws = workspace(grid, scheme, WS_RHS, U.device)
+    rc = load().tenoaa_wave_speeds(ctypes.byref(grid), ctypes.byref(scheme), gamma, _ptr(U), _ptr(out), _ptr(ws),
+                                   ws.numel(), _stream())
+    _check(rc, "tenoaa_wave_speeds")
+    return out
+
+
+def rk3_stage(grid, scheme, stage, amax, dt_dev, Un, Us, out, gamma=1.4, cfl=0.4, ws=None):
+    """Stage 1, 2 or 3 of the SSP-RK3 step into `out` (tenoaa_rk3_stage):
+    amax the step's wave speeds (ndim float64 on the device), dt_dev the
+    step's dt (computed from amax and cfl if it holds a value <= 0)."""
+    _check_state(Un, grid)
+    _check_state(out, grid)
+    if Us is not None:
+        _check_state(Us, grid)
+    _check_boundary_values(grid, scheme)
+    if ws is None:
+        ws = workspace(grid, scheme, WS_RHS, Un.device)
+    rc = load().tenoaa_rk3_stage(ctypes.byref(grid), ctypes.byref(scheme), gamma, cfl, stage, _ptr(amax),
+                                 _ptr(dt_dev), _ptr(Un), _ptr(Us), _ptr(out), _ptr(ws), ws.numel(), _stream())
+    _check(rc, "tenoaa_rk3_stage")
+    return out
 
 
 def get_status(ws):

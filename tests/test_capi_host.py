@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "tenoaa.h")).read()
-    return sorted(set(re.findall(r"\b(tenoaa_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(tenoaa_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_header_symbols():
@@ -113,7 +113,7 @@ def test_dirichlet_arguments_checked():
     assert L.tenoaa_workspace_bytes(ctypes.byref(ok), ctypes.byref(s), 0) > 0
     assert L.tenoaa_workspace_bytes(ctypes.byref(grid(sets=3)), ctypes.byref(s), 0) > 0
     assert L.tenoaa_workspace_bytes(ctypes.byref(grid(bc=tenoaa.BC_INFLOW)), ctypes.byref(s), 0) > 0
-    for bad in (grid(ptr=None), grid(sets=2), grid(sets=0), grid(bc=6)):
+    for bad in (grid(ptr=None), grid(sets=2), grid(sets=0), grid(bc=7)):
         assert L.tenoaa_workspace_bytes(ctypes.byref(bad), ctypes.byref(s), 0) == 0
     # the adjoint entry points accept such grids: with too small a workspace
     # they stop at the workspace check, before any device work
@@ -212,3 +212,39 @@ def test_batch_cache_key_buckets():
     s = tenoaa.make_scheme(8)
     grids = [tenoaa.make_grid((n, 64)) for n in (64, 160, 161, 320, 321, 512)]
     assert tenoaa.batch_cache_key(s, grids) == "gfx950 order=8 split=0 limit=0 buckets=2,2,2"
+
+
+def test_halo_and_stage_arguments_checked():
+    """Halo sides need their value pointer; the adjoint entry points reject
+    grids with halo sides; tenoaa_wave_speeds and tenoaa_rk3_stage check
+    their arguments before any device work."""
+    L = _lib()
+    vp = ctypes.c_void_p
+    H = tenoaa.BC_HALO
+    s = tenoaa.make_scheme(10)
+    g = tenoaa.make_grid((32, 24, 16), bc_lo=[0, 0, H], bc_hi=[0, 0, H])
+    assert L.tenoaa_workspace_bytes(ctypes.byref(g), ctypes.byref(s), 0) == 0  # no pointers bound
+    g.bc_values[2][0] = 4096
+    g.bc_values[2][1] = 8192
+    need = L.tenoaa_workspace_bytes(ctypes.byref(g), ctypes.byref(s), 0)
+    assert need > 0
+    big = 1 << 30
+    assert L.tenoaa_rhs_vjp(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), None, vp(1024),
+                            big, None) == -2
+    assert L.tenoaa_step_vjp(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), vp(4096), None,
+                             vp(1024), big, None) == -2
+    a, dt, un, us, out, ws = vp(256), vp(512), vp(1024), vp(2048), vp(4096), vp(8192)
+    # wave speeds: null state or output, small workspace
+    assert L.tenoaa_wave_speeds(ctypes.byref(g), ctypes.byref(s), 1.4, None, a, ws, need, None) == -1
+    assert L.tenoaa_wave_speeds(ctypes.byref(g), ctypes.byref(s), 1.4, un, None, ws, need, None) == -1
+    assert L.tenoaa_wave_speeds(ctypes.byref(g), ctypes.byref(s), 1.4, un, a, ws, need - 8, None) == -5
+
+    def stage(st=1, cfl=0.4, amax=a, dtd=dt, Un=un, Us=us, o=out, sch=s, nbytes=need):
+        return L.tenoaa_rk3_stage(ctypes.byref(g), ctypes.byref(sch), 1.4, cfl, st, amax, dtd, Un, Us, o, ws,
+                                  nbytes, None)
+
+    for bad in (dict(st=0), dict(st=4), dict(amax=None), dict(dtd=None), dict(Un=None), dict(o=None),
+                dict(st=2, Us=None), dict(cfl=0.0), dict(cfl=1.5),
+                dict(sch=tenoaa.make_scheme(10, 0, 1), cfl=0.6)):
+        assert stage(**bad) == -1, bad
+    assert stage(nbytes=need - 8) == -5
