@@ -80,12 +80,14 @@ __device__ __forceinline__ double weight_entry(int row, int q) {
   return 0.0;
 }
 
-// Row of the weight table selected by a decision byte (S6: selector 3 with
-// bit 2 set).
+// Row of the weight table selected by a decision byte (S6 of TENO12-AA:
+// selector 3 with bit 2 set).
+template <int ORDER>
 __device__ __forceinline__ int weight_row(uint8_t flag) {
   const int sel = flag & 3;
-  if (sel == 0) return (flag >> 2) & 7;
-  return (sel == 3 && (flag & 4)) ? 11 : 7 + sel;
+  int large = 7 + sel;
+  if constexpr (ORDER == 12) large += (sel == 3) & ((flag >> 2) & 1);
+  return sel == 0 ? (flag >> 2) & 7 : large;
 }
 
 __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
@@ -95,7 +97,7 @@ __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); 
 // cell's operands alive until the end of the window).
 __device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
 
-template <int ORDER, int NDIM, int DIR, int TT, int TN>
+template <int ORDER, int NDIM, int DIR, int TT, int TN, bool GENERAL>
 __global__ __launch_bounds__(TT* TN)
 #if TENOAA_ADJ_WAVES_PER_EU > 0
 __attribute__((amdgpu_waves_per_eu(TENOAA_ADJ_WAVES_PER_EU)))
@@ -181,10 +183,12 @@ void sweep_vjp_kernel(AdjointArgs A) {
       Wc[1 + DIR] = -Wc[1 + DIR];
     } else if (gbc == TENOAA_BC_NOSLIP) {
       unroll<NDIM>([&](auto k) { Wc[1 + k] = -Wc[1 + k]; });
-    } else if (gbc == TENOAA_BC_DIRICHLET) {
-      dirichlet_ghost<NDIM>(Wc, face_vals(side, t), plane, gm1);
-    } else if (gbc == TENOAA_BC_INFLOW) {
-      inflow_ghost<NDIM>(Wc, face_vals(side, t) + (layer - 1) * NV * plane, plane, gm1);
+    } else if constexpr (GENERAL) {
+      if (gbc == TENOAA_BC_DIRICHLET) {
+        dirichlet_ghost<NDIM>(Wc, face_vals(side, t), plane, gm1);
+      } else if (gbc == TENOAA_BC_INFLOW) {
+        inflow_ghost<NDIM>(Wc, face_vals(side, t) + (layer - 1) * NV * plane, plane, gm1);
+      }
     }
     // the same arithmetic as the forward sweep, so that the frozen splitting
     // speeds are attained by the same cells
@@ -400,9 +404,9 @@ void sweep_vjp_kernel(AdjointArgs A) {
       constexpr int s = decltype(ss)::value;
       const uint8_t bp = A.flags[(int64_t)(2 * s) * A.nft + flin];
       const uint8_t bm = A.flags[(int64_t)(2 * s + 1) * A.nft + flin];
-      rowp[s] = weight_row(bp);
-      rowm[s] = weight_row(bm);
-      one_side[s] = A.splitting == TENOAA_ROE && (bp == 0 || bm == 0);
+      rowp[s] = weight_row<ORDER>(bp);
+      rowm[s] = weight_row<ORDER>(bm);
+      one_side[s] = GENERAL && A.splitting == TENOAA_ROE && (bp == 0 || bm == 0);
     });
     double Lb[3][NV], Lbs[NT];
     unroll<3>([&](auto r) { unroll<NV>([&](auto c) { Lb[r][c] = 0.0; }); });
@@ -569,7 +573,7 @@ void sweep_vjp_kernel(AdjointArgs A) {
     int64_t tc, l, layer;
     int gbc, side;
     map_cell(ct, tc, l, gbc, side, layer);
-    if (tc >= nA || gbc == TENOAA_BC_INFLOW) continue;  // an inflow ghost does not depend on U
+    if (tc >= nA || (GENERAL && gbc == TENOAA_BC_INFLOW)) continue;  // an inflow ghost does not depend on U
     const double2 w0 = sWF[0][ct];
     const double rho = w0.x;
     const double E = sWF[NV - 1][ct].x;
@@ -635,7 +639,7 @@ void sweep_vjp_kernel(AdjointArgs A) {
     if (gbc == TENOAA_BC_SYMMETRY) Ub[1 + DIR] = -Ub[1 + DIR];
     if (gbc == TENOAA_BC_NOSLIP) unroll<NDIM>([&](auto k) { Ub[1 + k] = -Ub[1 + k]; });
     const int64_t off = l * stride[DIR] + tc * stride[AX_A] + bcoord * stride[AX_B];
-    if (gbc == TENOAA_BC_DIRICHLET) {
+    if (GENERAL && gbc == TENOAA_BC_DIRICHLET) {
       // through the ghost rule (rho, u, p)_g = 2 (rho, u, p)_face - (rho, u, p)_m
       // back to the mirror cell m: ghost conserved -> ghost primitives, the
       // reflection (-1), mirror primitives -> mirror conserved
@@ -699,12 +703,17 @@ __global__ void axpdtz_kernel(double* out, double a, const double* x, double c, 
 
 template <int ORDER, int NDIM, int DIR>
 static hipError_t launch_vjp_t(const AdjointArgs& a, hipStream_t st) {
+  // the Roe flux's one-sided fields and the ghost rules of prescribed sides
+  // in a variant of their own, which the common case does not carry
   constexpr int TT = (NDIM == 1) ? 1 : (DIR == 0 ? TENOAA_ADJ_TT_X : TENOAA_ADJ_TT_YZ);
   constexpr int TN = (DIR == 0) ? TENOAA_ADJ_TN_X : TENOAA_ADJ_TN_YZ;
   constexpr int AX_A = (DIR == 0) ? 1 : 0;
   constexpr int AX_B = (DIR == 2) ? 1 : 2;
   dim3 grid((unsigned)((a.nf + TN - 1) / TN), (unsigned)((a.n[AX_A] + TT - 1) / TT), (unsigned)a.n[AX_B]);
-  hipLaunchKernelGGL((sweep_vjp_kernel<ORDER, NDIM, DIR, TT, TN>), grid, dim3(TT * TN), 0, st, a);
+  if (a.splitting == TENOAA_ROE || a.bcv[0] || a.bcv[1])
+    hipLaunchKernelGGL((sweep_vjp_kernel<ORDER, NDIM, DIR, TT, TN, true>), grid, dim3(TT * TN), 0, st, a);
+  else
+    hipLaunchKernelGGL((sweep_vjp_kernel<ORDER, NDIM, DIR, TT, TN, false>), grid, dim3(TT * TN), 0, st, a);
   return hipGetLastError();
 }
 
