@@ -27,11 +27,12 @@ struct SweepArgs {
   int64_t n[3];
   int64_t nf;       // faces along the direction
   int64_t nft;      // faces of the direction in total
+  int64_t f_begin;  // first face along the direction of this launch's tiles
   int bc_lo, bc_hi;
   int splitting;
   int pad;
   double gamma;
-  const double* bcv[2];  // Dirichlet face values of the low/high side, this evaluation's set, or null
+  const double* bcv[2];  // boundary (Dirichlet, inflow, halo) values of the low/high side, this evaluation's set, or null
   const double* mu; // device: limiter factors
   int* status;      // device: status word
 };
@@ -97,6 +98,9 @@ hipError_t launch_update(int ndim, int mode, const UpdateArgs& a, hipStream_t st
 hipError_t launch_wave_speeds(int ndim, const double* U, int64_t ncell, double gam, Scalars* S, int* status,
                               hipStream_t st);
 hipError_t launch_ghost_speeds(int ndim, const GhostSpeedArgs& a, Scalars* S, int* status, hipStream_t st);
+// The faces [a.f_begin, a.nf) of a direction in one-wave tiles of 16 x 4
+// faces (the remainder of a direction's 32- or 64-face tiles).
+hipError_t launch_sweep_tail(int order, int ndim, int dir, const SweepArgs& a, bool limit, hipStream_t st);
 hipError_t launch_finalize_dt(Scalars* S, int ndim, const double* dx, double cfl, double* dt_dev, double dt_fixed,
                               hipStream_t st);
 // The scalars' wave speeds to amax (ndim doubles), and from it.

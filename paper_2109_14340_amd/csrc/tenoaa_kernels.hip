@@ -204,9 +204,19 @@ static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   constexpr int TN = (DIR == 0) ? TENOAA_TN_X : TENOAA_TN_YZ;
   constexpr int AX_A = (DIR == 0) ? 1 : 0;
   constexpr int AX_B = (DIR == 2) ? 1 : 2;
-  dim3 grid((unsigned)((a.nf + TN - 1) / TN), (unsigned)((a.n[AX_A] + TT - 1) / TT), (unsigned)a.n[AX_B]);
-  hipLaunchKernelGGL((sweep_kernel<ORDER, NDIM, DIR, TT, TN, LIMIT, ROE>), grid, dim3(TT * TN), 0, st, a);
-  return hipGetLastError();
+  // Whole tiles here; a remainder of faces (a non-periodic direction has
+  // n + 1) goes to one-wave tail tiles, since a block of full-tile LDS with
+  // one busy wave would hold a CU slot as long as a full tile.
+  const int64_t whole = (NDIM == 1) ? a.nf : (a.nf / TN) * TN;
+  if (whole > 0) {
+    dim3 grid((unsigned)((whole + TN - 1) / TN), (unsigned)((a.n[AX_A] + TT - 1) / TT), (unsigned)a.n[AX_B]);
+    hipLaunchKernelGGL((sweep_kernel<ORDER, NDIM, DIR, TT, TN, LIMIT, ROE>), grid, dim3(TT * TN), 0, st, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || whole == a.nf) return e;
+  }
+  SweepArgs t = a;
+  t.f_begin = whole;
+  return launch_sweep_tail(ORDER, NDIM, DIR, t, LIMIT, st);
 }
 
 template <int ORDER, int NDIM, int DIR>

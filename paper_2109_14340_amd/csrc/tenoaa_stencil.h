@@ -128,7 +128,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
   const int64_t nA = A.n[AX_A];
   const int64_t stride[3] = {1, A.n[0], A.n[0] * A.n[1]};
   const int64_t ncell = A.n[0] * A.n[1] * A.n[2];
-  const int64_t f0 = bx * TN;
+  const int64_t f0 = A.f_begin + bx * TN;
   const int64_t t0 = by * TT;
   const int64_t bcoord = bz;
   const double gam = A.gamma;
