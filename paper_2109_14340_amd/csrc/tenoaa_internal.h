@@ -98,8 +98,10 @@ hipError_t launch_update(int ndim, int mode, const UpdateArgs& a, hipStream_t st
 hipError_t launch_wave_speeds(int ndim, const double* U, int64_t ncell, double gam, Scalars* S, int* status,
                               hipStream_t st);
 hipError_t launch_ghost_speeds(int ndim, const GhostSpeedArgs& a, Scalars* S, int* status, hipStream_t st);
-// The faces [a.f_begin, a.nf) of a direction in one-wave tiles of 16 x 4
-// faces (the remainder of a direction's 32- or 64-face tiles).
+// One-wave tail tiles of the sweeps (pencils x faces) and their launch over
+// the faces [a.f_begin, a.nf) of a direction: a remainder of at most
+// SWEEP_TAIL_TN faces beyond the direction's last whole tile.
+constexpr int SWEEP_TAIL_TT = 16, SWEEP_TAIL_TN = 4;
 hipError_t launch_sweep_tail(int order, int ndim, int dir, const SweepArgs& a, bool limit, hipStream_t st);
 hipError_t launch_finalize_dt(Scalars* S, int ndim, const double* dx, double cfl, double* dt_dev, double dt_fixed,
                               hipStream_t st);

@@ -204,10 +204,12 @@ static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   constexpr int TN = (DIR == 0) ? TENOAA_TN_X : TENOAA_TN_YZ;
   constexpr int AX_A = (DIR == 0) ? 1 : 0;
   constexpr int AX_B = (DIR == 2) ? 1 : 2;
-  // Whole tiles here; a remainder of faces (a non-periodic direction has
-  // n + 1) goes to one-wave tail tiles, since a block of full-tile LDS with
-  // one busy wave would hold a CU slot as long as a full tile.
-  const int64_t whole = (NDIM == 1) ? a.nf : (a.nf / TN) * TN;
+  // Whole tiles here; a small remainder of faces (a non-periodic direction
+  // has n + 1) goes to one-wave tail tiles, since a block of full-tile LDS
+  // with one busy wave would hold a CU slot as long as a full tile.  Larger
+  // remainders take one more full-size tile, which stages fewer cells per face.
+  const int64_t rem = a.nf % TN;
+  const int64_t whole = (NDIM == 1 || rem == 0 || rem > SWEEP_TAIL_TN) ? a.nf : a.nf - rem;
   if (whole > 0) {
     dim3 grid((unsigned)((whole + TN - 1) / TN), (unsigned)((a.n[AX_A] + TT - 1) / TT), (unsigned)a.n[AX_B]);
     hipLaunchKernelGGL((sweep_kernel<ORDER, NDIM, DIR, TT, TN, LIMIT, ROE>), grid, dim3(TT * TN), 0, st, a);

@@ -1,5 +1,5 @@
-// Tail tiles of the forward sweeps: the faces of a direction beyond its last
-// whole 32- or 64-face tile (one face per pencil when a non-periodic
+// Tail tiles of the forward sweeps: the few faces of a direction beyond its
+// last whole 32- or 64-face tile (one face per pencil when a non-periodic
 // direction has n + 1 faces) in tiles of 16 pencils x 4 faces, one wave each,
 // with the same per-face code as the whole tiles.  Built in a translation
 // unit of its own so that it compiles beside the whole-tile kernels.
@@ -14,13 +14,7 @@
 namespace tenoaa {
 namespace {
 
-#ifndef TENOAA_TAIL_TT
-#define TENOAA_TAIL_TT 16
-#endif
-#ifndef TENOAA_TAIL_TN
-#define TENOAA_TAIL_TN 4
-#endif
-constexpr int TAIL_TT = TENOAA_TAIL_TT, TAIL_TN = TENOAA_TAIL_TN;  // pencils x faces, one wave
+constexpr int TAIL_TT = SWEEP_TAIL_TT, TAIL_TN = SWEEP_TAIL_TN;
 static_assert(TAIL_TT * TAIL_TN == 64, "a tail tile is one wave");
 
 template <int ORDER, int NDIM, int DIR, bool LIMIT, bool ROE>
