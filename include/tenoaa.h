@@ -281,7 +281,8 @@ typedef struct tenoaa_batch_plan tenoaa_batch_plan;
  * of the persistent kernel gives up after 20 s (the environment variable
  * TENOAA_BATCH_BARRIER_TIMEOUT_US, read here, sets another limit; tests use it
  * to exercise tenoaa_batch_get_status's TENOAA_ETIMEOUT).  Returns EINVAL
- * for bad arguments, EUNSUPPORTED for ndim != 2, EHIP on a HIP failure;
+ * for bad arguments, EUNSUPPORTED for ndim != 2, a side with boundary or
+ * halo values or order 12, EHIP on a HIP failure;
  * *out is NULL unless 0 is returned. */
 int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const tenoaa_scheme* scheme, double gamma,
                              double cfl, int32_t nsteps, const char* tune_cache_path, tenoaa_batch_plan** out);
