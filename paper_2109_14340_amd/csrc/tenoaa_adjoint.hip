@@ -1,679 +1,15 @@
-// Adjoint (vector-Jacobian product) of the TENO-AA Euler right-hand side.
-//
-// For a state U and a seed R = dL/d(dU/dt), one sweep kernel per direction
-// accumulates U_bar += (d(dU/dt)_d / dU)^T R with every threshold decision of
-// the method frozen at U: the stencil chosen by the cascade and the cut-off
-// deltas (Sec. 3.3 of the paper), hence the linear weights of each
-// reconstruction; the cell that attains each LLF/Rusanov splitting speed and
-// the sign of that speed; with the Roe flux, which side each field
-// reconstructs.  Everything else - cell primitives, Roe average,
-// eigenvectors, projection, split, back-projection - is differentiated
-// exactly.  With the positivity limiter, its factor theta per face (recorded
-// by the forward sweep) is frozen as well, and the Lax-Friedrichs flux it
-// blends in is differentiated with its speed's cell frozen.
-//
-// The forward sweep of the same direction runs first and leaves, per face,
-// the decision bytes and the per-field fluxes fh_s.  Per block: the tile of
-// cells is staged exactly as in the forward sweep; each thread takes one face,
-// recomputes the Roe average, eigenvectors, projections and splitting speeds,
-// then runs the reverse pass and scatters the adjoints of the window cells'
-// conserved states, physical fluxes and primitive quantities into LDS
-// accumulators (ds_add_f64).  After a barrier the cell-level reverse
-// pass turns those into conserved-state adjoints, maps ghost cells back to
-// their interior source (with the momentum sign flips of wall conditions) and
-// adds them to U_bar with global FP64 atomics (a Dirichlet ghost through the
-// Jacobian of its reflection rule; an inflow ghost is a constant), so the
-// summation order - and
-// the last bits of U_bar - can vary between runs.
+// Reverse-sweep launchers of the common case (LLF or Rusanov, no prescribed
+// sides) in whole tiles, and the element-wise kernels of the step adjoint's
+// SSP-RK3 chain.  The reverse sweep itself is in tenoaa_vjp.h.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
-#include "tenoaa_device.h"
 #include "tenoaa_internal.h"
-#include "tenoaa_stencil.h"
-
-#ifndef TENOAA_ADJ_TN_X
-#define TENOAA_ADJ_TN_X 64
-#endif
-#ifndef TENOAA_ADJ_TT_X
-#define TENOAA_ADJ_TT_X 2
-#endif
-#ifndef TENOAA_ADJ_TN_YZ
-#define TENOAA_ADJ_TN_YZ 16
-#endif
-#ifndef TENOAA_ADJ_TT_YZ
-#define TENOAA_ADJ_TT_YZ 8
-#endif
-#ifndef TENOAA_ADJ_WAVES_PER_EU
-#define TENOAA_ADJ_WAVES_PER_EU 0
-#endif
+#include "tenoaa_vjp.h"
 
 namespace tenoaa {
 namespace {
-
-// Derivatives of the frozen reconstructions with respect to the window values
-// f_{-G+1..G}: one row per outcome of the cascade.  Rows 0-7: the TENO5
-// fallback with delta mask 0-7 (weights d_k delta_k / sum, Sec. 3.3, times the
-// three third-order candidates); rows 8, 9, 10, 11: the linear schemes on S3,
-// S4, S5 (Sec. 4.1) and S6 (TENO12-AA), stencil S_p starting at v[G - p].
-// Row 0 (no small stencil kept) is all zeros: the byte of a side the Roe flux
-// does not reconstruct selects it.
-constexpr int NROW = 12;
-template <int ORDER>
-__device__ __forceinline__ double weight_entry(int row, int q) {
-  constexpr int G = ORDER / 2;
-  constexpr int I = G - 1;
-  if (row >= 8) {
-    const int p = row - 5;
-    const int P = G - p;
-    if (p > G || q < P || q >= P + 2 * p) return 0.0;
-    return p == 3 ? lin_coef<6>(q - P) : (p == 4 ? lin_coef<8>(q - P) : (p == 5 ? lin_coef<10>(q - P) : lin_coef<12>(q - P)));
-  }
-  const double w0 = WFALL.w[row][0], w1 = WFALL.w[row][1], w2 = WFALL.w[row][2];
-  constexpr double s6 = 1.0 / 6.0;
-  if (q == I - 2) return w2 * (2.0 * s6);
-  if (q == I - 1) return w0 * (-s6) + w2 * (-7.0 * s6);
-  if (q == I) return w0 * (5.0 * s6) + w1 * (2.0 * s6) + w2 * (11.0 * s6);
-  if (q == I + 1) return w0 * (2.0 * s6) + w1 * (5.0 * s6);
-  if (q == I + 2) return w1 * (-s6);
-  return 0.0;
-}
-
-// Row of the weight table selected by a decision byte (S6 of TENO12-AA:
-// selector 3 with bit 2 set).
-template <int ORDER>
-__device__ __forceinline__ int weight_row(uint8_t flag) {
-  const int sel = flag & 3;
-  int large = 7 + sel;
-  if constexpr (ORDER == 12) large += (sel == 3) & ((flag >> 2) & 1);
-  return sel == 0 ? (flag >> 2) & 7 : large;
-}
-
-__device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
-
-// Materialises x in a register here: keeps the compiler from sinking the
-// accumulations of a window cell past the next cell (which would keep every
-// cell's operands alive until the end of the window).
-__device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
-
-template <int ORDER, int NDIM, int DIR, int TT, int TN, bool GENERAL>
-__global__ __launch_bounds__(TT* TN)
-#if TENOAA_ADJ_WAVES_PER_EU > 0
-__attribute__((amdgpu_waves_per_eu(TENOAA_ADJ_WAVES_PER_EU)))
-#endif
-void sweep_vjp_kernel(AdjointArgs A) {
-  constexpr int G = ORDER / 2;
-  constexpr int W = ORDER;
-  constexpr int NV = NDIM + 2;
-  constexpr int NT = (NDIM > 1) ? NDIM - 1 : 1;
-  constexpr int NC = TN + W - 1;
-  constexpr int NCT = TT * NC;
-  constexpr int NTH = TT * TN;
-  constexpr int AX_A = (DIR == 0) ? 1 : 0;
-  constexpr int AX_B = (DIR == 2) ? 1 : 2;
-  using Fr = Frame<NDIM, DIR>;
-
-  // forward per-cell records (as in the forward sweep)
-  __shared__ double2 sWF[NV][NCT];
-  __shared__ double sUn[NCT], sC[NCT], sSr[NCT], sH[NCT];
-  __shared__ double sUt[NT][NCT];
-  // adjoint accumulators per tile cell: conserved state, physical flux,
-  // velocity (local slots: 0 normal, 1.. tangential), sound speed, enthalpy, sqrt(rho)
-  __shared__ double aW[NV][NCT], aF[NV][NCT], aU[NDIM][NCT], aC[NCT], aH[NCT], aS[NCT];
-  // derivative weights of the frozen reconstructions, [row][window position]
-  __shared__ double sWT[NROW * W];
-  for (int e = threadIdx.x; e < NROW * W; e += NTH) sWT[e] = weight_entry<ORDER>(e / W, e % W);
-
-  const int64_t nN = A.n[DIR];
-  const int64_t nA = A.n[AX_A];
-  const int64_t stride[3] = {1, A.n[0], A.n[0] * A.n[1]};
-  const int64_t ncell = A.n[0] * A.n[1] * A.n[2];
-  const int64_t f0 = (int64_t)blockIdx.x * TN;
-  const int64_t t0 = (int64_t)blockIdx.y * TT;
-  const int64_t bcoord = blockIdx.z;
-  const double gam = A.gamma;
-  const double gm1 = gam - 1.0;
-
-  // ghost mapping of tile cell ct, as in the forward sweep: the source cell
-  // along the normal, the boundary kind that makes it a ghost (-1 for a
-  // domain cell, a periodic or outflow copy, or a cell beyond the G ghost
-  // layers that no face reads), the side and the ghost layer 1..G
-  auto map_cell = [&](int ct, int64_t& t, int64_t& l, int& gbc, int& side, int64_t& layer) {
-    int tt, nn;
-    if (DIR == 0) {
-      tt = ct / NC;
-      nn = ct % NC;
-    } else {
-      tt = ct % TT;
-      nn = ct / TT;
-    }
-    t = t0 + tt;
-    l = f0 - G + nn;
-    gbc = -1;
-    side = (l < 0) ? 0 : 1;
-    layer = (l < 0) ? -l : l - nN + 1;
-    if (l < 0 || l >= nN) {
-      const int bc = (l < 0) ? A.bc_lo : A.bc_hi;
-      if (bc == TENOAA_BC_PERIODIC) {
-        l = ((l % nN) + nN) % nN;
-      } else if (bc == TENOAA_BC_OUTFLOW || layer > G) {
-        l = (l < 0) ? 0 : nN - 1;
-      } else {
-        l = (l < 0) ? -l - 1 : 2 * nN - 1 - l;
-        gbc = bc;
-      }
-      if (l < 0) l = 0;
-      if (l >= nN) l = nN - 1;
-    }
-  };
-  // boundary values of pencil t's cell of the face plane on side `side`
-  const int64_t plane = nA * A.n[AX_B];
-  auto face_vals = [&](int side, int64_t t) { return A.bcv[side] + t + nA * bcoord; };
-
-  for (int ct = threadIdx.x; ct < NCT; ct += NTH) {
-    int64_t t, l, layer;
-    int gbc, side;
-    map_cell(ct, t, l, gbc, side, layer);
-    if (t >= nA) t = nA - 1;
-    const int64_t off = l * stride[DIR] + t * stride[AX_A] + bcoord * stride[AX_B];
-    double Wc[NV];
-    unroll<NV>([&](auto c) { Wc[c] = A.U[c * ncell + off]; });
-    if (gbc == TENOAA_BC_SYMMETRY) {
-      Wc[1 + DIR] = -Wc[1 + DIR];
-    } else if (gbc == TENOAA_BC_NOSLIP) {
-      unroll<NDIM>([&](auto k) { Wc[1 + k] = -Wc[1 + k]; });
-    } else if constexpr (GENERAL) {
-      if (gbc == TENOAA_BC_DIRICHLET) {
-        dirichlet_ghost<NDIM>(Wc, face_vals(side, t), plane, gm1);
-      } else if (gbc == TENOAA_BC_INFLOW) {
-        inflow_ghost<NDIM>(Wc, face_vals(side, t) + (layer - 1) * NV * plane, plane, gm1);
-      }
-    }
-    // the same arithmetic as the forward sweep, so that the frozen splitting
-    // speeds are attained by the same cells
-    const double rho = Wc[0];
-    const double ir = div_rn(1.0, rho);
-    double u[NDIM];
-    double q2 = 0.0;
-    unroll<NDIM>([&](auto k) {
-      u[k] = Wc[1 + k] * ir;
-      q2 = (k == 0) ? u[0] * u[0] : q2 + u[k] * u[k];
-    });
-    const double E = Wc[NV - 1];
-    const double p = gm1 * (E - (0.5 * rho) * q2);
-    const double un = u[DIR];
-    sWF[0][ct] = make_double2(rho, Wc[1 + DIR]);
-    unroll<NDIM>([&](auto k) {
-      constexpr int slot = Fr::slot_of_axis(decltype(k)::value);
-      sWF[1 + slot][ct] = make_double2(Wc[1 + k], (k == DIR) ? Wc[1 + k] * un + p : Wc[1 + k] * un);
-      if constexpr (slot > 0) sUt[slot - 1][ct] = u[k];
-    });
-    sWF[NV - 1][ct] = make_double2(E, (E + p) * un);
-    sUn[ct] = un;
-    sC[ct] = sqrt_rn((gam * p) * ir);
-    sSr[ct] = sqrt_rn(rho);
-    sH[ct] = (E + p) * ir;
-    unroll<NV>([&](auto c) {
-      aW[c][ct] = 0.0;
-      aF[c][ct] = 0.0;
-    });
-    unroll<NDIM>([&](auto k) { aU[k][ct] = 0.0; });
-    aC[ct] = 0.0;
-    aH[ct] = 0.0;
-    aS[ct] = 0.0;
-  }
-  __syncthreads();
-
-  int tt, fn;
-  if (DIR == 0) {
-    tt = threadIdx.x / TN;
-    fn = threadIdx.x % TN;
-  } else {
-    tt = threadIdx.x % TT;
-    fn = threadIdx.x / TT;
-  }
-  const int64_t f = f0 + fn;
-  const int64_t t = t0 + tt;
-  const bool active = (f < A.nf) && (t < nA);
-  const int lbase = (DIR == 0) ? tt * NC + fn : fn * TT + tt;
-  constexpr int LSTEP = (DIR == 0) ? 1 : TT;
-  const int ia = lbase + (G - 1) * LSTEP, ib = lbase + G * LSTEP;
-
-  int64_t flin = 0;
-  {
-    int64_t m[3] = {A.n[0], A.n[1], A.n[2]};
-    m[DIR] = A.nf;
-    const int64_t fstr[3] = {1, m[0], m[0] * m[1]};
-    flin = f * fstr[DIR] + t * fstr[AX_A] + bcoord * fstr[AX_B];
-  }
-  if (active) {
-    // seed of the face flux: dU_i = -(F_{i+1} - F_i)/dx gives
-    // Fbar_f = (R_f - R_{f-1}) / dx over the cells that exist
-    double Fb[NV];  // local frame
-    {
-      const bool periodic = A.bc_lo == TENOAA_BC_PERIODIC;
-      const int64_t base = t * stride[AX_A] + bcoord * stride[AX_B];
-      const bool hasR = f < nN;
-      const bool hasL = f >= 1 || periodic;
-      const int64_t cR = f;
-      const int64_t cL = (f >= 1) ? f - 1 : nN - 1;
-      unroll<NV>([&](auto c) {
-        double r = hasR ? A.R[c * ncell + base + cR * stride[DIR]] : 0.0;
-        double lft = hasL ? A.R[c * ncell + base + cL * stride[DIR]] : 0.0;
-        const double v = (r - lft) / A.dx;
-        int slot;
-        if (c == 0) slot = 0;
-        else if (c == NV - 1) slot = NV - 1;
-        else slot = 1 + Fr::slot_of_axis(c - 1);
-        Fb[slot] = v;
-      });
-    }
-
-    // positivity limiter with its factor frozen: F = F_LF + theta (F_H - F_LF),
-    // F_LF = (F_a + F_b - a_L (W_b - W_a)) / 2 with a_L = max(|u_n| + c) of the
-    // two cells (that cell frozen); F_H continues below with seed theta Fbar
-    if (A.theta) {
-      const double th = A.theta[flin];
-      if (th < 1.0) {
-        const double sA = fabs(sUn[ia]) + sC[ia], sB = fabs(sUn[ib]) + sC[ib];
-        const bool onA = sA >= sB;
-        const double aL = onA ? sA : sB;
-        double aLb = 0.0;
-        unroll<NV>([&](auto c) {
-          const double flb = (1.0 - th) * Fb[c];
-          const double2 wa = sWF[c][ia], wb = sWF[c][ib];
-          lds_add(&aF[c][ia], 0.5 * flb);
-          lds_add(&aF[c][ib], 0.5 * flb);
-          lds_add(&aW[c][ia], (0.5 * aL) * flb);
-          lds_add(&aW[c][ib], -(0.5 * aL) * flb);
-          aLb -= 0.5 * flb * (wb.x - wa.x);
-          Fb[c] *= th;
-        });
-        const int li = onA ? ia : ib;
-        lds_add(&aU[0][li], (sUn[li] < 0.0 ? -1.0 : 1.0) * aLb);
-        lds_add(&aC[li], aLb);
-      }
-    }
-
-    // ---- forward recompute: Roe average and eigenvectors
-    const double sa = sSr[ia], sb = sSr[ib];
-    const double den = sa + sb;
-    const double iden = div_rn(1.0, den);
-    const double un = (sa * sUn[ia] + sb * sUn[ib]) * iden;
-    double ut[NT];
-    unroll<NDIM - 1>([&](auto k) { ut[k] = (sa * sUt[k][ia] + sb * sUt[k][ib]) * iden; });
-    double q2 = 0.0;
-    unroll<NDIM>([&](auto a) {
-      constexpr int slot = Fr::slot_of_axis(decltype(a)::value);
-      double ua;
-      if constexpr (slot == 0) ua = un;
-      else ua = ut[slot - 1];
-      q2 = (a == 0) ? ua * ua : q2 + ua * ua;
-    });
-    const double Hr = (sa * sH[ia] + sb * sH[ib]) * iden;
-    const double qq = 0.5 * q2;
-    const double c2 = gm1 * (Hr - qq);
-    const double cr = sqrt_rn(c2);
-    const double b1 = div_rn(gm1, c2);
-    const double b2 = b1 * qq;
-    const double ic = div_rn(1.0, cr);
-    const double unc = un * ic;
-
-    // splitting speeds and the cells attaining them
-    double am = -1.0, a0 = -1.0, ap = -1.0;
-    int jm = 0, j0 = 0, jp = 0;
-    unroll<W>([&](auto j) {
-      const int li = lbase + j * LSTEP;
-      const double u = sUn[li], c = sC[li];
-      if (A.splitting != TENOAA_RUSANOV) {  // LLF, also the Roe flux's fallback
-        const double lm = fabs(u - c), l0 = fabs(u), lp = fabs(u + c);
-        if (lm > am) { am = lm; jm = j; }
-        if (l0 > a0) { a0 = l0; j0 = j; }
-        if (lp > ap) { ap = lp; jp = j; }
-      } else {
-        const double lr = fabs(u) + c;
-        if (lr > a0) { a0 = lr; j0 = j; }
-      }
-    });
-    if (A.splitting == TENOAA_RUSANOV) {
-      am = ap = a0;
-      jm = jp = j0;
-    }
-
-    // ---- reverse pass
-    double un_b = 0.0, Hr_b = 0.0, qq_b = 0.0, cr_b = 0.0, b1_b = 0.0, b2_b = 0.0, unc_b = 0.0, ic_b = 0.0;
-    double ut_b[NT];
-    unroll<NT>([&](auto k) { ut_b[k] = 0.0; });
-
-    // back-projection F = sum_s R[:, s] fh_s: adjoints of fh_s and of R's entries
-    double fhb[NV];
-    unroll<NV>([&](auto ss) {
-      constexpr int s = decltype(ss)::value;
-      constexpr bool shear = (s >= 2 && s <= NV - 2);
-      const double fh = A.fh[(int64_t)s * A.nft + flin];
-      if constexpr (!shear) {
-        const double r1 = (s == 0) ? un - cr : (s == 1 ? un : un + cr);
-        const double re = (s == 0) ? Hr - un * cr : (s == 1 ? qq : Hr + un * cr);
-        double acc = Fb[0];
-        acc = fma(r1, Fb[1], acc);
-        unroll<NDIM - 1>([&](auto k) { acc = fma(ut[k], Fb[2 + k], acc); });
-        fhb[s] = fma(re, Fb[NV - 1], acc);
-        const double r1b = Fb[1] * fh, reb = Fb[NV - 1] * fh;
-        unroll<NDIM - 1>([&](auto k) { ut_b[k] += Fb[2 + k] * fh; });
-        if constexpr (s == 0) {
-          un_b += r1b - cr * reb;
-          cr_b += -r1b - un * reb;
-          Hr_b += reb;
-        } else if constexpr (s == 1) {
-          un_b += r1b;
-          qq_b += reb;
-        } else {
-          un_b += r1b + cr * reb;
-          cr_b += r1b + un * reb;
-          Hr_b += reb;
-        }
-      } else {
-        fhb[s] = fma(ut[s - 2], Fb[NV - 1], Fb[s]);
-        ut_b[s - 2] += Fb[NV - 1] * fh;
-      }
-    });
-
-    // left eigenvector rows: full rows for the acoustic and entropy fields
-    // (local slots 0, 1, NV-1 -> rows 0, 1, 2 here), -u_t + e_s for the shear fields
-    double L[3][NV];
-    unroll<2>([&](auto side) {
-      constexpr int r = side == 0 ? 0 : 2;
-      const double sg = side == 0 ? 1.0 : -1.0;
-      L[r][0] = 0.5 * (b2 + sg * unc);
-      L[r][1] = 0.5 * (-b1 * un - sg * ic);
-      unroll<NDIM - 1>([&](auto k) { L[r][2 + k] = 0.5 * (-b1 * ut[k]); });
-      L[r][NV - 1] = 0.5 * b1;
-    });
-    L[1][0] = 1.0 - b2;
-    L[1][1] = b1 * un;
-    unroll<NDIM - 1>([&](auto k) { L[1][2 + k] = b1 * ut[k]; });
-    L[1][NV - 1] = -b1;
-    // frozen reconstructions: row of the weight table per field and side.
-    // The Roe flux reconstructs the unsplit characteristic flux g from one
-    // side only where the field's eigenvalue keeps one sign at the face; the
-    // other side's byte is then 0 (no real decision has it)
-    int rowp[NV], rowm[NV];
-    bool one_side[NV];
-    unroll<NV>([&](auto ss) {
-      constexpr int s = decltype(ss)::value;
-      const uint8_t bp = A.flags[(int64_t)(2 * s) * A.nft + flin];
-      const uint8_t bm = A.flags[(int64_t)(2 * s + 1) * A.nft + flin];
-      rowp[s] = weight_row<ORDER>(bp);
-      rowm[s] = weight_row<ORDER>(bm);
-      one_side[s] = GENERAL && A.splitting == TENOAA_ROE && (bp == 0 || bm == 0);
-    });
-    double Lb[3][NV], Lbs[NT];
-    unroll<3>([&](auto r) { unroll<NV>([&](auto c) { Lb[r][c] = 0.0; }); });
-    unroll<NT>([&](auto k) { Lbs[k] = 0.0; });
-    double am_b = 0.0, a0_b = 0.0, ap_b = 0.0;
-
-    unroll<W>([&](auto jj) {
-      constexpr int j = decltype(jj)::value;
-      const int li = lbase + j * LSTEP;
-      double2 w[NV];
-      unroll<NV>([&](auto c) { w[c] = sWF[c][li]; });
-      double vb[NV], gb[NV];
-      unroll<NV>([&](auto ss) {
-        constexpr int s = decltype(ss)::value;
-        constexpr bool shear = (s >= 2 && s <= NV - 2);
-        constexpr int r = (s == 0) ? 0 : (s == 1 ? 1 : 2);
-        double v, g;
-        if constexpr (!shear) {
-          v = L[r][0] * w[0].x;
-          g = L[r][0] * w[0].y;
-          unroll<NV - 1>([&](auto cc) {
-            v = fma(L[r][cc + 1], w[cc + 1].x, v);
-            g = fma(L[r][cc + 1], w[cc + 1].y, g);
-          });
-        } else {
-          v = fma(-ut[s - 2], w[0].x, w[s].x);
-          g = fma(-ut[s - 2], w[0].y, w[s].y);
-        }
-        const double cp = sWT[rowp[s] * W + j] * fhb[s];
-        const double cm = sWT[rowm[s] * W + (W - 1 - j)] * fhb[s];
-        const double alpha = (s == 0) ? am : (s == NV - 1 ? ap : a0);
-        const double d = cp - cm;
-        // split: f+- = (g +- alpha v) / 2; one-sided Roe: f = g (the unused side's row is zero)
-        vb[s] = one_side[s] ? 0.0 : (0.5 * alpha) * d;
-        gb[s] = one_side[s] ? cp + cm : 0.5 * (cp + cm);
-        const double ab = one_side[s] ? 0.0 : (0.5 * v) * d;
-        if constexpr (s == 0) am_b += ab;
-        else if constexpr (s == NV - 1) ap_b += ab;
-        else a0_b += ab;
-        if constexpr (!shear) {
-          unroll<NV>([&](auto c) { Lb[r][c] = fma(vb[s], w[c].x, fma(gb[s], w[c].y, Lb[r][c])); });
-        } else {
-          Lbs[s - 2] = fma(vb[s], w[0].x, fma(gb[s], w[0].y, Lbs[s - 2]));
-        }
-      });
-      // adjoints of this cell's conserved state and flux: L^T (vb, gb)
-      unroll<NV>([&](auto cc) {
-        constexpr int c = decltype(cc)::value;
-        double sw = L[0][c] * vb[0] + L[1][c] * vb[1] + L[2][c] * vb[NV - 1];
-        double sf = L[0][c] * gb[0] + L[1][c] * gb[1] + L[2][c] * gb[NV - 1];
-        if constexpr (c == 0) {
-          unroll<NT>([&](auto k) {
-            if constexpr (NDIM > 1) {
-              sw = fma(-ut[k], vb[2 + k], sw);
-              sf = fma(-ut[k], gb[2 + k], sf);
-            }
-          });
-        } else if constexpr (c >= 2 && c <= NV - 2) {
-          sw += vb[c];
-          sf += gb[c];
-        }
-        lds_add(&aW[c][li], sw);
-        lds_add(&aF[c][li], sf);
-      });
-      unroll<3>([&](auto r) { unroll<NV>([&](auto c) { pin(Lb[r][c]); }); });
-      unroll<NT>([&](auto k) { pin(Lbs[k]); });
-      pin(am_b);
-      pin(a0_b);
-      pin(ap_b);
-      __builtin_amdgcn_sched_barrier(0);
-    });
-
-    // splitting speeds: frozen argmax cells and signs
-    if (A.splitting != TENOAA_RUSANOV) {
-      {
-        const int li = lbase + jm * LSTEP;
-        const double sg = (sUn[li] - sC[li]) < 0.0 ? -1.0 : 1.0;
-        lds_add(&aU[0][li], sg * am_b);
-        lds_add(&aC[li], -sg * am_b);
-      }
-      {
-        const int li = lbase + j0 * LSTEP;
-        const double sg = sUn[li] < 0.0 ? -1.0 : 1.0;
-        lds_add(&aU[0][li], sg * a0_b);
-      }
-      {
-        const int li = lbase + jp * LSTEP;
-        const double sg = (sUn[li] + sC[li]) < 0.0 ? -1.0 : 1.0;
-        lds_add(&aU[0][li], sg * ap_b);
-        lds_add(&aC[li], sg * ap_b);
-      }
-    } else {
-      const int li = lbase + j0 * LSTEP;
-      const double sg = sUn[li] < 0.0 ? -1.0 : 1.0;
-      const double tot = (am_b + a0_b) + ap_b;
-      lds_add(&aU[0][li], sg * tot);
-      lds_add(&aC[li], tot);
-    }
-
-    // adjoints of the L entries
-    unroll<2>([&](auto side) {
-      constexpr int r = side == 0 ? 0 : 2;
-      const double sgn = side == 0 ? 1.0 : -1.0;
-      b2_b += 0.5 * Lb[r][0];
-      unc_b += 0.5 * sgn * Lb[r][0];
-      b1_b += -0.5 * un * Lb[r][1];
-      un_b += -0.5 * b1 * Lb[r][1];
-      ic_b += -0.5 * sgn * Lb[r][1];
-      unroll<NDIM - 1>([&](auto k) {
-        b1_b += -0.5 * ut[k] * Lb[r][2 + k];
-        ut_b[k] += -0.5 * b1 * Lb[r][2 + k];
-      });
-      b1_b += 0.5 * Lb[r][NV - 1];
-    });
-    b2_b -= Lb[1][0];
-    b1_b += un * Lb[1][1];
-    un_b += b1 * Lb[1][1];
-    unroll<NDIM - 1>([&](auto k) {
-      b1_b += ut[k] * Lb[1][2 + k];
-      ut_b[k] += b1 * Lb[1][2 + k];
-    });
-    b1_b -= Lb[1][NV - 1];
-    unroll<NDIM - 1>([&](auto k) { ut_b[k] -= Lbs[k]; });
-
-    // ---- Roe average and eigen-system parameters
-    un_b += unc_b / cr;
-    cr_b -= unc_b * unc / cr;
-    cr_b -= ic_b * ic * ic;
-    b1_b += b2_b * qq;
-    qq_b += b2_b * b1;
-    double c2_b = -b1_b * b1 / c2;
-    c2_b += cr_b / (2.0 * cr);
-    Hr_b += gm1 * c2_b;
-    qq_b -= gm1 * c2_b;
-    // qq = |u~|^2 / 2
-    un_b += qq_b * un;
-    unroll<NDIM - 1>([&](auto k) { ut_b[k] += qq_b * ut[k]; });
-    // u~ = (sa ua + sb ub) / den, H~ likewise
-    double sa_b = 0.0, sb_b = 0.0;
-    {
-      const double wa = sa / den, wb = sb / den;
-      lds_add(&aU[0][ia], un_b * wa);
-      lds_add(&aU[0][ib], un_b * wb);
-      sa_b += un_b * (sUn[ia] - un) / den;
-      sb_b += un_b * (sUn[ib] - un) / den;
-      unroll<NDIM - 1>([&](auto k) {
-        lds_add(&aU[1 + k][ia], ut_b[k] * wa);
-        lds_add(&aU[1 + k][ib], ut_b[k] * wb);
-        sa_b += ut_b[k] * (sUt[k][ia] - ut[k]) / den;
-        sb_b += ut_b[k] * (sUt[k][ib] - ut[k]) / den;
-      });
-      lds_add(&aH[ia], Hr_b * wa);
-      lds_add(&aH[ib], Hr_b * wb);
-      sa_b += Hr_b * (sH[ia] - Hr) / den;
-      sb_b += Hr_b * (sH[ib] - Hr) / den;
-      lds_add(&aS[ia], sa_b);
-      lds_add(&aS[ib], sb_b);
-    }
-  }
-  __syncthreads();
-
-  // ---- cell-level reverse pass and scatter to U_bar
-  for (int ct = threadIdx.x; ct < NCT; ct += NTH) {
-    int64_t tc, l, layer;
-    int gbc, side;
-    map_cell(ct, tc, l, gbc, side, layer);
-    if (tc >= nA || (GENERAL && gbc == TENOAA_BC_INFLOW)) continue;  // an inflow ghost does not depend on U
-    const double2 w0 = sWF[0][ct];
-    const double rho = w0.x;
-    const double E = sWF[NV - 1][ct].x;
-    double m[NDIM], u[NDIM];  // local slots
-    unroll<NDIM>([&](auto k) {
-      m[k] = sWF[1 + k][ct].x;
-      u[k] = m[k] / rho;
-    });
-    double q2 = 0.0;
-    unroll<NDIM>([&](auto k) { q2 += u[k] * u[k]; });
-    const double p = gm1 * (E - (0.5 * rho) * q2);
-    const double c = sC[ct], H = sH[ct], sr = sSr[ct];
-    double rho_b = aW[0][ct], E_b = aW[NV - 1][ct];
-    double m_b[NDIM], u_b[NDIM];
-    unroll<NDIM>([&](auto k) {
-      m_b[k] = aW[1 + k][ct];
-      u_b[k] = aU[k][ct];
-    });
-    double p_b = 0.0;
-    // physical flux (Sec. 1): (m_n, m_n u_n + p, m_t u_n, (E + p) u_n)
-    {
-      const double F0b = aF[0][ct];
-      m_b[0] += F0b;
-      const double F1b = aF[1][ct];
-      m_b[0] += F1b * u[0];
-      u_b[0] += F1b * m[0];
-      p_b += F1b;
-      unroll<NDIM - 1>([&](auto k) {
-        const double Fkb = aF[2 + k][ct];
-        m_b[1 + k] += Fkb * u[0];
-        u_b[0] += Fkb * m[1 + k];
-      });
-      const double FEb = aF[NV - 1][ct];
-      E_b += FEb * u[0];
-      p_b += FEb * u[0];
-      u_b[0] += FEb * (E + p);
-    }
-    rho_b += aS[ct] / (2.0 * sr);
-    {
-      const double Hb = aH[ct];
-      E_b += Hb / rho;
-      p_b += Hb / rho;
-      rho_b -= Hb * H / rho;
-    }
-    {
-      const double tb = aC[ct] / (2.0 * c);  // c = sqrt(gam p / rho)
-      p_b += tb * gam / rho;
-      rho_b -= tb * (c * c) / rho;
-    }
-    E_b += gm1 * p_b;
-    rho_b -= gm1 * 0.5 * q2 * p_b;
-    const double q2_b = -gm1 * 0.5 * rho * p_b;
-    unroll<NDIM>([&](auto k) {
-      u_b[k] += 2.0 * u[k] * q2_b;
-      m_b[k] += u_b[k] / rho;
-      rho_b -= u_b[k] * u[k] / rho;
-    });
-    // back to axis order, undo the wall sign flips, add to the source cell
-    double Ub[NV];
-    Ub[0] = rho_b;
-    Ub[NV - 1] = E_b;
-    unroll<NDIM>([&](auto a) { Ub[1 + a] = m_b[Fr::slot_of_axis(decltype(a)::value)]; });
-    if (gbc == TENOAA_BC_SYMMETRY) Ub[1 + DIR] = -Ub[1 + DIR];
-    if (gbc == TENOAA_BC_NOSLIP) unroll<NDIM>([&](auto k) { Ub[1 + k] = -Ub[1 + k]; });
-    const int64_t off = l * stride[DIR] + tc * stride[AX_A] + bcoord * stride[AX_B];
-    if (GENERAL && gbc == TENOAA_BC_DIRICHLET) {
-      // through the ghost rule (rho, u, p)_g = 2 (rho, u, p)_face - (rho, u, p)_m
-      // back to the mirror cell m: ghost conserved -> ghost primitives, the
-      // reflection (-1), mirror primitives -> mirror conserved
-      double Wm[NV];
-      unroll<NV>([&](auto cc) { Wm[cc] = A.U[cc * ncell + off]; });
-      const double* fv = face_vals(side, tc);
-      const double rm = Wm[0];
-      double um[NDIM], q2m = 0.0;
-      unroll<NDIM>([&](auto k) {
-        um[k] = Wm[1 + k] / rm;
-        q2m += um[k] * um[k];
-      });
-      const double rg = 2.0 * fv[0] - rm;
-      double ug[NDIM], qg = 0.0;
-      unroll<NDIM>([&](auto k) {
-        ug[k] = 2.0 * fv[(1 + k) * plane] - um[k];
-        qg += ug[k] * ug[k];
-      });
-      double rg_b = Ub[0] + Ub[NV - 1] * (0.5 * qg);
-      unroll<NDIM>([&](auto k) { rg_b += Ub[1 + k] * ug[k]; });
-      const double pm_b = -Ub[NV - 1] / gm1;
-      double Um[NV];
-      Um[NV - 1] = gm1 * pm_b;
-      Um[0] = -rg_b + gm1 * 0.5 * q2m * pm_b;
-      unroll<NDIM>([&](auto k) {
-        const double um_b = -(Ub[1 + k] * rg + Ub[NV - 1] * rg * ug[k]);
-        Um[1 + k] = um_b / rm - gm1 * um[k] * pm_b;
-        Um[0] -= um_b * um[k] / rm;
-      });
-      unroll<NV>([&](auto cc) { Ub[cc] = Um[cc]; });
-    }
-    unroll<NV>([&](auto cc) { unsafeAtomicAdd(&A.Ubar[cc * ncell + off], Ub[cc]); });
-  }
-}
 
 __global__ void zero_kernel(double* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -701,34 +37,24 @@ __global__ void axpdtz_kernel(double* out, double a, const double* x, double c, 
 
 }  // namespace
 
-template <int ORDER, int NDIM, int DIR>
-static hipError_t launch_vjp_t(const AdjointArgs& a, hipStream_t st) {
-  // the Roe flux's one-sided fields and the ghost rules of prescribed sides
-  // in a variant of their own, which the common case does not carry
-  constexpr int TT = (NDIM == 1) ? 1 : (DIR == 0 ? TENOAA_ADJ_TT_X : TENOAA_ADJ_TT_YZ);
-  constexpr int TN = (DIR == 0) ? TENOAA_ADJ_TN_X : TENOAA_ADJ_TN_YZ;
-  constexpr int AX_A = (DIR == 0) ? 1 : 0;
-  constexpr int AX_B = (DIR == 2) ? 1 : 2;
-  dim3 grid((unsigned)((a.nf + TN - 1) / TN), (unsigned)((a.n[AX_A] + TT - 1) / TT), (unsigned)a.n[AX_B]);
-  if (a.splitting == TENOAA_ROE || a.bcv[0] || a.bcv[1])
-    hipLaunchKernelGGL((sweep_vjp_kernel<ORDER, NDIM, DIR, TT, TN, true>), grid, dim3(TT * TN), 0, st, a);
-  else
-    hipLaunchKernelGGL((sweep_vjp_kernel<ORDER, NDIM, DIR, TT, TN, false>), grid, dim3(TT * TN), 0, st, a);
-  return hipGetLastError();
-}
-
-template <int ORDER>
-static hipError_t launch_vjp_ord(int ndim, int dir, const AdjointArgs& a, hipStream_t st) {
-  if (ndim == 1) return launch_vjp_t<ORDER, 1, 0>(a, st);
-  if (ndim == 2) return dir == 0 ? launch_vjp_t<ORDER, 2, 0>(a, st) : launch_vjp_t<ORDER, 2, 1>(a, st);
-  if (dir == 0) return launch_vjp_t<ORDER, 3, 0>(a, st);
-  if (dir == 1) return launch_vjp_t<ORDER, 3, 1>(a, st);
-  return launch_vjp_t<ORDER, 3, 2>(a, st);
-}
-
 hipError_t launch_sweep_vjp(int order, int ndim, int dir, const AdjointArgs& a, hipStream_t st) {
-  if (order == 12) return launch_vjp_ord<12>(ndim, dir, a, st);
-  return order == 10 ? launch_vjp_ord<10>(ndim, dir, a, st) : launch_vjp_ord<8>(ndim, dir, a, st);
+  // the Roe flux's one-sided fields and the ghost rules of prescribed sides
+  // in a variant of their own (whole tiles only), which the common case does
+  // not carry.  The common case sends a remainder of at most SWEEP_TAIL_TN
+  // faces beyond the last whole 64-face tile of an x sweep (non-periodic
+  // directions have n + 1) to one-wave tail tiles; in y and z a 16-face
+  // tile more costs less than tail tiles, whose LDS per cell is as large
+  if (a.splitting == TENOAA_ROE || a.bcv[0] || a.bcv[1]) return launch_vjp_general(order, ndim, dir, a, st);
+  const int64_t rem = a.nf % TENOAA_ADJ_TN_X;
+  const bool tail = ndim > 1 && dir == 0 && rem > 0 && rem <= SWEEP_TAIL_TN;
+  const int64_t whole = tail ? a.nf - rem : a.nf;
+  if (whole > 0) {
+    const hipError_t e = launch_vjp_kind<false>(order, ndim, dir, a, whole, st);
+    if (e != hipSuccess || whole == a.nf) return e;
+  }
+  AdjointArgs t = a;
+  t.f_begin = whole;
+  return launch_vjp_tail(order, ndim, dir, t, st);
 }
 
 static unsigned grid_for(int64_t n) {

@@ -1,0 +1,29 @@
+// Reverse-sweep tail tiles of the common variant: the few faces of a 2D or 3D
+// x sweep beyond its last whole 64-face tile (one face per pencil when the
+// direction is non-periodic, n + 1 faces) in one-wave tiles of SWEEP_TAIL_TT
+// pencils x SWEEP_TAIL_TN faces.  A translation unit of its own so that it
+// compiles beside the whole-tile kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "tenoaa_internal.h"
+#include "tenoaa_vjp.h"
+
+namespace tenoaa {
+
+namespace {
+template <int ORDER>
+hipError_t tail_x(int ndim, const AdjointArgs& a, hipStream_t st) {
+  if (ndim == 2) return launch_vjp_tiles<ORDER, 2, 0, SWEEP_TAIL_TT, SWEEP_TAIL_TN, false>(a, a.nf, st);
+  return launch_vjp_tiles<ORDER, 3, 0, SWEEP_TAIL_TT, SWEEP_TAIL_TN, false>(a, a.nf, st);
+}
+}  // namespace
+
+hipError_t launch_vjp_tail(int order, int ndim, int dir, const AdjointArgs& a, hipStream_t st) {
+  if (ndim < 2 || dir != 0 || a.f_begin >= a.nf) return hipErrorInvalidValue;
+  if (order == 12) return tail_x<12>(ndim, a, st);
+  return order == 10 ? tail_x<10>(ndim, a, st) : tail_x<8>(ndim, a, st);
+}
+
+}  // namespace tenoaa

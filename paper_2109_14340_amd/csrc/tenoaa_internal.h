@@ -69,6 +69,7 @@ struct AdjointArgs {
   const double* theta;   // the sweep's limiter factors per face, or null (no limiter)
   const double* bcv[2];  // boundary values of the low/high side (Dirichlet, inflow), else null
   int64_t nft;
+  int64_t f_begin;       // first face along the direction of this launch's tiles
   int64_t n[3];
   int64_t nf;
   int bc_lo, bc_hi;
@@ -88,6 +89,11 @@ bool has_halo(const tenoaa_grid* g);
 void record_hip_error(hipError_t e);
 
 hipError_t launch_sweep_vjp(int order, int ndim, int dir, const AdjointArgs& a, hipStream_t st);
+// The reverse sweep's general variant (Roe flux, Dirichlet or inflow sides)
+// over all faces, and the common variant's one-wave tail tiles over the faces
+// [a.f_begin, a.nf) of a 2D or 3D x sweep.
+hipError_t launch_vjp_general(int order, int ndim, int dir, const AdjointArgs& a, hipStream_t st);
+hipError_t launch_vjp_tail(int order, int ndim, int dir, const AdjointArgs& a, hipStream_t st);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
 hipError_t launch_axpbypcz(double* out, double a, const double* x, double b, const double* y, double c,
                            const double* z, int64_t n, hipStream_t st);
