@@ -338,11 +338,17 @@ def main():
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
+    # events on the stream the library runs on (torch's current stream) between
+    # the steps give each step's duration; the wall clock gives the value
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        evs[k].record()
         one_step()
+    evs[-1].record()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    per_step = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps))
     if tenoaa.get_status(ws) != 0:
         raise RuntimeError("non-physical state during the benchmark")
     ms = el / args.steps * 1e3
@@ -383,6 +389,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 3),
+        "step_ms_median": round(per_step[len(per_step) // 2], 3),
+        "step_ms_min": round(per_step[0], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
