@@ -124,8 +124,8 @@ enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1, TENOAA_WS_RHS_VJP = 2, TENOAA_WS_S
  * and tenoaa_rhs reads set 0; with 1 every evaluation reads set 0.  A smaller
  * array than this is undefined behaviour (the library cannot check device
  * allocations).  Grids with such sides are rejected with
- * TENOAA_EUNSUPPORTED by the batch plan, and grids with halo sides by the
- * adjoint entry points.  The adjoint entry points differentiate a Dirichlet
+ * TENOAA_EUNSUPPORTED by the batch plan, and grids with halo sides by
+ * tenoaa_rhs_vjp and tenoaa_step_vjp (tenoaa_rhs_vjp_halo takes them).  The adjoint entry points differentiate a Dirichlet
  * ghost through its reflection rule (the face values are constants), take
  * inflow ghosts as constants, and read set s in stage s as the step does. */
 typedef struct {
@@ -186,6 +186,22 @@ int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gam
 int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
                    const double* dUdt_bar, double* U_bar, const uint8_t* flags, void* ws, size_t ws_bytes,
                    void* stream);
+
+/* tenoaa_rhs_vjp for a piece of a split grid: the grid may have halo sides,
+ * whose cells belong to neighbour pieces, so their share of the adjoint goes
+ * back to those pieces.  halo_bar (host array of 6 device pointers, entry
+ * 2 d + side) holds, for every halo side, order/2 x nvar x P doubles in the
+ * halo layout of one set (layer r = 1 .. order/2 outward, conserved planes);
+ * they are overwritten with (d dUdt / d halo)^T dUdt_bar, the adjoint of
+ * that side's halo cells, which the caller adds to the neighbour's U_bar at
+ * the same cells.  Entries of other sides are ignored.  U_bar covers the
+ * piece's own cells as in tenoaa_rhs_vjp; with the halos of a piece's
+ * neighbours summed in, the pieces give the whole grid's adjoint (up to the
+ * order of the atomic sums).  Same errors as tenoaa_rhs_vjp, and
+ * TENOAA_EINVAL for a null halo_bar or a halo side without its pointer. */
+int tenoaa_rhs_vjp_halo(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
+                        const double* dUdt_bar, double* U_bar, const uint8_t* flags, double* const* halo_bar,
+                        void* ws, size_t ws_bytes, void* stream);
 
 /* Vector-Jacobian product of one SSP-RK3 step with the time step frozen:
  * Un_bar (overwritten) = (d U^{n+1} / d U^n)^T Unp1_bar.  dt_dev is the device

@@ -303,7 +303,8 @@ int64_t flag_count(const tenoaa_grid* g) {
 
 // U_bar = (d(dU/dt)/dU)^T R at U, decisions frozen at U, from the decisions
 // and per-field fluxes that recorded_sweeps(U) left in stage slot `st`.
-int rhs_vjp(const Ctx& c, const double* U, const double* R, double* Ubar, int st, bool limit = false) {
+int rhs_vjp(const Ctx& c, const double* U, const double* R, double* Ubar, int st, bool limit = false,
+            double* const* halo_bar = nullptr) {
   const tenoaa_grid* g = c.g;
   const int nv = g->ndim + 2;
   const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
@@ -325,6 +326,8 @@ int rhs_vjp(const Ctx& c, const double* U, const double* R, double* Ubar, int st
     a.bc_hi = g->bc_hi[d];
     a.bcv[0] = face_values(g, c.s->order, d, 0, st);
     a.bcv[1] = face_values(g, c.s->order, d, 1, st);
+    for (int h = 0; h < 2; ++h)
+      a.hbar[h] = (halo_bar && (h ? g->bc_hi[d] : g->bc_lo[d]) == TENOAA_BC_HALO) ? halo_bar[2 * d + h] : nullptr;
     a.splitting = c.s->splitting;
     a.gamma = c.gamma;
     a.dx = g->dx[d];
@@ -446,6 +449,31 @@ int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double 
   if ((rc = begin(c))) return rc;
   if ((rc = recorded_sweeps(c, U, 0, flags))) return rc;
   return rhs_vjp(c, U, dUdt_bar, U_bar, 0);
+}
+
+int tenoaa_rhs_vjp_halo(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
+                        const double* dUdt_bar, double* U_bar, const uint8_t* flags, double* const* halo_bar,
+                        void* ws, size_t ws_bytes, void* stream) {
+  Ctx c;
+  int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_RHS_VJP);
+  if (rc) return rc;
+  if (!U || !dUdt_bar || !U_bar || U_bar == U || U_bar == dUdt_bar || !halo_bar) return TENOAA_EINVAL;
+  const int64_t G = scheme->order / 2, nv = grid->ndim + 2;
+  for (int d = 0; d < grid->ndim; ++d)
+    for (int h = 0; h < 2; ++h)
+      if ((h ? grid->bc_hi[d] : grid->bc_lo[d]) == TENOAA_BC_HALO && !halo_bar[2 * d + h]) return TENOAA_EINVAL;
+  if ((rc = begin(c))) return rc;
+  for (int d = 0; d < grid->ndim; ++d)
+    for (int h = 0; h < 2; ++h) {
+      if ((h ? grid->bc_hi[d] : grid->bc_lo[d]) != TENOAA_BC_HALO) continue;
+      int64_t plane = 1;
+      for (int k = 0; k < 3; ++k)
+        if (k != d) plane *= grid->n[k];
+      const hipError_t e = tenoaa::launch_zero(halo_bar[2 * d + h], G * nv * plane, c.st);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+  if ((rc = recorded_sweeps(c, U, 0, flags))) return rc;
+  return rhs_vjp(c, U, dUdt_bar, U_bar, 0, false, halo_bar);
 }
 
 int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* Un,

@@ -67,7 +67,8 @@ struct AdjointArgs {
   const uint8_t* flags;  // decisions of this direction's forward sweep at U, [nvar][2][nft]
   const double* fh;      // per-field fluxes of that sweep, [nvar][nft]
   const double* theta;   // the sweep's limiter factors per face, or null (no limiter)
-  const double* bcv[2];  // boundary values of the low/high side (Dirichlet, inflow), else null
+  const double* bcv[2];  // boundary values of the low/high side (Dirichlet, inflow, halo), else null
+  double* hbar[2];       // adjoints of the low/high halo cells (accumulated with atomics), or null
   int64_t nft;
   int64_t f_begin;       // first face along the direction of this launch's tiles
   int64_t n[3];

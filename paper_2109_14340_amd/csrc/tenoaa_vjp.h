@@ -189,6 +189,9 @@ void sweep_vjp_kernel(AdjointArgs A) {
         dirichlet_ghost<NDIM>(Wc, face_vals(side, t), plane, gm1);
       } else if (gbc == TENOAA_BC_INFLOW) {
         inflow_ghost<NDIM>(Wc, face_vals(side, t) + (layer - 1) * NV * plane, plane, gm1);
+      } else if (gbc == TENOAA_BC_HALO) {
+        const double* hv = face_vals(side, t) + (layer - 1) * NV * plane;
+        unroll<NV>([&](auto c) { Wc[c] = hv[c * plane]; });
       }
     }
     // the same arithmetic as the forward sweep, so that the frozen splitting
@@ -575,6 +578,7 @@ void sweep_vjp_kernel(AdjointArgs A) {
     int gbc, side;
     map_cell(ct, tc, l, gbc, side, layer);
     if (tc >= nA || (GENERAL && gbc == TENOAA_BC_INFLOW)) continue;  // an inflow ghost does not depend on U
+    if (GENERAL && gbc == TENOAA_BC_HALO && !A.hbar[side]) continue;
     const double2 w0 = sWF[0][ct];
     const double rho = w0.x;
     const double E = sWF[NV - 1][ct].x;
@@ -639,6 +643,12 @@ void sweep_vjp_kernel(AdjointArgs A) {
     unroll<NDIM>([&](auto a) { Ub[1 + a] = m_b[Fr::slot_of_axis(decltype(a)::value)]; });
     if (gbc == TENOAA_BC_SYMMETRY) Ub[1 + DIR] = -Ub[1 + DIR];
     if (gbc == TENOAA_BC_NOSLIP) unroll<NDIM>([&](auto k) { Ub[1 + k] = -Ub[1 + k]; });
+    if (GENERAL && gbc == TENOAA_BC_HALO) {
+      // a neighbour piece's cell: its adjoint goes back to that piece
+      double* hb = A.hbar[side] + tc + nA * bcoord + (layer - 1) * NV * plane;
+      unroll<NV>([&](auto cc) { unsafeAtomicAdd(&hb[cc * plane], Ub[cc]); });
+      continue;
+    }
     const int64_t off = l * stride[DIR] + tc * stride[AX_A] + bcoord * stride[AX_B];
     if (GENERAL && gbc == TENOAA_BC_DIRICHLET) {
       // through the ghost rule (rho, u, p)_g = 2 (rho, u, p)_face - (rho, u, p)_m

@@ -23,7 +23,7 @@ EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_step_f
            "tenoaa_get_status", "tenoaa_last_hip_error", "tenoaa_timing_enable", "tenoaa_timing_read",
            "tenoaa_batch_plan_create", "tenoaa_batch_offsets", "tenoaa_batch_run", "tenoaa_batch_get_status",
            "tenoaa_batch_plan_info", "tenoaa_batch_plan_destroy", "tenoaa_advect", "tenoaa_wave_speeds",
-           "tenoaa_rk3_stage"]
+           "tenoaa_rk3_stage", "tenoaa_rhs_vjp_halo"]
 KCLASS_SWEEP = (0, 1, 2)
 KCLASS_UPDATE, KCLASS_WAVESPEED = 3, 4
 KCLASS_VJP = (5, 6, 7)
@@ -96,6 +96,9 @@ def load():
                                     ctypes.c_int64, vp, vp]
         L.tenoaa_wave_speeds.restype = ctypes.c_int
         L.tenoaa_wave_speeds.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tenoaa_rhs_vjp_halo.restype = ctypes.c_int
+        L.tenoaa_rhs_vjp_halo.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, vp, ctypes.POINTER(vp), vp,
+                                          ctypes.c_size_t, vp]
         L.tenoaa_rk3_stage.restype = ctypes.c_int
         L.tenoaa_rk3_stage.argtypes = [gp, sp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp, vp, vp, vp,
                                        vp, ctypes.c_size_t, vp]
@@ -288,6 +291,34 @@ def rhs_vjp(grid, scheme, U, dUdt_bar, gamma=1.4, out=None, ws=None, flags=None)
                                _ptr(flags), _ptr(ws), ws.numel(), _stream())
     _check(rc, "tenoaa_rhs_vjp")
     return out
+
+
+def rhs_vjp_halo(grid, scheme, U, dUdt_bar, gamma=1.4, out=None, ws=None, flags=None):
+    """rhs_vjp for a piece of a split grid: returns (U_bar, {(d, side):
+    adjoint of that halo side's cells}), the latter shaped (order/2, nvar,
+    plane) like one set of its halo values, for the neighbour piece."""
+    import torch
+    _check_state(U, grid)
+    _check_state(dUdt_bar, grid)
+    _check_boundary_values(grid, scheme)
+    if out is None:
+        out = torch.empty_like(U)
+    if ws is None:
+        ws = workspace(grid, scheme, WS_RHS_VJP, U.device)
+    if flags is not None and (flags.dtype != torch.uint8 or flags.numel() < flags_size(grid)):
+        raise TenoaaError("flags must be uint8 with flags_size(grid) elements")
+    bars, ptrs = {}, (ctypes.c_void_p * 6)()
+    for d in range(grid.ndim):
+        for side, bc in ((0, grid.bc_lo[d]), (1, grid.bc_hi[d])):
+            if bc == BC_HALO:
+                t = torch.empty((scheme.order // 2, grid.ndim + 2, face_plane(grid, d)), dtype=torch.float64,
+                                device=U.device)
+                bars[(d, side)] = t
+                ptrs[2 * d + side] = t.data_ptr()
+    rc = load().tenoaa_rhs_vjp_halo(ctypes.byref(grid), ctypes.byref(scheme), gamma, _ptr(U), _ptr(dUdt_bar),
+                                    _ptr(out), _ptr(flags), ptrs, _ptr(ws), ws.numel(), _stream())
+    _check(rc, "tenoaa_rhs_vjp_halo")
+    return out, bars
 
 
 def step_vjp(grid, scheme, Un, dt_dev, Unp1_bar, gamma=1.4, out=None, ws=None, flags3=None):

@@ -233,6 +233,16 @@ def test_halo_and_stage_arguments_checked():
                             big, None) == -2
     assert L.tenoaa_step_vjp(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), vp(4096), None,
                              vp(1024), big, None) == -2
+    # the halo adjoint entry point: its halo buffers are required
+    bars = (vp * 6)()
+    assert L.tenoaa_rhs_vjp_halo(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), None, None,
+                                 vp(1024), big, None) == -1
+    bars[4] = 16384
+    assert L.tenoaa_rhs_vjp_halo(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), None, bars,
+                                 vp(1024), big, None) == -1  # the high z side has no buffer
+    bars[5] = 32768
+    assert L.tenoaa_rhs_vjp_halo(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), None, bars,
+                                 vp(1024), 16, None) == -5
     a, dt, un, us, out, ws = vp(256), vp(512), vp(1024), vp(2048), vp(4096), vp(8192)
     # wave speeds: null state or output, small workspace
     assert L.tenoaa_wave_speeds(ctypes.byref(g), ctypes.byref(s), 1.4, None, a, ws, need, None) == -1

@@ -172,3 +172,34 @@ def test_halo_layers_must_match_the_order():
     gp = _piece_grid(shape, d, 0, 8, _halos(U, d, 0, 8, 4))
     with pytest.raises(tenoaa.TenoaaError, match="ghost layers"):
         tenoaa.rhs(gp, tenoaa.make_scheme(10), _piece(U, d, 0, 8))
+
+
+@pytest.mark.parametrize("case", ["3d_z", "3d_x_ragged", "2d_y"])
+@pytest.mark.parametrize("splitting", [tenoaa.LLF, tenoaa.ROE])
+def test_pieces_rhs_vjp_sum_to_whole(case, splitting):
+    """The adjoint of a split right-hand side: each piece's tenoaa_rhs_vjp_halo
+    gives the adjoint of its own cells and of its halo cells; adding every
+    halo adjoint to the neighbour's cells it came from gives the whole grid's
+    tenoaa_rhs_vjp (up to the order of the atomic sums)."""
+    shape, d, cuts = CUTS[case]
+    order, G = 10, 5
+    U = torch.from_numpy(_state(shape)).cuda()
+    R = torch.randn(U.shape, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    sch = tenoaa.make_scheme(order, splitting, 0)
+    whole = tenoaa.rhs_vjp(tenoaa.make_grid(shape), sch, U, R)
+    n = shape[d]
+    ax = _ax(4, d)
+    assembled = torch.zeros_like(U)
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        gp = _piece_grid(shape, d, lo, hi, _halos(U, d, lo, hi, G))
+        own, bars = tenoaa.rhs_vjp_halo(gp, sch, _piece(U, d, lo, hi), _piece(R, d, lo, hi))
+        assembled.narrow(ax, lo, hi - lo).add_(own)
+        for side in (0, 1):
+            hb = bars[(d, side)]  # (G, nvar, plane)
+            for r in range(1, G + 1):
+                c = (lo - r) % n if side == 0 else (hi - 1 + r) % n
+                sl = assembled.narrow(ax, c, 1)
+                sl.add_(hb[r - 1].reshape(sl.shape))
+    err = float((assembled - whole).abs().max() / whole.abs().max())
+    print(case, splitting, "max rel difference of the assembled adjoint: %.2e" % err)
+    assert err <= 1e-13
