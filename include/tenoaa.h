@@ -141,8 +141,7 @@ typedef struct {
 /* order: 8 (TENO8-AA) or 10 (TENO10-AA), Sec. 4, or 12 (TENO12-AA: the
  * Sec. 3.1 framework with one more symmetric large stencil S6 = cells
  * i-5 .. i+6 tried before S5; the paper prints no optimised scheme for it, so
- * S6 uses the maximum-order (12th) reconstruction; not supported by the
- * batch plan); splitting: TENOAA_LLF,
+ * S6 uses the maximum-order (12th) reconstruction); splitting: TENOAA_LLF,
  * TENOAA_RUSANOV or TENOAA_ROE; positivity: 1 enables the flux limiter. */
 typedef struct {
   int32_t order;
@@ -297,8 +296,8 @@ typedef struct tenoaa_batch_plan tenoaa_batch_plan;
  * of the persistent kernel gives up after 20 s (the environment variable
  * TENOAA_BATCH_BARRIER_TIMEOUT_US, read here, sets another limit; tests use it
  * to exercise tenoaa_batch_get_status's TENOAA_ETIMEOUT).  Returns EINVAL
- * for bad arguments, EUNSUPPORTED for ndim != 2, a side with boundary or
- * halo values or order 12, EHIP on a HIP failure;
+ * for bad arguments, EUNSUPPORTED for ndim != 2 or a side with boundary or
+ * halo values, EHIP on a HIP failure;
  * *out is NULL unless 0 is returned. */
 int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const tenoaa_scheme* scheme, double gamma,
                              double cfl, int32_t nsteps, const char* tune_cache_path, tenoaa_batch_plan** out);

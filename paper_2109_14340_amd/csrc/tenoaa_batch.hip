@@ -361,9 +361,11 @@ using KernelFn = void (*)(BatchArgs);
 KernelFn pick_kernel(int order, bool limit, bool roe) {
   if (roe) {
     if (order == 8) return limit ? batch_kernel<8, true, true> : batch_kernel<8, false, true>;
+    if (order == 12) return limit ? batch_kernel<12, true, true> : batch_kernel<12, false, true>;
     return limit ? batch_kernel<10, true, true> : batch_kernel<10, false, true>;
   }
   if (order == 8) return limit ? batch_kernel<8, true, false> : batch_kernel<8, false, false>;
+  if (order == 12) return limit ? batch_kernel<12, true, false> : batch_kernel<12, false, false>;
   return limit ? batch_kernel<10, true, false> : batch_kernel<10, false, false>;
 }
 
@@ -690,7 +692,7 @@ int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const teno
   int64_t total = 0;
   for (int q = 0; q < nprob; ++q) {
     if (!tenoaa::grid_ok(&grids[q], scheme)) return TENOAA_EINVAL;
-    if (grids[q].ndim != 2 || tenoaa::has_boundary_values(&grids[q]) || scheme->order == 12) return TENOAA_EUNSUPPORTED;
+    if (grids[q].ndim != 2 || tenoaa::has_boundary_values(&grids[q])) return TENOAA_EUNSUPPORTED;
     if (grids[q].n[0] * grids[q].n[1] >= ((int64_t)1 << 31)) return TENOAA_EINVAL;
     total += 4 * grids[q].n[0] * grids[q].n[1];
     if (total > ((int64_t)1 << 40)) return TENOAA_EINVAL;

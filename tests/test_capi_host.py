@@ -148,8 +148,8 @@ def test_roe_flux_options():
 
 def test_teno12_options():
     """Order 12 (TENO12-AA) is a valid scheme, also for the adjoint entry
-    points (stopped here at the workspace check); the batch plan rejects it
-    before any device work."""
+    points (stopped here at the workspace check); the batch plan checks its
+    grids against order 12 (n >= 6) before any device work."""
     L = _lib()
     vp = ctypes.c_void_p
     g = tenoaa.make_grid((64, 48))
@@ -161,8 +161,9 @@ def test_teno12_options():
     assert L.tenoaa_step_vjp(ctypes.byref(g), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), vp(4096), None,
                              vp(1024), 16, None) == -5
     h = vp(None)
-    arr = (tenoaa.Grid * 1)(tenoaa.make_grid((64, 64), bc_lo=[1, 1]))
-    assert L.tenoaa_batch_plan_create(arr, 1, ctypes.byref(s), 1.4, 0.4, 2, None, ctypes.byref(h)) == -2
+    arr = (tenoaa.Grid * 1)(tenoaa.make_grid((64, 5), bc_lo=[1, 1]))
+    assert L.tenoaa_batch_plan_create(arr, 1, ctypes.byref(s), 1.4, 0.4, 2, None, ctypes.byref(h)) == -1
+    assert h.value is None
     assert L.tenoaa_advect(12, 11, 0.1, 0.01, 1, vp(256), None) == -1  # n < order
 
 

@@ -99,6 +99,18 @@ def test_batch_aa10_limiter_mixed_boundaries():
     _assert_same(plan, packed, dtb, ref, dtr)
 
 
+@pytest.mark.parametrize("splitting", [tenoaa.LLF, tenoaa.ROE])
+def test_batch_teno12_bitwise_equals_per_problem(splitting):
+    """TENO12-AA in the batched form (the S6 stencil), with the Roe flux too."""
+    sch = tenoaa.make_scheme(12, splitting, 0)
+    sizes = [(64, 64), (131, 67), (70, 150)]
+    grids, states = _problems(sizes)
+    plan, packed, dtb, st = _batched(grids, states, sch, 3)
+    assert st == [0] * len(grids)
+    ref, dtr = _per_problem(grids, states, sch, 3)
+    _assert_same(plan, packed, dtb, ref, dtr)
+
+
 def test_batch_rusanov_against_oracle():
     """Two small problems, two steps, compared with the oracle directly."""
     sch = tenoaa.make_scheme(8, tenoaa.RUSANOV, 0)
