@@ -4,10 +4,14 @@
  * The library evaluates the finite-difference right-hand side of the Euler
  * equations (arXiv 2109.14340, Sec. 1 for the equations and ideal-gas EOS,
  * Sec. 2 for the conservative flux-difference form) with the eight- or
- * ten-point TENO-AA reconstruction (Sec. 3 and 4) applied to Roe-averaged
- * characteristic fields with LLF or Rusanov flux splitting, optionally the
- * positivity-preserving flux limiter the paper applies in its extreme cases
- * (Sec. 5.3), and advances it with the SSP-RK3 scheme of Sec. 5.
+ * ten-point TENO-AA reconstruction (Sec. 3 and 4; also a twelve-point
+ * member of the same framework) applied to Roe-averaged characteristic
+ * fields with LLF or Rusanov flux splitting or the Roe flux with entropy fix
+ * (Sec. 5), optionally the positivity-preserving flux limiter the paper
+ * applies in its extreme cases (Sec. 5.3), and advances it with the SSP-RK3
+ * scheme of Sec. 5.  Added forms: vector-Jacobian products (the adjoint), a
+ * batched solver for many 2D grids, and the per-piece entry points of a grid
+ * split into one piece per GPU.
  *
  * Conventions shared by every entry point
  *  - Memory: every double/uint8 array argument is DEVICE memory on the
@@ -30,7 +34,8 @@
  *    0-1: large stencil chosen (0 none, 1 S3, 2 S4, 3 S5, or S6 of TENO12-AA
  *    when bit 2 is also set); bits 2-4: the cut-off deltas of the three
  *    small stencils when none was chosen; bits 5-7: [beta] - 7 of the
- *    adaptive C_T = 10^-[beta] (Sec. 3.4).
+ *    adaptive C_T = 10^-[beta] (Sec. 3.4).  With the Roe flux the byte of a
+ *    side that is not reconstructed is 0, which no decision produces.
  *  - Streams: `stream` is a hipStream_t passed as void*; NULL is the null
  *    stream.  Calls enqueue work and return without synchronising, except
  *    where stated.  Calls on distinct (stream, workspace) pairs are
