@@ -38,7 +38,7 @@ def _grids(shape, bc):
 
 
 @pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("order,splitting", [(10, tenoaa.LLF), (8, tenoaa.ROE)])
+@pytest.mark.parametrize("order,splitting", [(10, tenoaa.LLF), (8, tenoaa.ROE), (12, tenoaa.RUSANOV)])
 def test_rhs_with_tail_tiles(case, order, splitting):
     shape, bc = CASES[case]
     U = _state(shape)
@@ -73,17 +73,18 @@ def test_step_with_tail_tiles():
 
 
 @pytest.mark.parametrize("case", ["3d_r1_r1_r4", "2d_x_only"])
-def test_rhs_vjp_with_tail_tiles(case):
+@pytest.mark.parametrize("order", [10, 12])
+def test_rhs_vjp_with_tail_tiles(case, order):
     shape, bc = CASES[case]
     U = _state(shape)
     g_or, g_gpu = _grids(shape, bc)
     rng = np.random.default_rng(34)
     V = rng.standard_normal(U.shape) * np.abs(U).reshape(U.shape[0], -1).max(axis=1)[:, None, None, None]
     Wt = rng.standard_normal(U.shape)
-    _, flags, margins = oracle.rhs(g_or, U, order=10)
+    _, flags, margins = oracle.rhs(g_or, U, order=order)
     assert (margins <= 1e-12).sum() == 0
-    _, jv = oracle.rhs_jvp(g_or, U, V, flags, order=10)
-    jtw = tenoaa.to_numpy(tenoaa.rhs_vjp(g_gpu, tenoaa.make_scheme(10), torch.from_numpy(U).cuda(),
+    _, jv = oracle.rhs_jvp(g_or, U, V, flags, order=order)
+    jtw = tenoaa.to_numpy(tenoaa.rhs_vjp(g_gpu, tenoaa.make_scheme(order), torch.from_numpy(U).cuda(),
                                          torch.from_numpy(Wt).cuda()))
     lhs, rhs = float(np.sum(Wt * jv)), float(np.sum(jtw * V))
     scale = float(np.sum(np.abs(Wt * jv)))
