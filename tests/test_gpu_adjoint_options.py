@@ -258,3 +258,37 @@ def test_roe_step_replay():
     print("replayed decisions differing from the state's own (stage 1): %d" % int((flp != f[:nfl]).sum()))
     err = np.abs(Uc - U3).reshape(3, -1).max(axis=1) / np.abs(U3).reshape(3, -1).max(axis=1)
     assert err.max() <= 1e-13, err
+
+
+def test_trajectory_gradient_roe_limiter_dirichlet():
+    """adjoint.rk3_trajectory (checkpointed, autograd) with the Roe flux, the
+    limiter and prescribed sides: <grad, v> equals <w, J v> with J v chained
+    through the oracle's step JVPs of the same steps (each step's dt and
+    decisions from the oracle's own run of the trajectory)."""
+    from paper_2109_14340_amd import adjoint
+    n, nsteps = 64, 3
+    x = (np.arange(n) + 0.5) / n
+    U0 = inputs._as_layout(inputs.conserved_from_primitive(np.ones(n), [np.where(x < 0.5, -2.0, 2.0)],
+                                                           np.full(n, 0.1), 1.4), 1)
+    faces = _face_values(U0, (n,), [D], [D], 1.4, 1, seed=9, order=10)
+    g_or, g_gpu = _grids((n,), [D], [D], faces)
+    sch = tenoaa.make_scheme(10, tenoaa.ROE, 1)
+    # the oracle's trajectory with its decisions, dt and the chained JVP
+    V, Wt = _seeds(U0, 23)
+    U, jv, dts = U0, V, []
+    for _ in range(nsteps):
+        Un, dt, flags3, margins3 = oracle.step(g_or, U, order=10, splitting=tenoaa.ROE, positivity=1, cfl=0.4,
+                                               want_flags=True)
+        assert (margins3 <= 1e-12).sum() == 0
+        jv = oracle.step_jvp(g_or, U, jv, dt, flags3, order=10, splitting=tenoaa.ROE, positivity=1)
+        U = Un
+        dts.append(dt)
+    x0 = _dev(U0).requires_grad_(True)
+    UT = adjoint.rk3_trajectory(x0, g_gpu, sch, nsteps, checkpoint_every=2)
+    assert np.array_equal(UT.detach().cpu().numpy(), U)  # the same trajectory, bit for bit
+    (UT * _dev(Wt)).sum().backward()
+    grad = x0.grad.cpu().numpy()
+    lhs, rhs = float(np.sum(Wt * jv)), float(np.sum(grad * V))
+    scale = float(np.sum(np.abs(Wt * jv)))
+    print("trajectory <w,Jv> %.15e  <grad,v> %.15e  rel %.2e" % (lhs, rhs, abs(lhs - rhs) / scale))
+    assert abs(lhs - rhs) <= 1e-11 * scale
