@@ -75,6 +75,7 @@ struct BatchProblem {
   double dx[3];
   double rdx[3];      // 1 / dx, correctly rounded (host)
   int32_t bc_lo[2], bc_hi[2];
+  const double* bcv[2][2];  // Dirichlet/inflow values of side [d][low/high] (one set), else null
   int64_t u_off;      // state offset in the packed buffer (doubles)
   int64_t s_off;      // stage state offset
   int64_t f_off[2];   // face flux arrays
@@ -179,8 +180,6 @@ __device__ __forceinline__ void sweep_item(const BatchArgs& B, char* arena, int 
   A.splitting = B.splitting;
   A.pad = 0;
   A.gamma = B.gamma;
-  A.bcv[0] = nullptr;
-  A.bcv[1] = nullptr;
   A.mu = nullptr;
   A.status = B.status + p;
   const int64_t ntx = P.along[0] * P.across[0];
@@ -191,8 +190,32 @@ __device__ __forceinline__ void sweep_item(const BatchArgs& B, char* arena, int 
   A.nft = P.nft[dir];
   A.bc_lo = P.bc_lo[dir];
   A.bc_hi = P.bc_hi[dir];
+  A.bcv[0] = P.bcv[dir][0];
+  A.bcv[1] = P.bcv[dir][1];
   if (dir == 0) run_sweep_tile<ORDER, 0, LIMIT, ROE>(A, arena, P.tile[0], k, P.along[0], mu[0]);
   else run_sweep_tile<ORDER, 1, LIMIT, ROE>(A, arena, P.tile[1], k, P.along[1], mu[1]);
+}
+
+// The ghost cells next to the faces of a problem's sides with prescribed
+// values count in its CFL speeds (as in the single-grid step): for a cell W
+// at coordinates co on such a side, the ghost it makes (Dirichlet: W
+// reflected through the face values; inflow: the first prescribed layer).
+__device__ __forceinline__ void boundary_speeds(const BatchProblem& P, const int64_t (&co)[3], const double (&W)[4],
+                                                double gam, double (&amax)[2], bool& bad) {
+  unroll<2>([&](auto dd) {
+    constexpr int d = decltype(dd)::value;
+    unroll<2>([&](auto hh) {
+      constexpr int h = decltype(hh)::value;
+      const double* fv = P.bcv[d][h];
+      if (fv && co[d] == (h ? P.n[d] - 1 : 0)) {
+        const int64_t plane = P.n[1 - d];
+        double Wg[4] = {W[0], W[1], W[2], W[3]};
+        if ((h ? P.bc_hi[d] : P.bc_lo[d]) == TENOAA_BC_DIRICHLET) dirichlet_ghost<2>(Wg, fv + co[1 - d], plane, gam - 1.0);
+        else inflow_ghost<2>(Wg, fv + co[1 - d], plane, gam - 1.0);
+        cell_speeds<2>(Wg, gam, amax, bad);
+      }
+    });
+  });
 }
 
 template <int MODE>
@@ -233,7 +256,10 @@ __device__ __forceinline__ void update_item(const BatchArgs& B, char* arena, int
       const int64_t co[3] = {(int64_t)((uint32_t)idx - q * (uint32_t)P.n[0]), (int64_t)q, 0};
       double Wn[4];
       update_cell<2, MODE>(A, idx, co, dt, Wn);
-      if (speeds) cell_speeds<2>(Wn, B.gamma, amax, bad);
+      if (speeds) {
+        cell_speeds<2>(Wn, B.gamma, amax, bad);
+        boundary_speeds(P, co, Wn, B.gamma, amax, bad);
+      }
     }
   }
   if (speeds) {
@@ -254,6 +280,9 @@ __device__ __forceinline__ void speeds_item(const BatchArgs& B, char* arena, int
       double Wc[4];
       unroll<4>([&](auto c) { Wc[c] = U[c * ncell + idx]; });
       cell_speeds<2>(Wc, B.gamma, amax, bad);
+      const uint32_t q = (uint32_t)idx / (uint32_t)P.n[0];
+      const int64_t co[3] = {(int64_t)((uint32_t)idx - q * (uint32_t)P.n[0]), (int64_t)q, 0};
+      boundary_speeds(P, co, Wc, B.gamma, amax, bad);
     }
   }
   if (bad) atomicOr(B.status + p, 1);
@@ -437,6 +466,10 @@ hipError_t upload_table(tenoaa_batch_plan* P) {
       b.nft[d] = b.nf[d] * g.n[1 - d];
       b.bc_lo[d] = g.bc_lo[d];
       b.bc_hi[d] = g.bc_hi[d];
+      for (int h = 0; h < 2; ++h) {
+        const int bc = h ? g.bc_hi[d] : g.bc_lo[d];
+        b.bcv[d][h] = (bc == TENOAA_BC_DIRICHLET || bc == TENOAA_BC_INFLOW) ? g.bc_values[d][h] : nullptr;
+      }
       const int tt = cand_tt(d, b.tile[d]), tn = cand_tn(d, b.tile[d]);
       b.along[d] = (b.nf[d] + tn - 1) / tn;
       b.across[d] = (g.n[1 - d] + tt - 1) / tt;
@@ -692,7 +725,8 @@ int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const teno
   int64_t total = 0;
   for (int q = 0; q < nprob; ++q) {
     if (!tenoaa::grid_ok(&grids[q], scheme)) return TENOAA_EINVAL;
-    if (grids[q].ndim != 2 || tenoaa::has_boundary_values(&grids[q])) return TENOAA_EUNSUPPORTED;
+    if (grids[q].ndim != 2 || tenoaa::has_halo(&grids[q])) return TENOAA_EUNSUPPORTED;
+    if (tenoaa::has_boundary_values(&grids[q]) && grids[q].bc_sets != 1) return TENOAA_EUNSUPPORTED;
     if (grids[q].n[0] * grids[q].n[1] >= ((int64_t)1 << 31)) return TENOAA_EINVAL;
     total += 4 * grids[q].n[0] * grids[q].n[1];
     if (total > ((int64_t)1 << 40)) return TENOAA_EINVAL;

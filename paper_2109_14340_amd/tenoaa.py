@@ -419,10 +419,14 @@ def timing_read(kclass):
 
 class BatchPlan:
     """A tenoaa_batch_plan: nprob independent 2D grids (tenoaa Grid structs,
-    ndim 2) advanced together by `nsteps` SSP-RK3 steps per run."""
+    ndim 2) advanced together by `nsteps` SSP-RK3 steps per run.  Dirichlet
+    and inflow sides take one value set, used by every step."""
 
     def __init__(self, grids, scheme, nsteps, gamma=1.4, cfl=0.4, tune_cache=None):
         L = load()
+        for g in grids:
+            _check_boundary_values(g, scheme)
+        self._keep = [getattr(g, "_faces", {}) for g in grids]  # the boundary-value tensors stay alive
         self.nprob = len(grids)
         arr = (Grid * self.nprob)(*grids)
         self._grids = arr

@@ -96,7 +96,7 @@ def test_bad_call_arguments_rejected():
 
 def test_dirichlet_arguments_checked():
     """A Dirichlet or inflow side needs its value pointer and 1 or 3 value sets;
-    the batch plan rejects grids with such sides."""
+    the batch plan rejects three sets."""
     L = _lib()
     vp = ctypes.c_void_p
     s = tenoaa.make_scheme(8)
@@ -121,8 +121,9 @@ def test_dirichlet_arguments_checked():
                             16, None) == -5
     assert L.tenoaa_step_vjp(ctypes.byref(ok), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), vp(4096), None,
                              vp(1024), 16, None) == -5
+    # the batch plan takes one value set only (its steps reuse it)
     h = vp(None)
-    arr = (tenoaa.Grid * 1)(ok)
+    arr = (tenoaa.Grid * 1)(grid(sets=3))
     assert L.tenoaa_batch_plan_create(arr, 1, ctypes.byref(s), 1.4, 0.4, 2, None, ctypes.byref(h)) == -2
     assert h.value is None
 

@@ -111,6 +111,35 @@ def test_batch_teno12_bitwise_equals_per_problem(splitting):
     _assert_same(plan, packed, dtb, ref, dtr)
 
 
+@pytest.mark.parametrize("order", [8, 10])
+def test_batch_prescribed_boundaries_bitwise(order):
+    """Problems with Dirichlet and inflow sides (one value set for every step)
+    beside walls and outflow: batched states and dt equal per-problem steps,
+    whose CFL speeds include the ghost cells of those sides."""
+    from tests.test_gpu_dirichlet import _face_values, _smooth
+    D, I = tenoaa.BC_DIRICHLET, tenoaa.BC_INFLOW  # noqa: E741
+    sch = tenoaa.make_scheme(order, tenoaa.LLF, 1)
+    specs = [((64, 70), [D, tenoaa.BC_OUTFLOW], [I, D]), ((131, 67), [I, tenoaa.BC_NOSLIP], [D, I]),
+             ((96, 96), [tenoaa.BC_OUTFLOW, D], [tenoaa.BC_SYMMETRY, D])]
+    grids, states = [], []
+    for p, ((nx, ny), lo, hi) in enumerate(specs):
+        U = _smooth((nx, ny), 40 + p)  # Dirichlet reflections of it stay physical
+        faces = _face_values(U, (nx, ny), lo, hi, 1.4, 1, seed=40 + p, order=order)
+        if p == 1:
+            # a fast inflow through the low x side: its ghost cells set the problem's CFL speed
+            faces[(0, 0)][:, :, 1] = 2.5
+            g_or = oracle.make_grid((nx, ny), [1.0 / nx, 1.0 / ny], lo, hi, bc_values=faces)
+            g_walls = oracle.make_grid((nx, ny), [1.0 / nx, 1.0 / ny], [1, 1])
+            assert oracle.dt(g_or, 1.4, 0.4, U) < oracle.dt(g_walls, 1.4, 0.4, U)
+        grids.append(tenoaa.make_grid((nx, ny), bc_lo=lo, bc_hi=hi,
+                                      bc_values={k: torch.from_numpy(v).cuda() for k, v in faces.items()}))
+        states.append(U)
+    plan, packed, dtb, st = _batched(grids, states, sch, 3)
+    assert st == [0] * len(grids)
+    ref, dtr = _per_problem(grids, states, sch, 3)
+    _assert_same(plan, packed, dtb, ref, dtr)
+
+
 def test_batch_rusanov_against_oracle():
     """Two small problems, two steps, compared with the oracle directly."""
     sch = tenoaa.make_scheme(8, tenoaa.RUSANOV, 0)
