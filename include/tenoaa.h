@@ -129,9 +129,9 @@ enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1, TENOAA_WS_RHS_VJP = 2, TENOAA_WS_S
  * and tenoaa_rhs reads set 0; with 1 every evaluation reads set 0.  A smaller
  * array than this is undefined behaviour (the library cannot check device
  * allocations).  The batch plan takes Dirichlet and inflow sides with one
- * value set (used by every step of a run) and rejects other cases with
- * TENOAA_EUNSUPPORTED; tenoaa_rhs_vjp and tenoaa_step_vjp reject halo sides
- * (tenoaa_rhs_vjp_halo takes them).  The adjoint entry points differentiate a Dirichlet
+ * value set (used by every step of a run) and without the Roe flux, and
+ * rejects other cases with TENOAA_EUNSUPPORTED; tenoaa_rhs_vjp and
+ * tenoaa_step_vjp reject halo sides (tenoaa_rhs_vjp_halo takes them).  The adjoint entry points differentiate a Dirichlet
  * ghost through its reflection rule (the face values are constants), take
  * inflow ghosts as constants, and read set s in stage s as the step does. */
 typedef struct {
@@ -302,8 +302,8 @@ typedef struct tenoaa_batch_plan tenoaa_batch_plan;
  * of the persistent kernel gives up after 20 s (the environment variable
  * TENOAA_BATCH_BARRIER_TIMEOUT_US, read here, sets another limit; tests use it
  * to exercise tenoaa_batch_get_status's TENOAA_ETIMEOUT).  Returns EINVAL
- * for bad arguments, EUNSUPPORTED for ndim != 2, a halo side or three value
- * sets, EHIP on a HIP failure;
+ * for bad arguments, EUNSUPPORTED for ndim != 2, a halo side, three value
+ * sets, or prescribed sides with the Roe flux, EHIP on a HIP failure;
  * *out is NULL unless 0 is returned. */
 int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const tenoaa_scheme* scheme, double gamma,
                              double cfl, int32_t nsteps, const char* tune_cache_path, tenoaa_batch_plan** out);

@@ -160,7 +160,7 @@ __device__ __forceinline__ void run_sweep_tile(const SweepArgs& A, char* arena, 
   }
 }
 
-template <int ORDER, bool LIMIT, bool ROE>
+template <int ORDER, bool LIMIT, bool ROE, bool BV>
 __device__ __forceinline__ void sweep_item(const BatchArgs& B, char* arena, int p, int64_t k, int n, int stage) {
   const BatchProblem& P = B.probs[p];
   const double* in = (stage == 1 ? B.U + P.u_off : B.S + P.s_off);
@@ -190,8 +190,12 @@ __device__ __forceinline__ void sweep_item(const BatchArgs& B, char* arena, int 
   A.nft = P.nft[dir];
   A.bc_lo = P.bc_lo[dir];
   A.bc_hi = P.bc_hi[dir];
-  A.bcv[0] = P.bcv[dir][0];
-  A.bcv[1] = P.bcv[dir][1];
+  // (without prescribed sides the pointers stay null constants, and their
+  // ghost rules drop out of the staging)
+  if constexpr (BV) {
+    A.bcv[0] = P.bcv[dir][0];
+    A.bcv[1] = P.bcv[dir][1];
+  }
   if (dir == 0) run_sweep_tile<ORDER, 0, LIMIT, ROE>(A, arena, P.tile[0], k, P.along[0], mu[0]);
   else run_sweep_tile<ORDER, 1, LIMIT, ROE>(A, arena, P.tile[1], k, P.along[1], mu[1]);
 }
@@ -218,7 +222,7 @@ __device__ __forceinline__ void boundary_speeds(const BatchProblem& P, const int
   });
 }
 
-template <int MODE>
+template <int MODE, bool BV>
 __device__ __forceinline__ void update_item(const BatchArgs& B, char* arena, int p, int64_t k, int n) {
   const BatchProblem& P = B.probs[p];
   double dt, mu[3];
@@ -246,6 +250,7 @@ __device__ __forceinline__ void update_item(const BatchArgs& B, char* arena, int
   A.dt = nullptr;
   const int64_t ncell = P.n[0] * P.n[1];
   const bool speeds = (MODE == 3) && (n + 1 < B.nsteps);
+  const bool bvals = P.bcv[0][0] || P.bcv[0][1] || P.bcv[1][0] || P.bcv[1][1];
   double amax[2] = {0.0, 0.0};
   bool bad = false;
   for (int r = 0; r < CELLS_ITEM / BT; ++r) {
@@ -258,7 +263,7 @@ __device__ __forceinline__ void update_item(const BatchArgs& B, char* arena, int
       update_cell<2, MODE>(A, idx, co, dt, Wn);
       if (speeds) {
         cell_speeds<2>(Wn, B.gamma, amax, bad);
-        boundary_speeds(P, co, Wn, B.gamma, amax, bad);
+        if constexpr (BV) boundary_speeds(P, co, Wn, B.gamma, amax, bad);
       }
     }
   }
@@ -268,6 +273,7 @@ __device__ __forceinline__ void update_item(const BatchArgs& B, char* arena, int
   }
 }
 
+template <bool BV>
 __device__ __forceinline__ void speeds_item(const BatchArgs& B, char* arena, int p, int64_t k) {
   const BatchProblem& P = B.probs[p];
   const int64_t ncell = P.n[0] * P.n[1];
@@ -280,9 +286,11 @@ __device__ __forceinline__ void speeds_item(const BatchArgs& B, char* arena, int
       double Wc[4];
       unroll<4>([&](auto c) { Wc[c] = U[c * ncell + idx]; });
       cell_speeds<2>(Wc, B.gamma, amax, bad);
-      const uint32_t q = (uint32_t)idx / (uint32_t)P.n[0];
-      const int64_t co[3] = {(int64_t)((uint32_t)idx - q * (uint32_t)P.n[0]), (int64_t)q, 0};
-      boundary_speeds(P, co, Wc, B.gamma, amax, bad);
+      if constexpr (BV) {
+        const uint32_t q = (uint32_t)idx / (uint32_t)P.n[0];
+        const int64_t co[3] = {(int64_t)((uint32_t)idx - q * (uint32_t)P.n[0]), (int64_t)q, 0};
+        boundary_speeds(P, co, Wc, B.gamma, amax, bad);
+      }
     }
   }
   if (bad) atomicOr(B.status + p, 1);
@@ -317,7 +325,7 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs& B, unsigned long l
   return *s_flag != 0;
 }
 
-template <int ORDER, bool LIMIT, bool ROE>
+template <int ORDER, bool LIMIT, bool ROE, bool BV>
 __global__ __launch_bounds__(BT)
 #if TENOAA_BATCH_WAVES_PER_EU > 0
 __attribute__((amdgpu_waves_per_eu(TENOAA_BATCH_WAVES_PER_EU)))
@@ -353,15 +361,15 @@ void batch_kernel(BatchArgs B) {
         const int p = find_problem(pre, B.nprob, it);
         const int64_t k = it - pre[p];
         if (kind == 0) {
-          speeds_item(B, arena, p, k);
+          speeds_item<BV>(B, arena, p, k);
         } else if (kind == 1) {
-          sweep_item<ORDER, LIMIT, ROE>(B, arena, p, k, n, stage);
+          sweep_item<ORDER, LIMIT, ROE, BV>(B, arena, p, k, n, stage);
         } else if (stage == 1) {
-          update_item<1>(B, arena, p, k, n);
+          update_item<1, BV>(B, arena, p, k, n);
         } else if (stage == 2) {
-          update_item<2>(B, arena, p, k, n);
+          update_item<2, BV>(B, arena, p, k, n);
         } else {
-          update_item<3>(B, arena, p, k, n);
+          update_item<3, BV>(B, arena, p, k, n);
         }
       }
     }
@@ -387,15 +395,21 @@ __global__ __launch_bounds__(256) void batch_fill_kernel(double* U, const int64_
 
 using KernelFn = void (*)(BatchArgs);
 
-KernelFn pick_kernel(int order, bool limit, bool roe) {
-  if (roe) {
-    if (order == 8) return limit ? batch_kernel<8, true, true> : batch_kernel<8, false, true>;
-    if (order == 12) return limit ? batch_kernel<12, true, true> : batch_kernel<12, false, true>;
-    return limit ? batch_kernel<10, true, true> : batch_kernel<10, false, true>;
+// The variant with prescribed sides (BV) only without the Roe flux.
+KernelFn pick_kernel(int order, bool limit, bool roe, bool bv) {
+  if (bv) {
+    if (order == 8) return limit ? batch_kernel<8, true, false, true> : batch_kernel<8, false, false, true>;
+    if (order == 12) return limit ? batch_kernel<12, true, false, true> : batch_kernel<12, false, false, true>;
+    return limit ? batch_kernel<10, true, false, true> : batch_kernel<10, false, false, true>;
   }
-  if (order == 8) return limit ? batch_kernel<8, true, false> : batch_kernel<8, false, false>;
-  if (order == 12) return limit ? batch_kernel<12, true, false> : batch_kernel<12, false, false>;
-  return limit ? batch_kernel<10, true, false> : batch_kernel<10, false, false>;
+  if (roe) {
+    if (order == 8) return limit ? batch_kernel<8, true, true, false> : batch_kernel<8, false, true, false>;
+    if (order == 12) return limit ? batch_kernel<12, true, true, false> : batch_kernel<12, false, true, false>;
+    return limit ? batch_kernel<10, true, true, false> : batch_kernel<10, false, true, false>;
+  }
+  if (order == 8) return limit ? batch_kernel<8, true, false, false> : batch_kernel<8, false, false, false>;
+  if (order == 12) return limit ? batch_kernel<12, true, false, false> : batch_kernel<12, false, false, false>;
+  return limit ? batch_kernel<10, true, false, false> : batch_kernel<10, false, false, false>;
 }
 
 int64_t faces_along2(const tenoaa_grid& g, int d) {
@@ -726,7 +740,8 @@ int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const teno
   for (int q = 0; q < nprob; ++q) {
     if (!tenoaa::grid_ok(&grids[q], scheme)) return TENOAA_EINVAL;
     if (grids[q].ndim != 2 || tenoaa::has_halo(&grids[q])) return TENOAA_EUNSUPPORTED;
-    if (tenoaa::has_boundary_values(&grids[q]) && grids[q].bc_sets != 1) return TENOAA_EUNSUPPORTED;
+    if (tenoaa::has_boundary_values(&grids[q]) && (grids[q].bc_sets != 1 || scheme->splitting == TENOAA_ROE))
+      return TENOAA_EUNSUPPORTED;
     if (grids[q].n[0] * grids[q].n[1] >= ((int64_t)1 << 31)) return TENOAA_EINVAL;
     total += 4 * grids[q].n[0] * grids[q].n[1];
     if (total > ((int64_t)1 << 40)) return TENOAA_EINVAL;
@@ -746,7 +761,9 @@ int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const teno
   std::stable_sort(P->order.begin(), P->order.end(), [&](int a, int b) {
     return grids[a].n[0] * grids[a].n[1] > grids[b].n[0] * grids[b].n[1];
   });
-  P->kernel = pick_kernel(scheme->order, scheme->positivity != 0, scheme->splitting == TENOAA_ROE);
+  bool bv = false;
+  for (const tenoaa_grid& g : P->grids) bv = bv || tenoaa::has_boundary_values(&g);
+  P->kernel = pick_kernel(scheme->order, scheme->positivity != 0, scheme->splitting == TENOAA_ROE, bv);
   P->cache_key = make_key(P);
 
   int dev = 0, rate_khz = 0, nblk = 0;

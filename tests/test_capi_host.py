@@ -121,10 +121,13 @@ def test_dirichlet_arguments_checked():
                             16, None) == -5
     assert L.tenoaa_step_vjp(ctypes.byref(ok), ctypes.byref(s), 1.4, vp(256), vp(512), vp(768), vp(4096), None,
                              vp(1024), 16, None) == -5
-    # the batch plan takes one value set only (its steps reuse it)
+    # the batch plan takes one value set only (its steps reuse it), and not with the Roe flux
     h = vp(None)
     arr = (tenoaa.Grid * 1)(grid(sets=3))
     assert L.tenoaa_batch_plan_create(arr, 1, ctypes.byref(s), 1.4, 0.4, 2, None, ctypes.byref(h)) == -2
+    arr = (tenoaa.Grid * 1)(grid())
+    roe = tenoaa.make_scheme(8, tenoaa.ROE)
+    assert L.tenoaa_batch_plan_create(arr, 1, ctypes.byref(roe), 1.4, 0.4, 2, None, ctypes.byref(h)) == -2
     assert h.value is None
 
 
