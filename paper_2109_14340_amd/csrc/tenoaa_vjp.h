@@ -22,9 +22,9 @@
 // pass turns those into conserved-state adjoints, maps ghost cells back to
 // their interior source (with the momentum sign flips of wall conditions) and
 // adds them to U_bar with global FP64 atomics (a Dirichlet ghost through the
-// Jacobian of its reflection rule; an inflow ghost is a constant), so the
-// summation order - and
-// the last bits of U_bar - can vary between runs.
+// Jacobian of its reflection rule; an inflow ghost is a constant; a halo
+// cell, a neighbour piece's, goes to the caller's halo-adjoint buffer), so
+// the summation order - and the last bits of U_bar - can vary between runs.
 #pragma once
 #include <hip/hip_runtime.h>
 
