@@ -148,3 +148,29 @@ def test_inflow_layers_must_match_the_order():
     _, g = _grids(shape, [I, 1], [I, 1], faces)
     with pytest.raises(tenoaa.TenoaaError, match="ghost layers"):
         tenoaa.rhs(g, tenoaa.make_scheme(10), torch.from_numpy(U).cuda())
+
+
+def test_stage_entry_points_equal_the_step():
+    """tenoaa_wave_speeds + tenoaa_rk3_stage 1, 2, 3 (stage s reading value set
+    s of three) give tenoaa_step's state and dt bit for bit, with the limiter,
+    on a grid with Dirichlet, inflow and wall sides."""
+    shape, lo, hi = (40, 36), [D, tenoaa.BC_NOSLIP], [I, D]
+    U0 = _smooth(shape, 6)
+    faces = _face_values(U0, shape, lo, hi, 1.4, 3, seed=8, order=10)
+    _, g = _grids(shape, lo, hi, faces)
+    sch = tenoaa.make_scheme(10, tenoaa.LLF, 1)
+    Uw = torch.from_numpy(U0).cuda()
+    dtw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tenoaa.step(g, sch, Uw, dtw)
+    Un = torch.from_numpy(U0).cuda()
+    ws = tenoaa.workspace(g, sch, tenoaa.WS_RHS)
+    amax = tenoaa.wave_speeds(g, sch, Un, ws=ws).clone()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Us = torch.empty_like(Un)
+    tenoaa.rk3_stage(g, sch, 1, amax, dt, Un, None, Us, ws=ws)
+    tenoaa.rk3_stage(g, sch, 2, amax, dt, Un, Us, Us, ws=ws)
+    tenoaa.rk3_stage(g, sch, 3, amax, dt, Un, Us, Un, ws=ws)
+    torch.cuda.synchronize()
+    assert tenoaa.get_status(ws) == 0
+    assert float(dt.item()) == float(dtw.item())
+    assert torch.equal(Un, Uw)
