@@ -203,3 +203,72 @@ def test_pieces_rhs_vjp_sum_to_whole(case, splitting):
     err = float((assembled - whole).abs().max() / whole.abs().max())
     print(case, splitting, "max rel difference of the assembled adjoint: %.2e" % err)
     assert err <= 1e-13
+
+
+@pytest.mark.parametrize("case", ["3d_z", "2d_y"])
+def test_pieces_step_adjoint_equals_whole(case):
+    """The adjoint of a split SSP-RK3 step, composed from the pieces'
+    tenoaa_rhs_vjp_halo with the stages' transposes (the chain
+    tenoaa_step_vjp runs in one piece) and a reverse halo exchange per stage,
+    equals the whole grid's tenoaa_step_vjp (limiter off; up to the order of
+    the atomic sums)."""
+    shape, d, cuts = CUTS[case]
+    order, G = 10, 5
+    ax = _ax(4, d)
+    n = shape[d]
+    sch = tenoaa.make_scheme(order, tenoaa.LLF, 0)
+    if len(shape) == 3:  # without the limiter: the random field without the near-vacuum sphere
+        U0 = torch.from_numpy(inputs.grf_3d(max(shape), spheres=False)[:, :shape[2], :shape[1], :shape[0]].copy()).cuda()
+    else:
+        U0 = torch.from_numpy(_state(shape)).cuda()
+    W = torch.randn(U0.shape, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(7))
+    g = tenoaa.make_grid(shape)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tenoaa.step(g, sch, U0.clone(), dt)
+    whole = tenoaa.step_vjp(g, sch, U0, dt, W)
+    spans = list(zip(cuts[:-1], cuts[1:]))
+    grids = [_piece_grid(shape, d, lo, hi, _halos(U0, d, lo, hi, G)) for lo, hi in spans]
+
+    def exchange(full):
+        for (lo, hi), gp in zip(spans, grids):
+            for key, v in _halos(full, d, lo, hi, G).items():
+                gp._faces[key].copy_(v)
+
+    def jt(state, seed):
+        """(dL/dU at state)^T seed over the whole grid, assembled from the pieces."""
+        exchange(state)
+        out = torch.zeros_like(state)
+        for (lo, hi), gp in zip(spans, grids):
+            own, bars = tenoaa.rhs_vjp_halo(gp, sch, _piece(state, d, lo, hi), _piece(seed, d, lo, hi))
+            out.narrow(ax, lo, hi - lo).add_(own)
+            for side in (0, 1):
+                for r in range(1, G + 1):
+                    c = (lo - r) % n if side == 0 else (hi - 1 + r) % n
+                    sl = out.narrow(ax, c, 1)
+                    sl.add_(bars[(d, side)][r - 1].reshape(sl.shape))
+        return out
+
+    # forward stages of the pieces (the halos of each stage's input exchanged first)
+    amax = None
+    pieces = [_piece(U0, d, lo, hi) for lo, hi in spans]
+    exchange(U0)
+    amax = torch.stack([tenoaa.wave_speeds(gp, sch, u) for gp, u in zip(grids, pieces)]).max(dim=0).values
+    dts = dt.clone()
+    U1p = [torch.empty_like(u) for u in pieces]
+    for gp, u, o in zip(grids, pieces, U1p):
+        tenoaa.rk3_stage(gp, sch, 1, amax.contiguous(), dts, u, None, o)
+    U1 = torch.cat(U1p, dim=ax)
+    exchange(U1)
+    U2p = [torch.empty_like(u) for u in pieces]
+    for gp, u, s1, o in zip(grids, pieces, U1p, U2p):
+        tenoaa.rk3_stage(gp, sch, 2, amax.contiguous(), dts, u, s1, o)
+    U2 = torch.cat(U2p, dim=ax)
+    # reverse: the transposes of the Shu-Osher stages
+    h = float(dt.item())
+    B3 = W
+    B2 = (2.0 / 3.0) * B3 + ((2.0 / 3.0) * h) * jt(U2, B3)
+    B1 = 0.25 * B2 + (0.25 * h) * jt(U1, B2)
+    Bn = (1.0 / 3.0) * B3 + 0.75 * B2 + B1 + h * jt(U0, B1)
+    err = float((Bn - whole).abs().max() / whole.abs().max())
+    print(case, "split step adjoint against the whole grid's: max rel %.2e" % err)
+    assert err <= 1e-13
