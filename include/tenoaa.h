@@ -110,7 +110,9 @@ enum { TENOAA_LLF = 0, TENOAA_RUSANOV = 1, TENOAA_ROE = 2 };
 enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1, TENOAA_WS_RHS_VJP = 2, TENOAA_WS_STEP_VJP = 3 };
 
 /* Uniform cell-centred grid: cell i of direction d has centre (i + 1/2) dx[d].
- * n[d] >= order/2 for d < ndim and n[d] == 1 otherwise; dx[d] > 0.
+ * n[d] >= order/2 for d < ndim and n[d] == 1 otherwise; dx[d] > 0; in 2D
+ * and 3D n[1], n[2] <= 65535 and n[0] <= 524280 (the launch grids' y and z
+ * extents); nvar x the cell count below 9e15.
  *
  * Boundary values (read only where bc_lo[d] / bc_hi[d] is
  * TENOAA_BC_DIRICHLET, TENOAA_BC_INFLOW or TENOAA_BC_HALO, else ignored and

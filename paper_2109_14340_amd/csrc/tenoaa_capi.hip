@@ -100,9 +100,13 @@ bool valid_grid(const tenoaa_grid* g, const tenoaa_scheme* s) {
       return false;
     }
   }
-  // flat indices stay within int64 and the grid within a launch's z extent
+  // flat indices stay within int64, and the y and z extents of every sweep's
+  // launch grid (tiles across the direction, the remaining axis) within 65535
+  // blocks: n_y, n_z <= 65535, and n_x <= 8 x 65535 (y and z sweeps tile x by
+  // at least 8 pencils)
   const double cells = (double)g->n[0] * (double)g->n[1] * (double)g->n[2];
   if (cells * (g->ndim + 2) > 9.0e15) return false;
+  if (g->ndim >= 2 && (g->n[1] > 65535 || g->n[2] > 65535 || g->n[0] > 8 * 65535)) return false;
   return true;
 }
 

@@ -263,3 +263,18 @@ def test_halo_and_stage_arguments_checked():
                 dict(sch=tenoaa.make_scheme(10, 0, 1), cfl=0.6)):
         assert stage(**bad) == -1, bad
     assert stage(nbytes=need - 8) == -5
+
+
+def test_launch_extents_checked():
+    """Grids whose sweeps would need more than 65535 blocks along a launch's y
+    or z extent are rejected before any device work."""
+    L = _lib()
+    s = tenoaa.make_scheme(8)
+
+    def ws(shape):
+        return L.tenoaa_workspace_bytes(ctypes.byref(tenoaa.make_grid(shape)), ctypes.byref(s), 0)
+
+    assert ws((8, 8, 65535)) > 0 and ws((8, 8, 65536)) == 0
+    assert ws((8, 65535, 8)) > 0 and ws((8, 65536, 8)) == 0
+    assert ws((8 * 65535, 8)) > 0 and ws((8 * 65535 + 1, 8)) == 0
+    assert ws((1 << 24,)) > 0  # 1D: one launch dimension
