@@ -154,9 +154,11 @@ __device__ __forceinline__ void run_sweep_tile(const SweepArgs& A, char* arena, 
                                                int64_t along, double mu) {
   const int64_t bx = k % along, by = k / along;
   if (cand == 0) {
-    sweep_tile<ORDER, 2, DIR, Cand<DIR, 0>::TT, Cand<DIR, 0>::TN, LIMIT, ROE>(A, arena, bx, by, 0, mu);
+    sweep_tile<ORDER, 2, DIR, Cand<DIR, 0>::TT, Cand<DIR, 0>::TN, LIMIT, ROE ? TENOAA_ROE : SPLIT_RUNTIME>(
+        A, arena, bx, by, 0, mu);
   } else {
-    sweep_tile<ORDER, 2, DIR, Cand<DIR, 1>::TT, Cand<DIR, 1>::TN, LIMIT, ROE>(A, arena, bx, by, 0, mu);
+    sweep_tile<ORDER, 2, DIR, Cand<DIR, 1>::TT, Cand<DIR, 1>::TN, LIMIT, ROE ? TENOAA_ROE : SPLIT_RUNTIME>(
+        A, arena, bx, by, 0, mu);
   }
 }
 

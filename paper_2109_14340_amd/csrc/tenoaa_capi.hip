@@ -207,8 +207,7 @@ hipError_t wave_speeds(const Ctx& c, const double* U) {
     for (int h = 0; h < 2 && e == hipSuccess; ++h) {
       const double* fv = face_values(g, c.s->order, d, h, 0);
       if (!fv) continue;
-      tenoaa::GhostSpeedArgs a;
-      std::memset(&a, 0, sizeof(a));
+      tenoaa::GhostSpeedArgs a{};
       a.U = U;
       a.fv = fv;
       for (int k = 0; k < 3; ++k) a.n[k] = g->n[k];
@@ -233,8 +232,7 @@ int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint
       flag_off += (int64_t)nv * 2 * faces_total(g, d);
       continue;
     }
-    tenoaa::SweepArgs a;
-    std::memset(&a, 0, sizeof(a));
+    tenoaa::SweepArgs a{};
     a.U = U;
     a.F = reinterpret_cast<double*>(c.ws + c.L.fbuf[d]);
     // with only_dir set, flags/frozen point at that direction's own array
@@ -264,8 +262,7 @@ int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint
 
 int update(const Ctx& c, int mode, const double* Un, const double* Us, double* out) {
   const tenoaa_grid* g = c.g;
-  tenoaa::UpdateArgs a;
-  std::memset(&a, 0, sizeof(a));
+  tenoaa::UpdateArgs a{};
   for (int d = 0; d < 3; ++d) {
     a.F[d] = reinterpret_cast<const double*>(c.ws + c.L.fbuf[d]);
     a.nft[d] = d < g->ndim ? faces_total(g, d) : 0;
@@ -315,8 +312,7 @@ int rhs_vjp(const Ctx& c, const double* U, const double* R, double* Ubar, int st
   hipError_t e = tenoaa::launch_zero(Ubar, (int64_t)nv * ncell, c.st);
   if (e != hipSuccess) return hip_fail(e);
   for (int d = 0; d < g->ndim; ++d) {
-    tenoaa::AdjointArgs a;
-    std::memset(&a, 0, sizeof(a));
+    tenoaa::AdjointArgs a{};
     a.U = U;
     a.R = R;
     a.Ubar = Ubar;

@@ -17,67 +17,70 @@ struct Scalars {
   int pad;
 };
 
+// Every member has a default (null pointers, zero sizes), so an argument
+// block that a caller fills only in part never carries an indeterminate
+// pointer into a kernel.
 struct SweepArgs {
-  const double* U;
-  double* F;        // face fluxes of this direction, [nvar][nft]
-  uint8_t* flags;   // flags of this direction, [nvar][2][nft], or null
-  const uint8_t* frozen;  // decisions to replay instead of taking them, or null
-  double* fh_out;         // per-field reconstructed fluxes fh_s = f+_s + f-_s, [nvar][nft], or null
-  double* theta_out;      // per face: the limiter's theta_rho * theta_p (1 where it leaves the flux), or null
-  int64_t n[3];
-  int64_t nf;       // faces along the direction
-  int64_t nft;      // faces of the direction in total
-  int64_t f_begin;  // first face along the direction of this launch's tiles
-  int bc_lo, bc_hi;
-  int splitting;
-  int pad;
-  double gamma;
-  const double* bcv[2];  // boundary (Dirichlet, inflow, halo) values of the low/high side, this evaluation's set, or null
-  const double* mu; // device: limiter factors
-  int* status;      // device: status word
+  const double* U = nullptr;
+  double* F = nullptr;               // face fluxes of this direction, [nvar][nft]
+  uint8_t* flags = nullptr;          // flags of this direction, [nvar][2][nft], or null
+  const uint8_t* frozen = nullptr;   // decisions to replay instead of taking them, or null
+  double* fh_out = nullptr;          // per-field reconstructed fluxes fh_s = f+_s + f-_s, [nvar][nft], or null
+  double* theta_out = nullptr;       // per face: the limiter's theta_rho * theta_p (1 where it leaves the flux), or null
+  int64_t n[3] = {0, 0, 0};
+  int64_t nf = 0;       // faces along the direction
+  int64_t nft = 0;      // faces of the direction in total
+  int64_t f_begin = 0;  // first face along the direction of this launch's tiles
+  int bc_lo = 0, bc_hi = 0;
+  int splitting = 0;
+  int pad = 0;
+  double gamma = 0.0;
+  const double* bcv[2] = {nullptr, nullptr};  // boundary (Dirichlet, inflow, halo) values of the low/high side, this evaluation's set, or null
+  const double* mu = nullptr;  // device: limiter factors
+  int* status = nullptr;       // device: status word
 };
 
 struct UpdateArgs {
-  uint32_t div_m[2], div_l[2];  // fast division by n0 and n1 (grids below 2^32 cells)
-  const double* F[3];
-  int64_t nft[3];
-  int64_t nf[3];
-  int64_t n[3];
-  double dx[3];
-  double rdx[3];     // 1 / dx, correctly rounded (host)
-  const double* Un;
-  const double* Us;
-  double* out;
-  const double* dt;  // device
+  uint32_t div_m[2] = {0, 0}, div_l[2] = {0, 0};  // fast division by n0 and n1 (grids below 2^32 cells)
+  const double* F[3] = {nullptr, nullptr, nullptr};
+  int64_t nft[3] = {0, 0, 0};
+  int64_t nf[3] = {0, 0, 0};
+  int64_t n[3] = {0, 0, 0};
+  double dx[3] = {0.0, 0.0, 0.0};
+  double rdx[3] = {0.0, 0.0, 0.0};  // 1 / dx, correctly rounded (host)
+  const double* Un = nullptr;
+  const double* Us = nullptr;
+  double* out = nullptr;
+  const double* dt = nullptr;  // device
 };
 
 // One side with prescribed values, for the ghost-cell wave speeds.
 struct GhostSpeedArgs {
-  const double* U;
-  const double* fv;  // the side's values, set 0 (face values or the first inflow layer)
-  int64_t n[3];
-  int dir, hi, bc, pad;
-  double gamma;
+  const double* U = nullptr;
+  const double* fv = nullptr;  // the side's values, set 0 (face values or the first inflow layer)
+  int64_t n[3] = {0, 0, 0};
+  int dir = 0, hi = 0, bc = 0, pad = 0;
+  double gamma = 0.0;
 };
 
 struct AdjointArgs {
-  const double* U;   // state at which the right-hand side is differentiated
-  const double* R;   // seed: adjoint of dU/dt, layout of U
-  double* Ubar;      // accumulated with atomics (caller zeroes it)
-  const uint8_t* flags;  // decisions of this direction's forward sweep at U, [nvar][2][nft]
-  const double* fh;      // per-field fluxes of that sweep, [nvar][nft]
-  const double* theta;   // the sweep's limiter factors per face, or null (no limiter)
-  const double* bcv[2];  // boundary values of the low/high side (Dirichlet, inflow, halo), else null
-  double* hbar[2];       // adjoints of the low/high halo cells (accumulated with atomics), or null
-  int64_t nft;
-  int64_t f_begin;       // first face along the direction of this launch's tiles
-  int64_t n[3];
-  int64_t nf;
-  int bc_lo, bc_hi;
-  int splitting;
-  int pad;
-  double gamma;
-  double dx;
+  const double* U = nullptr;       // state at which the right-hand side is differentiated
+  const double* R = nullptr;       // seed: adjoint of dU/dt, layout of U
+  double* Ubar = nullptr;          // accumulated with atomics (caller zeroes it)
+  const uint8_t* flags = nullptr;  // decisions of this direction's forward sweep at U, [nvar][2][nft]
+  const double* fh = nullptr;      // per-field fluxes of that sweep, [nvar][nft]
+  const double* theta = nullptr;   // the sweep's limiter factors per face, or null (no limiter)
+  const double* bcv[2] = {nullptr, nullptr};  // boundary values of the low/high side (Dirichlet, inflow, halo), else null
+  double* hbar[2] = {nullptr, nullptr};       // adjoints of the low/high halo cells (accumulated with atomics), or null
+  int64_t nft = 0;
+  int64_t f_begin = 0;  // first face along the direction of this launch's tiles
+  int64_t n[3] = {0, 0, 0};
+  int64_t nf = 0;
+  int bc_lo = 0, bc_hi = 0;
+  int splitting = 0;
+  int pad = 0;
+  double gamma = 0.0;
+  double dx = 0.0;
 };
 
 // Argument check of a grid and scheme (shared by every entry point).

@@ -49,7 +49,7 @@ namespace tenoaa {
 namespace {
 
 // ------------------------------------------------------------ sweep kernel
-template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT, bool ROE>
+template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT, int SPLIT>
 __global__ __launch_bounds__(TT* TN)
 #if TENOAA_WAVES_PER_EU > 0
 __attribute__((amdgpu_waves_per_eu(TENOAA_WAVES_PER_EU)))
@@ -57,7 +57,7 @@ __attribute__((amdgpu_waves_per_eu(TENOAA_WAVES_PER_EU)))
 void sweep_kernel(SweepArgs A) {
   __shared__ __align__(16) char arena[SweepShape<ORDER, NDIM, TT, TN>::LDS_BYTES];
   const double mu = LIMIT ? A.mu[DIR] : 0.0;
-  sweep_tile<ORDER, NDIM, DIR, TT, TN, LIMIT, ROE>(A, arena, blockIdx.x, blockIdx.y, blockIdx.z, mu);
+  sweep_tile<ORDER, NDIM, DIR, TT, TN, LIMIT, SPLIT>(A, arena, blockIdx.x, blockIdx.y, blockIdx.z, mu);
 }
 
 // --------------------------------------------------- flux difference / RK
@@ -198,7 +198,7 @@ __global__ void speeds_in_kernel(Scalars* S, int ndim, const double* amax) {
 }  // namespace
 
 // ------------------------------------------------------------ host launchers
-template <int ORDER, int NDIM, int DIR, bool LIMIT, bool ROE>
+template <int ORDER, int NDIM, int DIR, bool LIMIT, int SPLIT>
 static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   constexpr int TT = (NDIM == 1) ? 1 : (DIR == 0 ? TENOAA_TT_X : TENOAA_TT_YZ);
   constexpr int TN = (DIR == 0) ? TENOAA_TN_X : TENOAA_TN_YZ;
@@ -212,7 +212,7 @@ static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   const int64_t whole = (NDIM == 1 || rem == 0 || rem > SWEEP_TAIL_TN) ? a.nf : a.nf - rem;
   if (whole > 0) {
     dim3 grid((unsigned)((whole + TN - 1) / TN), (unsigned)((a.n[AX_A] + TT - 1) / TT), (unsigned)a.n[AX_B]);
-    hipLaunchKernelGGL((sweep_kernel<ORDER, NDIM, DIR, TT, TN, LIMIT, ROE>), grid, dim3(TT * TN), 0, st, a);
+    hipLaunchKernelGGL((sweep_kernel<ORDER, NDIM, DIR, TT, TN, LIMIT, SPLIT>), grid, dim3(TT * TN), 0, st, a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess || whole == a.nf) return e;
   }
@@ -221,11 +221,16 @@ static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   return launch_sweep_tail(ORDER, NDIM, DIR, t, LIMIT, st);
 }
 
+template <int ORDER, int NDIM, int DIR, int SPLIT>
+static hipError_t launch_sweep_s(const SweepArgs& a, bool limit, hipStream_t st) {
+  return limit ? launch_sweep_t<ORDER, NDIM, DIR, true, SPLIT>(a, st) : launch_sweep_t<ORDER, NDIM, DIR, false, SPLIT>(a, st);
+}
+
 template <int ORDER, int NDIM, int DIR>
 static hipError_t launch_sweep_o(const SweepArgs& a, bool limit, hipStream_t st) {
-  if (a.splitting == TENOAA_ROE)
-    return limit ? launch_sweep_t<ORDER, NDIM, DIR, true, true>(a, st) : launch_sweep_t<ORDER, NDIM, DIR, false, true>(a, st);
-  return limit ? launch_sweep_t<ORDER, NDIM, DIR, true, false>(a, st) : launch_sweep_t<ORDER, NDIM, DIR, false, false>(a, st);
+  if (a.splitting == TENOAA_ROE) return launch_sweep_s<ORDER, NDIM, DIR, TENOAA_ROE>(a, limit, st);
+  if (a.splitting == TENOAA_RUSANOV) return launch_sweep_s<ORDER, NDIM, DIR, TENOAA_RUSANOV>(a, limit, st);
+  return launch_sweep_s<ORDER, NDIM, DIR, TENOAA_LLF>(a, limit, st);
 }
 
 template <int ORDER>

@@ -44,9 +44,17 @@ struct SweepShape {
   static constexpr int NC = TN + W - 1;
   static constexpr int NCT = TT * NC;
   static constexpr int NTH = TT * TN;
-  // per-cell records: NV double2 (conserved, flux) + un, c, sqrt(rho), H + NT tangential velocities
-  static constexpr int LDS_BYTES = NCT * (16 * NV + 8 * (4 + NT));
+  // cells that are one of the two cells of a face of the tile: TN + 1 per pencil
+  static constexpr int NFC = TN + 1;
+  static constexpr int NFCT = TT * NFC;
+  // per-cell records: NV double2 (conserved, flux) + un, c for every staged
+  // cell; sqrt(rho), H and the NT tangential velocities for the face cells
+  static constexpr int LDS_BYTES = NCT * (16 * NV + 16) + NFCT * 8 * (2 + NT);
 };
+
+// Splitting of a sweep, fixed at compile time (TENOAA_LLF, TENOAA_RUSANOV,
+// TENOAA_ROE), or SPLIT_RUNTIME: LLF or Rusanov as the arguments say.
+constexpr int SPLIT_RUNTIME = -1;
 
 // Dirichlet ghost cell (Appendix A): in primitive variables the ghost is the
 // mirror cell reflected through the prescribed face value,
@@ -100,10 +108,14 @@ __device__ __forceinline__ void inflow_ghost(double* W, const double* pv, int64_
 // least SweepShape::LDS_BYTES bytes, 16-byte aligned; the caller separates
 // consecutive tiles that reuse it with a barrier.  `mu` is the limiter factor
 // of this direction (used when LIMIT).  ROE selects the Roe flux with entropy
-// fix; otherwise A.splitting chooses LLF or Rusanov.
-template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT, bool ROE = false>
+// fix (SPLIT = TENOAA_ROE); SPLIT = TENOAA_LLF or TENOAA_RUSANOV fixes the
+// flux splitting, SPLIT_RUNTIME takes it from A.splitting.
+template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT, int SPLIT = SPLIT_RUNTIME>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_t bx, int64_t by, int64_t bz,
                                            double mu) {
+  static_assert(SPLIT == SPLIT_RUNTIME || SPLIT == TENOAA_LLF || SPLIT == TENOAA_RUSANOV || SPLIT == TENOAA_ROE,
+                "unknown splitting");
+  constexpr bool ROE = SPLIT == TENOAA_ROE;
   using Sh = SweepShape<ORDER, NDIM, TT, TN>;
   constexpr int G = ORDER / 2;
   constexpr int W = ORDER;
@@ -111,18 +123,22 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
   constexpr int NT = Sh::NT;
   constexpr int NC = Sh::NC;
   constexpr int NCT = Sh::NCT;
+  constexpr int NFC = Sh::NFC;
+  constexpr int NFCT = Sh::NFCT;
   constexpr int AX_A = (DIR == 0) ? 1 : 0;  // transverse axis spread over threads
   constexpr int AX_B = (DIR == 2) ? 1 : 2;  // remaining axis
   using Fr = Frame<NDIM, DIR>;
 
-  // per-cell records: (conserved, flux) pairs in the local frame, then
-  // normal velocity, sound speed, sqrt(rho), enthalpy, tangential velocities
+  // per-cell records: half the (conserved, flux) pairs in the local frame
+  // (the splitting's factor 1/2, exact as a power of two, applied once per
+  // cell), normal velocity, sound speed; for the face cells also sqrt(rho),
+  // enthalpy and the tangential velocities
   double2* const sWF = reinterpret_cast<double2*>(lds);
   double* const sUn = reinterpret_cast<double*>(lds + 16 * NV * NCT);
   double* const sC = sUn + NCT;
   double* const sSr = sC + NCT;
-  double* const sH = sSr + NCT;
-  double* const sUt = sH + NCT;
+  double* const sH = sSr + NFCT;
+  double* const sUt = sH + NFCT;
 
   const int64_t nN = A.n[DIR];
   const int64_t nA = A.n[AX_A];
@@ -197,22 +213,27 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     const double E = Wc[NV - 1];
     const double p = gm1 * (E - (0.5 * rho) * q2);
     const double c = sqrt_rn((gam * p) * ir);
-    const double H = (E + p) * ir;
-    const double sr = sqrt_rn(rho);
     const double un = u[DIR];
     if (!(rho > 0.0) || !(p > 0.0)) atomicOr(A.status, 1);
-    // conserved state and physical flux along DIR in the local frame
-    sWF[ct] = make_double2(rho, Wc[1 + DIR]);
+    // half the conserved state and physical flux along DIR in the local frame
+    sWF[ct] = make_double2(0.5 * rho, 0.5 * Wc[1 + DIR]);
     unroll<NDIM>([&](auto k) {
       constexpr int slot = Fr::slot_of_axis(decltype(k)::value);
-      sWF[(1 + slot) * NCT + ct] = make_double2(Wc[1 + k], (k == DIR) ? Wc[1 + k] * un + p : Wc[1 + k] * un);
-      if constexpr (slot > 0) sUt[(slot - 1) * NCT + ct] = u[k];
+      sWF[(1 + slot) * NCT + ct] =
+          make_double2(0.5 * Wc[1 + k], 0.5 * ((k == DIR) ? Wc[1 + k] * un + p : Wc[1 + k] * un));
     });
-    sWF[(NV - 1) * NCT + ct] = make_double2(E, (E + p) * un);
+    sWF[(NV - 1) * NCT + ct] = make_double2(0.5 * E, 0.5 * ((E + p) * un));
     sUn[ct] = un;
     sC[ct] = c;
-    sSr[ct] = sr;
-    sH[ct] = H;
+    if (nn >= G - 1 && nn <= G - 1 + TN) {  // one of the two cells of a face of the tile
+      const int fc = (DIR == 0) ? tt * NFC + (nn - (G - 1)) : (nn - (G - 1)) * TT + tt;
+      sSr[fc] = sqrt_rn(rho);
+      sH[fc] = (E + p) * ir;
+      unroll<NDIM>([&](auto k) {
+        constexpr int slot = Fr::slot_of_axis(decltype(k)::value);
+        if constexpr (slot > 0) sUt[(slot - 1) * NFCT + fc] = u[k];
+      });
+    }
   }
   __syncthreads();
 
@@ -245,14 +266,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
   const int lbase = (DIR == 0) ? tt * NC + fn : fn * TT + tt;
   constexpr int LSTEP = (DIR == 0) ? 1 : TT;
   const int ia = lbase + (G - 1) * LSTEP, ib = lbase + G * LSTEP;
+  // index of the face's two cells among the face-cell records
+  const int fa = (DIR == 0) ? tt * NFC + fn : fn * TT + tt, fb = fa + LSTEP;
 
   // Roe average (Sec. 5: characteristic decomposition at the face)
-  const double sa = sSr[ia], sb = sSr[ib];
+  const double sa = sSr[fa], sb = sSr[fb];
   const double den = sa + sb;
   const double iden = div_rn(1.0, den);  // the Roe weights' denominator, inverted once
   const double un = (sa * sUn[ia] + sb * sUn[ib]) * iden;
   double ut[NT];
-  unroll<NDIM - 1>([&](auto k) { ut[k] = (sa * sUt[k * NCT + ia] + sb * sUt[k * NCT + ib]) * iden; });
+  unroll<NDIM - 1>([&](auto k) { ut[k] = (sa * sUt[k * NFCT + fa] + sb * sUt[k * NFCT + fb]) * iden; });
   double q2 = 0.0;  // |u|^2 summed in axis order
   unroll<NDIM>([&](auto a) {
     constexpr int slot = Fr::slot_of_axis(decltype(a)::value);
@@ -261,7 +284,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     else ua = ut[slot - 1];
     q2 = (a == 0) ? ua * ua : q2 + ua * ua;
   });
-  const double Hr = (sa * sH[ia] + sb * sH[ib]) * iden;
+  const double Hr = (sa * sH[fa] + sb * sH[fb]) * iden;
   const double qq = 0.5 * q2;
   const double c2 = gm1 * (Hr - qq);
   const double cr = sqrt_rn(c2);
@@ -271,18 +294,30 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
   const double unc = un * ic;
   // splitting speeds over the window
   double am = 0.0, a0 = 0.0, ap = 0.0;
-  unroll<W>([&](auto j) {
-    const int li = lbase + j * LSTEP;
-    const double u = sUn[li], c = sC[li];
-    if (ROE || A.splitting == TENOAA_LLF) {  // LLF, also the Roe flux's fallback
+  auto llf_speeds = [&]() {  // LLF, also the Roe flux's fallback
+    unroll<W>([&](auto j) {
+      const int li = lbase + j * LSTEP;
+      const double u = sUn[li], c = sC[li];
       am = fmax(am, fabs(u - c));
       a0 = fmax(a0, fabs(u));
       ap = fmax(ap, fabs(u + c));
-    } else {
-      a0 = fmax(a0, fabs(u) + c);
-    }
-  });
-  if (!ROE && A.splitting != TENOAA_LLF) am = ap = a0;
+    });
+  };
+  auto rusanov_speeds = [&]() {
+    unroll<W>([&](auto j) {
+      const int li = lbase + j * LSTEP;
+      a0 = fmax(a0, fabs(sUn[li]) + sC[li]);
+    });
+    am = ap = a0;
+  };
+  if constexpr (SPLIT == TENOAA_LLF || ROE) {
+    llf_speeds();
+  } else if constexpr (SPLIT == TENOAA_RUSANOV) {
+    rusanov_speeds();
+  } else {
+    if (A.splitting == TENOAA_LLF) llf_speeds();
+    else rusanov_speeds();
+  }
 
   int64_t flin;
   {
@@ -337,7 +372,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
         upwind = (la > 0.0 && lb > 0.0) ? 1 : ((la < 0.0 && lb < 0.0) ? 2 : 0);
       }
     }
-    // projection of the window's state and flux on field s, then the split
+    // projection of the window's (halved) state and flux on field s, then the split
     double gp[W], gm[W];
     unroll<W>([&](auto j) {
       const int li = lbase + j * LSTEP;
@@ -357,12 +392,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
         v = mut * w0.x + ws.x;
         g = mut * w0.y + ws.y;
       }
+      // v, g are half the projections: the split 1/2 (g +- alpha v) is one fma
       if (!ROE || upwind == 0) {
-        gp[j] = 0.5 * fma(alpha, v, g);
-        gm[W - 1 - j] = 0.5 * fma(-alpha, v, g);  // mirrored for the - side
+        gp[j] = fma(alpha, v, g);
+        gm[W - 1 - j] = fma(-alpha, v, g);  // mirrored for the - side
       } else {
-        gp[j] = g;
-        gm[W - 1 - j] = g;
+        gp[j] = 2.0 * g;
+        gm[W - 1 - j] = 2.0 * g;
       }
 #if TENOAA_CELL_BARRIER
       __builtin_amdgcn_sched_barrier(0);
@@ -433,8 +469,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     const double aL = (sA >= sB) ? sA : sB;
     double FL[NV];
     unroll<NV>([&](auto c) {
+      // the records hold half the state and flux: this is 1/2 (F_a + F_b - aL (U_b - U_a))
       const double2 wa = sWF[c * NCT + ia], wb = sWF[c * NCT + ib];
-      FL[c] = 0.5 * ((wa.y + wb.y) - aL * (wb.x - wa.x));
+      FL[c] = (wa.y + wb.y) - aL * (wb.x - wa.x);
     });
     // pressure of X; EXACT selects correctly rounded divisions, otherwise
     // the compiler's (within an ulp), and `scale` bounds the terms of p
@@ -454,7 +491,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     unroll<2>([&](auto side) {
       const int li = side == 0 ? ia : ib;
       const double sg = side == 0 ? -1.0 : 1.0;
-      const double r = sWF[li].x;
+      const double r = 2.0 * sWF[li].x;
       const double rL = r + (sg * mu) * FL[0];
       const double rH = r + (sg * mu) * Fh[0];
       const double eps = rL < 1e-13 ? rL : 1e-13;
@@ -471,8 +508,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
       const double sg = side == 0 ? -1.0 : 1.0;
       double XL[NV], XS[NV];
       unroll<NV>([&](auto c) {
-        XL[c] = sWF[c * NCT + li].x + (sg * mu) * FL[c];
-        XS[c] = sWF[c * NCT + li].x + (sg * mu) * Fs[c];
+        const double x = 2.0 * sWF[c * NCT + li].x;
+        XL[c] = x + (sg * mu) * FL[c];
+        XS[c] = x + (sg * mu) * Fs[c];
       });
       // The test pS < eps with the compiler's divisions differs from the exact
       // one only if pS is within ~1e-15 of the pressures' term scale of eps;

@@ -22,7 +22,8 @@ __global__ __launch_bounds__(TAIL_TT* TAIL_TN) __attribute__((amdgpu_waves_per_e
 void sweep_tail_kernel(SweepArgs A) {
   __shared__ __align__(16) char arena[SweepShape<ORDER, NDIM, TAIL_TT, TAIL_TN>::LDS_BYTES];
   const double mu = LIMIT ? A.mu[DIR] : 0.0;
-  sweep_tile<ORDER, NDIM, DIR, TAIL_TT, TAIL_TN, LIMIT, ROE>(A, arena, blockIdx.x, blockIdx.y, blockIdx.z, mu);
+  sweep_tile<ORDER, NDIM, DIR, TAIL_TT, TAIL_TN, LIMIT, ROE ? TENOAA_ROE : SPLIT_RUNTIME>(A, arena, blockIdx.x, blockIdx.y,
+                                                                                  blockIdx.z, mu);
 }
 
 template <int ORDER, int NDIM, int DIR, bool LIMIT, bool ROE>
