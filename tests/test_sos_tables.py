@@ -1,0 +1,157 @@
+"""The kernels' smoothness-indicator tables (csrc/tenoaa_sos.h) against the
+paper: the header is what its generator writes, its sums of squares expand to
+the quadratic forms printed in Sec. 4.2 (tests/golden/beta_printed.txt), and
+the operation count of the roofline (flops.SOS_NNZ) is the number of their
+non-zero off-diagonal factors.  CPU only."""
+import os
+import re
+import sys
+from fractions import Fraction
+from math import comb
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2109_14340_amd", "csrc")
+HEADER = os.path.join(CSRC, "tenoaa_sos.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "beta_printed.txt")
+NAMES = {6: "S3", 8: "S4", 10: "S5", 12: "S6"}
+
+
+def header_tables():
+    """{width: (D, L)} parsed from tenoaa_sos.h (floats, L[m][k] row-major)."""
+    text = open(HEADER).read()
+    out = {}
+    for r, name in NAMES.items():
+        d = re.search(r"SOS_%s_D\[(\d+)\] = \{([^}]*)\};" % name, text)
+        lm = re.search(r"SOS_%s_L\[(\d+)\]\[\d+\] = \{(.*?)\};" % name, text, re.S)
+        n = int(d.group(1))
+        assert n == r - 1 and int(lm.group(1)) == n
+        D = [float(x) for x in d.group(2).split(",")]
+        L = [[float(x) for x in row.split(",")] for row in re.findall(r"\{([^{}]*)\}", lm.group(2))]
+        assert len(D) == n and len(L) == n and all(len(row) == n for row in L)
+        out[r] = (D, L)
+    return out
+
+
+def printed_forms():
+    """{width: (lo, den, {(a, b): coef})} from the golden file (Sec. 4.2)."""
+    forms, cur = {}, None
+    for ln in open(GOLDEN):
+        ln = ln.strip()
+        if not ln or ln.startswith("#"):
+            continue
+        t = ln.split()
+        if t[0] == "beta":
+            r, lo, hi, den = int(t[1]), int(t[2]), int(t[3]), int(t[4])
+            assert hi - lo + 1 == r
+            cur = forms[r] = (lo, den, {})
+        else:
+            cur[2][(int(t[0]), int(t[1]))] = int(t[2])
+    return forms
+
+
+def expand(D, L, r):
+    """Exact coefficients of f_a f_b (a <= b, indices 0..r-1 from the stencil's
+    leftmost cell) of sum_k D_k (sum_{m >= k} L_mk Delta^{m+1} f_0)^2, with the
+    table's doubles taken exactly."""
+    n = r - 1
+    Dq = [Fraction(x) for x in D]
+    Lq = [[Fraction(x) for x in row] for row in L]
+    # Delta^{m+1} f_0 = sum_j (-1)^{m+1-j} C(m+1, j) f_j
+    dif = [[Fraction((-1) ** (m + 1 - j) * comb(m + 1, j)) if j <= m + 1 else Fraction(0) for j in range(r)]
+           for m in range(n)]
+    coef = {}
+    for k in range(n):
+        y = [sum(Lq[m][k] * dif[m][j] for m in range(k, n)) for j in range(r)]
+        for a in range(r):
+            for b in range(a, r):
+                c = Dq[k] * y[a] * y[b] * (1 if a == b else 2)
+                coef[(a, b)] = coef.get((a, b), Fraction(0)) + c
+    return coef
+
+
+def test_unit_diagonal_and_positive_weights():
+    for r, (D, L) in header_tables().items():
+        assert all(L[m][m] == 1.0 for m in range(r - 1)), r
+        assert all(L[m][k] == 0.0 for m in range(r - 1) for k in range(m + 1, r - 1)), r
+        assert all(d > 0.0 for d in D), r
+
+
+@pytest.mark.parametrize("r", [6, 8, 10])
+def test_tables_expand_to_printed_forms(r):
+    """Sec. 4.2: the sums of squares, with their doubles taken exactly, equal
+    the printed integer forms to the tables' rounding (1e-15 of the largest
+    printed coefficient); the forms are invariant under constants, so the
+    printed coefficients of each row sum to zero."""
+    D, L = header_tables()[r]
+    lo, den, printed = printed_forms()[r]
+    got = expand(D, L, r)
+    big = max(abs(c) for c in printed.values())
+    assert {(a - lo, b - lo) for a, b in printed} == set(got)
+    for (a, b), c in printed.items():
+        # printed indices are offsets from i; the tables start at the leftmost cell
+        want = Fraction(c, den)
+        assert abs(got[(a - lo, b - lo)] - want) <= Fraction(big, den) * Fraction(1, 10 ** 15), (r, a, b)
+    for a in range(lo, lo + r):
+        row = sum(c * (2 if x == y else 1) for (x, y), c in printed.items() if a in (x, y))
+        assert row == 0, (r, a)
+
+
+def test_sos_nnz_matches_tables():
+    """The roofline's count of factor products is the number of non-zero
+    entries below the unit diagonal."""
+    sys.path.insert(0, ROOT)
+    from paper_2109_14340_amd import flops
+
+    for r, (D, L) in header_tables().items():
+        nnz = sum(1 for m in range(r - 1) for k in range(m) if L[m][k] != 0.0)
+        assert flops.SOS_NNZ[r] == nnz, (r, nnz)
+
+
+_GEN = []
+
+
+def generator():
+    """gen_beta_sos with its exact forms computed once for both tests."""
+    if not _GEN:
+        pytest.importorskip("sympy")
+        sys.path.insert(0, CSRC)
+        import functools
+
+        import gen_beta_sos
+
+        gen_beta_sos.jiang_shu_form = functools.lru_cache(maxsize=None)(gen_beta_sos.jiang_shu_form)
+        _GEN.append(gen_beta_sos)
+    return _GEN[0]
+
+
+def test_generator_reproduces_header():
+    """tenoaa_sos.h is exactly what gen_beta_sos.py writes from the Sec. 3.2
+    definition."""
+    gen_beta_sos = generator()
+    assert gen_beta_sos.render() == open(HEADER).read()
+
+
+def test_generator_forms_match_printed():
+    """The generator's exact forms (from the Sec. 3.2 definition) are the
+    printed Sec. 4.2 integers exactly; its S6 form, which the paper does not
+    print, is built the same way and its table expands to it."""
+    gen_beta_sos = generator()
+    exact = gen_beta_sos.exact_forms()
+    forms = printed_forms()
+    for r in (6, 8, 10):
+        lo, H = exact[r]
+        plo, den, printed = forms[r]
+        assert lo == plo
+        for (a, b), c in printed.items():
+            h = H[a - lo, b - lo] * (1 if a == b else 2)
+            assert Fraction(int(h.p), int(h.q)) == Fraction(c, den), (r, a, b)
+    lo, H = exact[12]
+    D, L = header_tables()[12]
+    got = expand(D, L, 12)
+    big = max(abs(Fraction(int(H[a, b].p), int(H[a, b].q))) for a in range(12) for b in range(12))
+    for a in range(12):
+        for b in range(a, 12):
+            h = H[a, b] * (1 if a == b else 2)
+            assert abs(got[(a, b)] - Fraction(int(h.p), int(h.q))) <= 2 * big * Fraction(1, 10 ** 15), (a, b)
