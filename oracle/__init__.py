@@ -84,6 +84,11 @@ def lib():
         L.or_eigen.restype = None
         L.or_eigen.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp,
                                ctypes.POINTER(ctypes.c_int32)]
+        L.or_face_fluxes.restype = ctypes.c_int
+        L.or_face_fluxes.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
+                                     ctypes.c_double, dp, dp, dp]
+        L.or_limit_face.restype = None
+        L.or_limit_face.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -180,6 +185,24 @@ def rhs(grid, U, order=10, splitting=LLF, positivity=0, gamma=1.4, dt_lim=0.0, w
     return dU, fl, mg
 
 
+def face_fluxes(grid, U, order=10, splitting=LLF, positivity=0, gamma=1.4, dt_lim=0.0):
+    """Face fluxes of every direction of the right-hand side `rhs` evaluates:
+    a list of (nvar, faces of d) arrays, faces in the flag arrays' order."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    nd = grid.ndim
+    out = []
+    for d in range(3):
+        if d < nd:
+            nf = grid.n[d] if grid.bc_lo[d] == BC_PERIODIC else grid.n[d] + 1
+            tot = nf * int(np.prod([grid.n[k] for k in range(nd) if k != d]))
+            out.append(np.zeros((nd + 2, tot)))
+    ptrs = [_dp(a) for a in out] + [None] * (3 - nd)
+    rc = lib().or_face_fluxes(ctypes.byref(grid), order, splitting, positivity, gamma, _dp(U), dt_lim, *ptrs)
+    if rc:
+        raise ValueError("oracle face_fluxes rejected its arguments (rc=%d)" % rc)
+    return out
+
+
 def rhs_cells(grid, U, cells, order=10, splitting=LLF, positivity=0, gamma=1.4, dt_lim=0.0, amax=None):
     """dU/dt at flat cell indices `cells` only; returns (len(cells), nvar)."""
     U = np.ascontiguousarray(U, dtype=np.float64)
@@ -269,6 +292,18 @@ def eigen(ndim, gamma, d, Wa, Wb):
     lib().or_eigen(ndim, gamma, d, _dp(Wa), _dp(Wb), _dp(L), _dp(R), _dp(lam),
                    perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return L, R, lam, perm
+
+
+def limit_face(ndim, gamma, d, mu, Wa, Wb, F):
+    """The positivity limiter of one face (direction d, factor mu = kappa_d
+    dt/dx_d) between conserved states Wa, Wb for the high-order flux F (all in
+    axis order); returns (limited flux, (theta_rho, theta_p))."""
+    Wa = np.ascontiguousarray(Wa, dtype=np.float64)
+    Wb = np.ascontiguousarray(Wb, dtype=np.float64)
+    out = np.array(F, dtype=np.float64)
+    th = np.zeros(2)
+    lib().or_limit_face(int(ndim), gamma, int(d), mu, _dp(Wa), _dp(Wb), _dp(out), _dp(th))
+    return out, (float(th[0]), float(th[1]))
 
 
 def decode_flag(flag):

@@ -518,8 +518,10 @@ struct Scheme {
 // pulled towards FL: first so that the density of both half-states stays
 // >= min(1e-13, rho(X(FL))), then so that their pressure stays
 // >= min(1e-13, p(X(FL))), using that pressure is concave in U.
+// `thetas`, if given, receives (theta_rho, theta_p).
 template <class T>
-void limit_face(int ndim, double gam, int d, double mu, const CellQ<T>& a, const CellQ<T>& b, T* F) {
+void limit_face(int ndim, double gam, int d, double mu, const CellQ<T>& a, const CellQ<T>& b, T* F,
+                double* thetas = nullptr) {
   const int nv = ndim + 2;
   const T sa = absT(a.u[d]) + a.c;
   const T sb = absT(b.u[d]) + b.c;
@@ -554,6 +556,10 @@ void limit_face(int ndim, double gam, int d, double mu, const CellQ<T>& a, const
     theta_p = std::min(theta_p, th);
   }
   for (int c = 0; c < nv; ++c) F[c] = (theta_p < 1.0) ? FL[c] + theta_p * (Fs[c] - FL[c]) : Fs[c];
+  if (thetas) {
+    thetas[0] = theta_r;
+    thetas[1] = theta_p;
+  }
 }
 
 // Number of faces along direction d (face f is the left face of cell f).
@@ -831,9 +837,11 @@ void load_pencil(const Grid& g, double gam, int d, int G, const T* U, int64_t ba
 
 // Semi-discrete right-hand side dU/dt = -sum_d (F_{i+1/2} - F_{i-1/2})/dx_d
 // (Sec. 2, conservative finite-difference form), directions in order x, y, z.
+// face_out[d], if given, receives the face fluxes of direction d, layout
+// [nv][faces of d] in the flag arrays' face order.
 template <class T>
 int rhs_impl(const Grid& g, const Scheme& sc, double gam, const T* U, T* dU, double dt_lim, const double* amax,
-             uint8_t* flags, double* margins, const uint8_t* frozen, int set = 0) {
+             uint8_t* flags, double* margins, const uint8_t* frozen, int set = 0, double* const* face_out = nullptr) {
   const int nd = g.ndim, nv = nd + 2, G = sc.order / 2;
   const int64_t nc = g.n[0] * g.n[1] * g.n[2];
   for (int64_t i = 0; i < nv * nc; ++i) dU[i] = T(0.0);
@@ -874,6 +882,8 @@ int rhs_impl(const Grid& g, const Scheme& sc, double gam, const T* U, T* dU, dou
           const int64_t flin = (idx[2] * m1 + idx[1]) * m0 + idx[0];
           face_flux<T>(g, sc, gam, d, cells.data() + G, f, limit ? mu[d] : 0.0, limit, foff + flin, nft, flags,
                        margins, frozen, &Fh[(size_t)f * nv]);
+          if (face_out && face_out[d])
+            for (int c = 0; c < nv; ++c) face_out[d][c * nft + flin] = re(Fh[(size_t)f * nv + c]);
         }
         for (int64_t i = 0; i < n; ++i) {
           const int64_t fr = periodic ? (i + 1) % n : i + 1;
@@ -1017,6 +1027,22 @@ int or_rhs(const or_grid* g, int order, int splitting, int positivity, double ga
 // dU/dt at the listed cells only (flat cell indices), written to out[k*nv + c].
 // amax (wave speeds of the whole state, for the limiter) may be null when the
 // limiter is off.  Used to check full-size results at sampled cells.
+// Face fluxes of every direction for the right-hand side or_rhs would
+// evaluate: F[d] (nv x faces of d, flag-array face order) for d < ndim.
+int or_face_fluxes(const or_grid* g, int order, int splitting, int positivity, double gam, const double* U,
+                   double dt_lim, double* F0, double* F1, double* F2) {
+  build_beta_tables();
+  Grid G = to_grid(g);
+  Scheme s{order, splitting, positivity};
+  if (check_grid(G, s)) return -1;
+  double amax[3];
+  wave_speeds(G, gam, U, amax);
+  const int64_t nc = G.n[0] * G.n[1] * G.n[2];
+  std::vector<double> dU((size_t)(G.ndim + 2) * nc);
+  double* fo[3] = {F0, F1, F2};
+  return rhs_impl<double>(G, s, gam, U, dU.data(), dt_lim, amax, nullptr, nullptr, nullptr, 0, fo);
+}
+
 int or_rhs_cells(const or_grid* g, int order, int splitting, int positivity, double gam, const double* U,
                  double dt_lim, const double* amax, int64_t ncells, const int64_t* cells, double* out) {
   build_beta_tables();
@@ -1182,6 +1208,18 @@ void or_eigen(int ndim, double gam, int d, const double* Wa, const double* Wb, d
   }
   // speeds at the Roe state: the normal-momentum row of R holds u_n - c, u_n, u_n + c
   for (int s = 0; s < nv; ++s) lam[s] = (s == 0) ? e.R[1][0] : (s == nv - 1) ? e.R[1][nv - 1] : e.R[1][1];
+}
+
+// The positivity limiter of one face of direction d between the cells of
+// conserved states Wa (left) and Wb (right), axis order, with factor mu =
+// kappa_d dt / dx_d: F (axis order) holds the high-order flux on entry and the
+// limited flux on return; thetas receives (theta_rho, theta_p).
+void or_limit_face(int ndim, double gam, int d, double mu, const double* Wa, const double* Wb, double* F,
+                   double* thetas) {
+  CellQ<double> a, b;
+  cell_state(ndim, gam, d, Wa, a);
+  cell_state(ndim, gam, d, Wb, b);
+  limit_face<double>(ndim, gam, d, mu, a, b, F, thetas);
 }
 
 }  // extern "C"
