@@ -133,23 +133,19 @@ __device__ __forceinline__ double gamma7(double beta) {
 }
 
 // Smoothness indicator of a large stencil of width R whose leftmost value is
-// v[P]: the exact sum of squares in the forward-difference basis.
+// v[P]: the exact sum of squares beta = sum_k D[k] y_k^2 over the stencil's
+// first differences d_m = f_{P+m+1} - f_{P+m}, y_k = sum_{m >= k} L[m][k] d_m.
+// The differences are the ones the cut-off's eta and the other indicators
+// use (the compiler computes each once).
 template <int R, int P, int W>
 __device__ __forceinline__ double sos_beta(const double (&v)[W]) {
   static_assert(R == 6 || R == 8 || R == 10 || R == 12, "large stencils only");
-  double lev[R];
-  unroll<R>([&](auto q) { lev[q] = v[P + q]; });
-  double dif[R - 1];  // Delta^{m+1} f_P
-  unroll<R - 1>([&](auto mm) {
-    constexpr int m = decltype(mm)::value;
-    unroll<R - 1 - m>([&](auto q) { lev[q] = lev[q + 1] - lev[q]; });
-    dif[m] = lev[0];
-  });
+  double dif[R - 1];
+  unroll<R - 1>([&](auto m) { dif[m] = v[P + m + 1] - v[P + m]; });
   double beta = 0.0;
   unroll<R - 1>([&](auto kk) {
     constexpr int k = decltype(kk)::value;
-    // y_k = sum_{m >= k} L[m][k] dif[m]; L has a unit diagonal, so the sum
-    // starts from dif[k] itself (no addition of a zero)
+    // L has a unit diagonal, so the sum starts from d_k itself (no product by 1)
     constexpr double lkk = (R == 12)   ? SOS_S6_L[k][k]
                            : (R == 10) ? SOS_S5_L[k][k]
                            : (R == 8)  ? SOS_S4_L[k][k]
@@ -194,9 +190,13 @@ __device__ __forceinline__ double linear_flux(const double (&v)[W]) {
 // v[0..W-1] = f_{i-G+1..i+G}, ORDER = W = 8, 10 or 12 (TENO12-AA: the
 // framework with the twelve-point stencil S6 above S5).  Returns
 // fhat_{i+1/2}; flag gets the decision byte (bits 0-1 large stencil, with
-// bit 2 set for S6; 2-4 deltas of the fallback; 5-7 K-7).
-template <int ORDER>
-__device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& flag) {
+// bit 2 set for S6; 2-4 deltas of the fallback; 5-7 K-7).  With AUDIT, near
+// gets 1 if a test the reconstruction made lies within the relative distance
+// tol of its threshold (chi_p / C_T or chi_k / C_T within 1 +- tol, or the
+// cut-off exponent B within tol B of an integer while m > 0), else 0.
+template <int ORDER, bool AUDIT = false>
+__device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& flag, uint8_t* near = nullptr,
+                                          double tol = 0.0) {
   constexpr int G = ORDER / 2;
   constexpr int I = G - 1;  // index of f_i
 
@@ -228,6 +228,9 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   K = K < 7 ? 7 : (K > 14 ? 14 : K);
   const double CT = CT_TABLE[K - 7];
   const uint8_t kbits = (uint8_t)((K - 7) << 5);
+  // chi / C_T - 1 = (g - t) / t for the test g >= t
+  [[maybe_unused]] auto close = [&](double g, double t) { return fabs(g - t) <= tol * t; };
+  if constexpr (AUDIT) *near = (m > 0.0 && fabs(B - rint(B)) <= tol * B) ? 1 : 0;
 
   // small stencils (Sec. 4.2, printed WENO-JS indicators) in difference form
   const double b0a = dd[1] + dd[2];                // f_{i+1} - f_{i-1}
@@ -246,6 +249,7 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   // chi_p = gamma_p / (S + gamma_p) >= C_T.  Stencil Sp starts at v[G - p].
   if constexpr (ORDER == 12) {
     const double gp = gamma7(sos_beta<12, 0>(v));
+    if constexpr (AUDIT) *near |= close(gp, CT * (S + gp)) ? 1 : 0;
     if (gp >= CT * (S + gp)) {
       flag = (uint8_t)(7 | kbits);
       return linear_flux<12, 0>(v);
@@ -254,6 +258,7 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   if constexpr (ORDER >= 10) {
     constexpr int P = G - 5;
     const double gp = gamma7(sos_beta<10, P>(v));
+    if constexpr (AUDIT) *near |= close(gp, CT * (S + gp)) ? 1 : 0;
     if (gp >= CT * (S + gp)) {
       flag = (uint8_t)(3 | kbits);
       return linear_flux<10, P>(v);
@@ -262,6 +267,7 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   {
     constexpr int P = G - 4;
     const double gp = gamma7(sos_beta<8, P>(v));
+    if constexpr (AUDIT) *near |= close(gp, CT * (S + gp)) ? 1 : 0;
     if (gp >= CT * (S + gp)) {
       flag = (uint8_t)(2 | kbits);
       return linear_flux<8, P>(v);
@@ -270,6 +276,7 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   {
     constexpr int P = G - 3;
     const double gp = gamma7(sos_beta<6, P>(v));
+    if constexpr (AUDIT) *near |= close(gp, CT * (S + gp)) ? 1 : 0;
     if (gp >= CT * (S + gp)) {
       flag = (uint8_t)(1 | kbits);
       return linear_flux<6, P>(v);
@@ -277,6 +284,7 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   }
   // fallback: TENO5 cut-off among the small stencils (Sec. 3.3)
   const double cs = CT * S;
+  if constexpr (AUDIT) *near |= (close(g0, cs) || close(g1, cs) || close(g2, cs)) ? 1 : 0;
   const int dm = (g0 >= cs ? 1 : 0) | (g1 >= cs ? 2 : 0) | (g2 >= cs ? 4 : 0);
   flag = (uint8_t)((dm << 2) | kbits);
   const double fm1 = v[I - 1], f0 = v[I], f1 = v[I + 1];

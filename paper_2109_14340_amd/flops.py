@@ -8,26 +8,26 @@ minimum, the sums of squares of the large-stencil indicators) and only the
 work on the path a face actually takes: a large stencil's indicator is
 counted only when the cascade reaches it.  Products by a coefficient that is
 0 or 1 (the unit diagonal of the sum-of-squares factors, the zero and unit
-entries of the shear fields' eigenvectors) are not counted, nor is a
-difference the indicators share with the cut-off's eta.  Per-cell work
+entries of the shear fields' eigenvectors) are not counted, and a first
+difference is counted once however many indicators use it.  Per-cell work
 (primitives, physical flux, the split's factor 1/2) is counted once per cell
 and direction, not per halo copy.
 """
 
 # non-zero entries below the unit diagonal of the sum-of-squares factors
 # (tenoaa_sos.h): stencil width -> count
-SOS_NNZ = {12: 50, 10: 32, 8: 18, 6: 8}
+SOS_NNZ = {12: 55, 10: 36, 8: 21, 6: 10}
 
 # first differences f_{j+1} - f_j, j = -2..2, that the cut-off's eta and the
-# small-stencil indicators use and the first large indicator's difference
-# table contains
+# small-stencil indicators use; the first (largest) large stencil's first
+# differences contain them, and every nested stencil's are among its
 SHARED_DIFFS = 5
 
 
 def sos_cost(r, shared=0):
-    """Difference table + factor products + weighted squares of one indicator
+    """First differences + factor products + weighted squares of one indicator
     (`shared` first differences already computed)."""
-    return r * (r - 1) // 2 - shared + 2 * SOS_NNZ[r] + 3 * (r - 1)
+    return (r - 1) - shared + 2 * SOS_NNZ[r] + 3 * (r - 1)
 
 
 ETA_CT = 40 + 11        # eta_j, their minimum, m, g(m), [beta]
@@ -46,7 +46,7 @@ def scalar_cost(order, sel):
     sel_r = {6: 12, 5: 10, 4: 8, 3: 6}.get(sel, 0)
     c = ETA_CT + SMALL
     for k, r in enumerate(large_stencils(order)):
-        c += sos_cost(r, SHARED_DIFFS if k == 0 else 0) + TEST
+        c += sos_cost(r, SHARED_DIFFS if k == 0 else r - 1) + TEST
         if r == sel_r:
             return c + FLUX[r]
     return c + FALLBACK

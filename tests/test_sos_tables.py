@@ -1,13 +1,13 @@
-"""The kernels' smoothness-indicator tables (csrc/tenoaa_sos.h) against the
-paper: the header is what its generator writes, its sums of squares expand to
-the quadratic forms printed in Sec. 4.2 (tests/golden/beta_printed.txt), and
-the operation count of the roofline (flops.SOS_NNZ) is the number of their
-non-zero off-diagonal factors.  CPU only."""
+"""The kernels' smoothness-indicator tables (csrc/tenoaa_sos.h: sums of
+squares over the stencil's first differences) against the paper: the header is
+what its generator writes, its sums of squares expand to the quadratic forms
+printed in Sec. 4.2 (tests/golden/beta_printed.txt), and the operation count of
+the roofline (flops.SOS_NNZ) is the number of their non-zero off-diagonal
+factors.  CPU only."""
 import os
 import re
 import sys
 from fractions import Fraction
-from math import comb
 
 import pytest
 
@@ -53,13 +53,13 @@ def printed_forms():
 
 def expand(D, L, r):
     """Exact coefficients of f_a f_b (a <= b, indices 0..r-1 from the stencil's
-    leftmost cell) of sum_k D_k (sum_{m >= k} L_mk Delta^{m+1} f_0)^2, with the
-    table's doubles taken exactly."""
+    leftmost cell) of sum_k D_k (sum_{m >= k} L_mk d_m)^2, d_m = f_{m+1} - f_m,
+    with the table's doubles taken exactly."""
     n = r - 1
     Dq = [Fraction(x) for x in D]
     Lq = [[Fraction(x) for x in row] for row in L]
-    # Delta^{m+1} f_0 = sum_j (-1)^{m+1-j} C(m+1, j) f_j
-    dif = [[Fraction((-1) ** (m + 1 - j) * comb(m + 1, j)) if j <= m + 1 else Fraction(0) for j in range(r)]
+    # d_m = f_{m+1} - f_m
+    dif = [[Fraction(1) if j == m + 1 else (Fraction(-1) if j == m else Fraction(0)) for j in range(r)]
            for m in range(n)]
     coef = {}
     for k in range(n):
