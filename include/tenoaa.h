@@ -265,6 +265,27 @@ enum { TENOAA_FLAGS_NONE = 0, TENOAA_FLAGS_RECORD = 1, TENOAA_FLAGS_REPLAY = 2 }
 int tenoaa_step_flags(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,
                       double* dt_dev, uint8_t* flags3, int32_t mode, void* ws, size_t ws_bytes, void* stream);
 
+/* tenoaa_step with every threshold decision (Sec. 3.3 selection cascade and
+ * its fallback deltas, Sec. 3.4 cut-off bucket) audited for its distance to
+ * the threshold: the finite-difference check of the adjoint freezes only the
+ * decisions near a threshold and takes the others live.  All arrays are
+ * device arrays of 3 x the flag-array size (stage-major, the flag layout
+ * above), one byte per reconstruction:
+ *   near_in3 (or NULL): where non-zero the reconstruction replays the byte of
+ *     base3 (required with near_in3) instead of deciding; elsewhere, and
+ *     everywhere with NULL, it decides live;
+ *   flags_out3 (or NULL): the decision bytes used (live or replayed);
+ *   near_out3 (or NULL): 1 where a live decision made a test within the
+ *     relative distance near_tol of its threshold (chi_p / C_T or chi_k / C_T
+ *     within 1 +- near_tol, or the cut-off exponent within near_tol of an
+ *     integer), 1 for a replayed one, else 0.
+ * dt_dev as in tenoaa_step (> 0: used as given).  0 < near_tol < 1; LLF or
+ * Rusanov splitting (TENOAA_EUNSUPPORTED for the Roe flux); other errors as
+ * tenoaa_step.  Workspace: STEP. */
+int tenoaa_step_near(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,
+                     double* dt_dev, const uint8_t* base3, const uint8_t* near_in3, uint8_t* flags_out3,
+                     uint8_t* near_out3, double near_tol, void* ws, size_t ws_bytes, void* stream);
+
 /* Scalar linear advection u_t + u_x = 0 on a periodic grid of n cells of
  * width dx (Sec. 5.1, the paper's accuracy test): `nsteps` SSP-RK3 steps of
  * size dt of du_i/dt = -(fhat_{i+1/2} - fhat_{i-1/2}) / dx, where fhat_{i+1/2}

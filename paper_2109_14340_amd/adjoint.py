@@ -81,3 +81,32 @@ def replay_trajectory(U0, grid, scheme, dts, flags, gamma=1.4):
     for n in range(dts.numel()):
         tenoaa.step_flags(grid, scheme, U, dts[n:n + 1], flags[n], tenoaa.FLAGS_REPLAY, gamma=gamma, ws=ws)
     return U
+
+
+def record_trajectory_near(U0, grid, scheme, nsteps, tol=1e-3, gamma=1.4, cfl=0.4):
+    """Forward run recording each step's dt, the decisions of every stage and
+    which of them lie within `tol` (relative) of a threshold: returns
+    (U_final, dts, flags, near), flags and near of shape (nsteps, 3 * flags_size)."""
+    U = U0.detach().clone()
+    ws = tenoaa.workspace(grid, scheme, tenoaa.WS_STEP, U.device)
+    nfl = tenoaa.flags_size(grid)
+    dts = torch.zeros(nsteps, dtype=torch.float64, device=U.device)
+    flags = torch.zeros((nsteps, 3 * nfl), dtype=torch.uint8, device=U.device)
+    near = torch.zeros((nsteps, 3 * nfl), dtype=torch.uint8, device=U.device)
+    for n in range(nsteps):
+        tenoaa.step_near(grid, scheme, U, dts[n:n + 1], flags_out3=flags[n], near_out3=near[n], tol=tol,
+                         gamma=gamma, cfl=cfl, ws=ws)
+    return U, dts, flags, near
+
+
+def near_replay_trajectory(U0, grid, scheme, dts, flags, near, tol=1e-3, gamma=1.4):
+    """Forward run with the recorded dt of every step, the decisions that
+    `near` marks replayed from `flags` and every other decision taken live:
+    returns (U_final, flags_used)."""
+    U = U0.detach().clone()
+    ws = tenoaa.workspace(grid, scheme, tenoaa.WS_STEP, U.device)
+    used = torch.empty_like(flags)
+    for n in range(dts.numel()):
+        tenoaa.step_near(grid, scheme, U, dts[n:n + 1], base3=flags[n], near_in3=near[n], flags_out3=used[n],
+                         tol=tol, gamma=gamma, ws=ws)
+    return U, used

@@ -7,8 +7,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtenoaa.so")
-SOURCES = ["tenoaa_kernels.hip", "tenoaa_tail.hip", "tenoaa_adjoint.hip", "tenoaa_adjoint_general.hip",
-           "tenoaa_adjoint_tail.hip", "tenoaa_batch.hip", "tenoaa_advect.hip", "tenoaa_capi.hip"]
+SOURCES = ["tenoaa_kernels.hip", "tenoaa_tail.hip", "tenoaa_audit.hip", "tenoaa_adjoint.hip",
+           "tenoaa_adjoint_general.hip", "tenoaa_adjoint_tail.hip", "tenoaa_batch.hip", "tenoaa_advect.hip",
+           "tenoaa_capi.hip"]
 HEADERS = ["tenoaa_internal.h", "tenoaa_sos.h", "tenoaa_device.h", "tenoaa_stencil.h", "tenoaa_vjp.h"]
 
 FLAGS = [

@@ -220,10 +220,22 @@ hipError_t wave_speeds(const Ctx& c, const double* U) {
   return e;
 }
 
+// Near-threshold audit of a step's sweeps (tenoaa_step_near): arrays in the
+// flag layout of one right-hand side.
+struct Audit {
+  const uint8_t* base = nullptr;     // recorded decisions, replayed where near_in is set
+  const uint8_t* near_in = nullptr;  // or null: every decision live
+  uint8_t* flags_out = nullptr;      // decisions used, or null
+  uint8_t* near_out = nullptr;       // 1 = within tol of a threshold (or replayed), or null
+  double tol = 0.0;
+};
+
 // Face fluxes of every direction for state U; flags optional.  `stage`
-// selects the Dirichlet value set.
+// selects the Dirichlet value set.  With `audit` the audit sweep runs instead
+// (flags and frozen are then taken from it).
 int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint8_t* frozen = nullptr,
-           int only_dir = -1, double* fh_out = nullptr, int stage = 0, double* theta_out = nullptr) {
+           int only_dir = -1, double* fh_out = nullptr, int stage = 0, double* theta_out = nullptr,
+           const Audit* audit = nullptr) {
   const tenoaa_grid* g = c.g;
   const int nv = g->ndim + 2;
   int64_t flag_off = 0;
@@ -252,8 +264,17 @@ int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint
     a.gamma = c.gamma;
     a.mu = c.S->mu;
     a.status = &c.S->status;
-    hipError_t e = timed(TENOAA_KCLASS_SWEEP_X + d, c.st,
-                         [&] { return tenoaa::launch_sweep(c.s->order, g->ndim, d, a, limit, c.st); });
+    if (audit) {
+      a.frozen = audit->base ? audit->base + fo : nullptr;
+      a.flags = audit->flags_out ? audit->flags_out + fo : nullptr;
+      a.near_in = audit->near_in ? audit->near_in + fo : nullptr;
+      a.near_out = audit->near_out ? audit->near_out + fo : nullptr;
+      a.near_tol = audit->tol;
+    }
+    hipError_t e = timed(TENOAA_KCLASS_SWEEP_X + d, c.st, [&] {
+      return audit ? tenoaa::launch_sweep_audit(c.s->order, g->ndim, d, a, limit, c.st)
+                   : tenoaa::launch_sweep(c.s->order, g->ndim, d, a, limit, c.st);
+    });
     if (e != hipSuccess) return hip_fail(e);
     flag_off += (int64_t)nv * 2 * a.nft;
   }
@@ -355,6 +376,23 @@ int prepare(Ctx& c, const tenoaa_grid* g, const tenoaa_scheme* s, double gamma, 
 // First device work of an entry point, after every argument check passed.
 int begin(const Ctx&) { return TENOAA_OK; }
 
+// One right-hand side (tenoaa_rhs after its argument checks).
+int rhs_body(const Ctx& c, const double* U, double* dUdt, double dt_limiter, uint8_t* flags) {
+  const tenoaa_grid* grid = c.g;
+  const bool limit = c.s->positivity && dt_limiter > 0.0;
+  if (limit) {
+    hipError_t e = timed(TENOAA_KCLASS_WAVESPEED, c.st, [&] {
+      hipError_t r = wave_speeds(c, U);
+      if (r == hipSuccess) r = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, 1.0, nullptr, dt_limiter, c.st);
+      return r;
+    });
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  int rc = sweeps(c, U, limit, flags);
+  if (rc) return rc;
+  return update(c, 0, nullptr, nullptr, dUdt);
+}
+
 }  // namespace
 
 namespace tenoaa {
@@ -383,19 +421,7 @@ int tenoaa_rhs(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamm
   if (rc) return rc;
   if (!U || !dUdt || U == dUdt) return TENOAA_EINVAL;
   if ((rc = begin(c))) return rc;
-  const bool limit = scheme->positivity && dt_limiter > 0.0;
-  const int64_t ncell = grid->n[0] * grid->n[1] * grid->n[2];
-  if (limit) {
-    hipError_t e = timed(TENOAA_KCLASS_WAVESPEED, c.st, [&] {
-      hipError_t r = wave_speeds(c, U);
-      if (r == hipSuccess) r = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, 1.0, nullptr, dt_limiter, c.st);
-      return r;
-    });
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  rc = sweeps(c, U, limit, flags);
-  if (rc) return rc;
-  return update(c, 0, nullptr, nullptr, dUdt);
+  return rhs_body(c, U, dUdt, dt_limiter, flags);
 }
 
 int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,
@@ -435,6 +461,46 @@ int tenoaa_step_flags(const tenoaa_grid* grid, const tenoaa_scheme* scheme, doub
   if ((rc = update(c, 2, U, Us, Us))) return rc;
   // stage 3: U = 1/3 Un + 2/3 U2 + 2/3 dt L(U2)    -> U (in place)
   if ((rc = sweeps(c, Us, limit, rec(2), rep(2), -1, nullptr, 2))) return rc;
+  return update(c, 3, U, Us, U);
+}
+
+int tenoaa_step_near(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,
+                     double* dt_dev, const uint8_t* base3, const uint8_t* near_in3, uint8_t* flags_out3,
+                     uint8_t* near_out3, double near_tol, void* ws, size_t ws_bytes, void* stream) {
+  Ctx c;
+  int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP);
+  if (rc) return rc;
+  if (!U || !dt_dev) return TENOAA_EINVAL;
+  if (!(cfl > 0.0) || cfl > 1.0) return TENOAA_EINVAL;
+  if (scheme->positivity && cfl > 0.5) return TENOAA_EINVAL;
+  if (!(near_tol > 0.0) || !(near_tol < 1.0)) return TENOAA_EINVAL;
+  if (near_in3 && !base3) return TENOAA_EINVAL;
+  if (scheme->splitting == TENOAA_ROE) return TENOAA_EUNSUPPORTED;
+  if ((rc = begin(c))) return rc;
+  double* Us = reinterpret_cast<double*>(c.ws + c.L.stage);
+  const int64_t nfl = flag_count(grid);
+  auto audit = [&](int st) {
+    Audit a;
+    a.base = base3 ? base3 + st * nfl : nullptr;
+    a.near_in = near_in3 ? near_in3 + st * nfl : nullptr;
+    a.flags_out = flags_out3 ? flags_out3 + st * nfl : nullptr;
+    a.near_out = near_out3 ? near_out3 + st * nfl : nullptr;
+    a.tol = near_tol;
+    return a;
+  };
+  const bool limit = scheme->positivity != 0;
+  hipError_t e = timed(TENOAA_KCLASS_WAVESPEED, c.st, [&] {
+    hipError_t r = wave_speeds(c, U);
+    if (r == hipSuccess) r = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, cfl, dt_dev, 0.0, c.st);
+    return r;
+  });
+  if (e != hipSuccess) return hip_fail(e);
+  const Audit a0 = audit(0), a1 = audit(1), a2 = audit(2);
+  if ((rc = sweeps(c, U, limit, nullptr, nullptr, -1, nullptr, 0, nullptr, &a0))) return rc;
+  if ((rc = update(c, 1, U, nullptr, Us))) return rc;
+  if ((rc = sweeps(c, Us, limit, nullptr, nullptr, -1, nullptr, 1, nullptr, &a1))) return rc;
+  if ((rc = update(c, 2, U, Us, Us))) return rc;
+  if ((rc = sweeps(c, Us, limit, nullptr, nullptr, -1, nullptr, 2, nullptr, &a2))) return rc;
   return update(c, 3, U, Us, U);
 }
 

@@ -38,6 +38,13 @@ struct SweepArgs {
   const double* bcv[2] = {nullptr, nullptr};  // boundary (Dirichlet, inflow, halo) values of the low/high side, this evaluation's set, or null
   const double* mu = nullptr;  // device: limiter factors
   int* status = nullptr;       // device: status word
+  // near-threshold audit (the audit sweep only): decisions whose byte in
+  // near_in is non-zero replay `frozen`, the others are taken live; near_out
+  // receives 1 where a live decision came within near_tol (relative) of one
+  // of its thresholds, and 1 for a replayed one
+  const uint8_t* near_in = nullptr;
+  uint8_t* near_out = nullptr;
+  double near_tol = 0.0;
 };
 
 struct UpdateArgs {
@@ -104,6 +111,10 @@ hipError_t launch_axpbypcz(double* out, double a, const double* x, double b, con
 hipError_t launch_axpdtz(double* out, double a, const double* x, double c, const double* dt, const double* z,
                          int64_t n, hipStream_t st);
 hipError_t launch_sweep(int order, int ndim, int dir, const SweepArgs& a, bool limit, hipStream_t st);
+// The audit sweep (LLF or Rusanov): decisions replayed where a.near_in says,
+// taken live elsewhere, with their distance to the thresholds reported in
+// a.near_out; whole tiles over every face of the direction.
+hipError_t launch_sweep_audit(int order, int ndim, int dir, const SweepArgs& a, bool limit, hipStream_t st);
 hipError_t launch_update(int ndim, int mode, const UpdateArgs& a, hipStream_t st);
 hipError_t launch_wave_speeds(int ndim, const double* U, int64_t ncell, double gam, Scalars* S, int* status,
                               hipStream_t st);

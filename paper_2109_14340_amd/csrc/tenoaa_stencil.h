@@ -109,13 +109,17 @@ __device__ __forceinline__ void inflow_ghost(double* W, const double* pv, int64_
 // consecutive tiles that reuse it with a barrier.  `mu` is the limiter factor
 // of this direction (used when LIMIT).  ROE selects the Roe flux with entropy
 // fix (SPLIT = TENOAA_ROE); SPLIT = TENOAA_LLF or TENOAA_RUSANOV fixes the
-// flux splitting, SPLIT_RUNTIME takes it from A.splitting.
-template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT, int SPLIT = SPLIT_RUNTIME>
+// flux splitting, SPLIT_RUNTIME takes it from A.splitting.  AUDIT (LLF or
+// Rusanov only) takes each decision live unless A.near_in marks it, replays
+// A.frozen where it does, and reports in A.near_out which live decisions lie
+// within A.near_tol of a threshold.
+template <int ORDER, int NDIM, int DIR, int TT, int TN, bool LIMIT, int SPLIT = SPLIT_RUNTIME, bool AUDIT = false>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_t bx, int64_t by, int64_t bz,
                                            double mu) {
   static_assert(SPLIT == SPLIT_RUNTIME || SPLIT == TENOAA_LLF || SPLIT == TENOAA_RUSANOV || SPLIT == TENOAA_ROE,
                 "unknown splitting");
   constexpr bool ROE = SPLIT == TENOAA_ROE;
+  static_assert(!(AUDIT && ROE), "the audit sweep splits the fluxes");
   using Sh = SweepShape<ORDER, NDIM, TT, TN>;
   constexpr int G = ORDER / 2;
   constexpr int W = ORDER;
@@ -406,7 +410,29 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     });
     uint8_t flp = 0, flm = 0;
     double hp, hm;
-    if (frozen) {
+    if constexpr (AUDIT) {
+      // live decisions except where near_in marks a replayed one
+      const int64_t op = (int64_t)(s * 2 + 0) * A.nft, om = (int64_t)(s * 2 + 1) * A.nft;
+      const uint8_t* nin = A.near_in ? A.near_in + flin : nullptr;
+      uint8_t np = 1, nm = 1;
+      if (nin && nin[op]) {
+        flp = frozen[op];
+        hp = replay_recon<ORDER>(gp, flp);
+      } else {
+        hp = teno_aa<ORDER, true>(gp, flp, &np, A.near_tol);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (nin && nin[om]) {
+        flm = frozen[om];
+        hm = replay_recon<ORDER>(gm, flm);
+      } else {
+        hm = teno_aa<ORDER, true>(gm, flm, &nm, A.near_tol);
+      }
+      if (A.near_out) {
+        A.near_out[flin + op] = np;
+        A.near_out[flin + om] = nm;
+      }
+    } else if (frozen) {
       // replay recorded decisions
       flp = frozen[(int64_t)(s * 2 + 0) * A.nft];
       flm = frozen[(int64_t)(s * 2 + 1) * A.nft];

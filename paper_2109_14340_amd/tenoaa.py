@@ -23,7 +23,7 @@ EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_step_f
            "tenoaa_get_status", "tenoaa_last_hip_error", "tenoaa_timing_enable", "tenoaa_timing_read",
            "tenoaa_batch_plan_create", "tenoaa_batch_offsets", "tenoaa_batch_run", "tenoaa_batch_get_status",
            "tenoaa_batch_plan_info", "tenoaa_batch_plan_destroy", "tenoaa_advect", "tenoaa_wave_speeds",
-           "tenoaa_rk3_stage", "tenoaa_rhs_vjp_halo"]
+           "tenoaa_rk3_stage", "tenoaa_rhs_vjp_halo", "tenoaa_step_near"]
 KCLASS_SWEEP = (0, 1, 2)
 KCLASS_UPDATE, KCLASS_WAVESPEED = 3, 4
 KCLASS_VJP = (5, 6, 7)
@@ -65,6 +65,9 @@ def load():
         L.tenoaa_step_flags.restype = ctypes.c_int
         L.tenoaa_step_flags.argtypes = [gp, sp, ctypes.c_double, ctypes.c_double, vp, vp, vp, ctypes.c_int32, vp,
                                         ctypes.c_size_t, vp]
+        L.tenoaa_step_near.restype = ctypes.c_int
+        L.tenoaa_step_near.argtypes = [gp, sp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp, vp,
+                                       ctypes.c_double, vp, ctypes.c_size_t, vp]
         L.tenoaa_rhs_vjp.restype = ctypes.c_int
         L.tenoaa_rhs_vjp.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.tenoaa_step_vjp.restype = ctypes.c_int
@@ -350,6 +353,28 @@ def step_flags(grid, scheme, U, dt_dev, flags3, mode, gamma=1.4, cfl=0.4, ws=Non
     rc = load().tenoaa_step_flags(ctypes.byref(grid), ctypes.byref(scheme), gamma, cfl, _ptr(U), _ptr(dt_dev),
                                   _ptr(flags3), mode, _ptr(ws), ws.numel(), _stream())
     _check(rc, "tenoaa_step_flags")
+    return U
+
+
+def step_near(grid, scheme, U, dt_dev, base3=None, near_in3=None, flags_out3=None, near_out3=None, tol=1e-3,
+              gamma=1.4, cfl=0.4, ws=None):
+    """tenoaa_step with its decisions audited: replayed from base3 where
+    near_in3 is non-zero, live elsewhere; the decisions used go to flags_out3
+    and the live ones within `tol` of a threshold are marked in near_out3
+    (all uint8, 3 * flags_size(grid), or None)."""
+    _check_state(U, grid)
+    _check_boundary_values(grid, scheme)
+    nfl = 3 * flags_size(grid)
+    for a in (base3, near_in3, flags_out3, near_out3):
+        if a is not None and (a.dtype != _torch().uint8 or a.numel() != nfl or not a.is_contiguous()):
+            raise TenoaaError("decision arrays must be contiguous uint8 of 3 x flags_size(grid)")
+    if ws is None:
+        ws = workspace(grid, scheme, WS_STEP, U.device)
+    opt = lambda a: _ptr(a) if a is not None else None  # noqa: E731
+    rc = load().tenoaa_step_near(ctypes.byref(grid), ctypes.byref(scheme), gamma, cfl, _ptr(U), _ptr(dt_dev),
+                                 opt(base3), opt(near_in3), opt(flags_out3), opt(near_out3), tol, _ptr(ws),
+                                 ws.numel(), _stream())
+    _check(rc, "tenoaa_step_near")
     return U
 
 
