@@ -133,9 +133,14 @@ def test_shock_tube_100_steps_synchronised():
         U_g, dt_g, st = _step_gpu(U, (256,), [1], 8, 0)
         assert st == 0 and dt_g == dt_or
         scale = np.abs(U_next).reshape(3, -1).max(axis=1)
-        err = (np.abs(U_g - U_next).reshape(3, -1).max(axis=1) / scale).max()
-        if (mg <= 1e-12).sum() == 0:
-            assert err <= 1e-11, (k, err)
+        # a decision within the near band of a threshold (any stage) may
+        # legitimately differ: leave out the cells its face reaches within the
+        # step (three stages of the stencil's half-width)
+        keep = np.ones(256, bool)
+        for f in np.nonzero((mg.reshape(3, -1) <= 1e-12).any(axis=0))[0] % 257:
+            keep[max(0, f - 15):min(256, f + 15)] = False
+        err = (np.abs(U_g - U_next).reshape(3, -1)[:, keep].max(axis=1) / scale).max()
+        assert err <= 1e-11, (k, err)
         worst = max(worst, err)
         same += int((U_g == U_next).all())
         U = U_next
@@ -171,22 +176,9 @@ def test_full_2d_1024_sampled(order):
     assert err <= 1e-11
 
 
-def test_full_3d_256_sampled_and_step_composition():
-    """3D 256^3 blast/cavity workload, TENO10-AA, limiter on: sampled RHS cells
-    against the oracle, and tenoaa_step equal to the SSP-RK3 composition of
-    tenoaa_rhs calls on the same device."""
-    U = inputs.grf_3d(256)
-    g_or, g_gpu = _pair((256, 256, 256), [0, 0, 0])
-    amax = oracle.wave_speeds(g_or, 1.4, U)
-    dt = oracle.dt(g_or, 1.4, 0.4, U)
-    sch = tenoaa.make_scheme(10, 0, 1)
-    Ud = _dev(U)
-    del U
-    out = tenoaa.rhs(g_gpu, sch, Ud, dt_limiter=dt)
-    d = tenoaa.to_numpy(out).reshape(5, -1)
-    Uh = tenoaa.to_numpy(Ud)
-    # sampled cells: random plus the two spheres' surfaces
-    n = 256
+def _stage_cells(n):
+    """Sampled cells of the 3D workload: random ones plus cells on the blast
+    and cavity spheres' surfaces."""
     x = (np.arange(n) + 0.5) / n
     cells = [_sample_cells(n ** 3, 150, 5)]
     for cx in (0.3, 0.7):
@@ -194,25 +186,95 @@ def test_full_3d_256_sampled_and_step_composition():
         rng = np.random.default_rng(int(cx * 10))
         k = rng.integers(0, ii.size, (60, 3))
         cells.append((ii[k[:, 2]] * n + (n // 2)) * n + ii[k[:, 0]])
-    cells = np.unique(np.concatenate(cells))
-    ref = oracle.rhs_cells(g_or, Uh, cells, order=10, positivity=1, dt_lim=dt, amax=amax)
+    return np.unique(np.concatenate(cells))
+
+
+def test_full_3d_256_step_stages_sampled():
+    """3D 256^3 blast/cavity workload, TENO10-AA, LLF, limiter on, one SSP-RK3
+    step at CFL 0.4 (Sec. 5): tenoaa_step equals its three stages taken by
+    tenoaa_rk3_stage bit for bit, and each stage's new state at sampled cells
+    equals the Shu-Osher combination of the oracle's right-hand side of that
+    stage's input (the GPU's stage state: stage-synchronised), with the
+    limiter factors from the step's dt and wave speeds."""
+    n = 256
+    U = inputs.grf_3d(n)
+    g_or, g_gpu = _pair((n, n, n), [0, 0, 0])
+    amax_or = oracle.wave_speeds(g_or, 1.4, U)
+    dt_or = oracle.dt(g_or, 1.4, 0.4, U)
+    sch = tenoaa.make_scheme(10, 0, 1)
+    U0 = _dev(U)
+    del U
+    # the whole step
+    Us_ = U0.clone()
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = tenoaa.workspace(g_gpu, sch, tenoaa.WS_STEP)
+    tenoaa.step(g_gpu, sch, Us_, dts, cfl=0.4, ws=ws)
+    torch.cuda.synchronize()
+    assert float(dts.item()) == dt_or
+    assert tenoaa.get_status(ws) == 0
+    # the same step stage by stage
+    wsr = tenoaa.workspace(g_gpu, sch, tenoaa.WS_RHS)
+    amax = tenoaa.wave_speeds(g_gpu, sch, U0, ws=wsr)
+    assert np.array_equal(tenoaa.to_numpy(amax), amax_or[:3])
+    dtg = torch.zeros(1, dtype=torch.float64, device="cuda")
+    S1 = torch.empty_like(U0)
+    S2 = torch.empty_like(U0)
+    S3 = torch.empty_like(U0)
+    tenoaa.rk3_stage(g_gpu, sch, 1, amax, dtg, U0, None, S1, ws=wsr)
+    tenoaa.rk3_stage(g_gpu, sch, 2, amax, dtg, U0, S1, S2, ws=wsr)
+    tenoaa.rk3_stage(g_gpu, sch, 3, amax, dtg, U0, S2, S3, ws=wsr)
+    torch.cuda.synchronize()
+    assert float(dtg.item()) == dt_or
+    assert torch.equal(S3, Us_), "tenoaa_step differs from its three stages"
+    del Us_
+    cells = _stage_cells(n)
+    Un = tenoaa.to_numpy(U0).reshape(5, -1)
+    dt = dt_or
+    worst = 0.0
+    bitwise = 0
+    for stage, (src, dst) in enumerate(((U0, S1), (S1, S2), (S2, S3)), start=1):
+        Uin = tenoaa.to_numpy(src)
+        ref = oracle.rhs_cells(g_or, Uin, cells, order=10, positivity=1, dt_lim=dt, amax=amax_or).T
+        Uin = Uin.reshape(5, -1)[:, cells]
+        un = Un[:, cells]
+        if stage == 1:
+            want = un + dt * ref
+        elif stage == 2:
+            want = 0.75 * un + 0.25 * Uin + (0.25 * dt) * ref
+        else:
+            want = (1.0 / 3.0) * un + (2.0 / 3.0) * Uin + ((2.0 / 3.0) * dt) * ref
+        got = tenoaa.to_numpy(dst).reshape(5, -1)[:, cells]
+        scale = np.abs(tenoaa.to_numpy(dst).reshape(5, -1)).max(axis=1)[:, None]
+        err = float((np.abs(got - want) / scale).max())
+        worst = max(worst, err)
+        bitwise += int((got == want).sum())
+        assert err <= 1e-11, (stage, err)
+    print("3d 256 step: stage composition bitwise, %d sampled cells x 3 stages, max rel %.3e, bitwise %d of %d"
+          % (cells.size, worst, bitwise, 3 * 5 * cells.size))
+    # properties of the whole step: conservation (periodic), positivity
+    before = U0.reshape(5, -1).sum(dim=1)
+    after = S3.reshape(5, -1).sum(dim=1)
+    tot = S3.reshape(5, -1).abs().sum(dim=1)
+    assert float(((after - before).abs() / tot).max()) < 1e-13
+    rho = S3[0]
+    p = 0.4 * (S3[4] - 0.5 * (S3[1] ** 2 + S3[2] ** 2 + S3[3] ** 2) / rho)
+    assert float(rho.min()) > 0 and float(p.min()) > 0
+
+
+def test_full_3d_256_rhs_sampled():
+    """3D 256^3 blast/cavity workload, TENO10-AA, limiter on: one right-hand
+    side at sampled cells against the oracle."""
+    n = 256
+    U = inputs.grf_3d(n)
+    g_or, g_gpu = _pair((n, n, n), [0, 0, 0])
+    amax = oracle.wave_speeds(g_or, 1.4, U)
+    dt = oracle.dt(g_or, 1.4, 0.4, U)
+    sch = tenoaa.make_scheme(10, 0, 1)
+    out = tenoaa.rhs(g_gpu, sch, _dev(U), dt_limiter=dt)
+    d = tenoaa.to_numpy(out).reshape(5, -1)
+    cells = _stage_cells(n)
+    ref = oracle.rhs_cells(g_or, U, cells, order=10, positivity=1, dt_lim=dt, amax=amax)
     scale = np.abs(d).max(axis=1)
     err = (np.abs(d[:, cells].T - ref) / scale).max()
     print("3d 256 sampled", cells.size, "cells, max rel", err, "bitwise", int((d[:, cells].T == ref).sum()))
     assert err <= 1e-11
-    del out, d
-    # the step at full size: dt from the same wave speeds, conservation of every
-    # component (periodic), positive density and pressure (limiter on)
-    dtd = torch.tensor([0.0], dtype=torch.float64, device="cuda")
-    ws = tenoaa.workspace(g_gpu, sch, tenoaa.WS_STEP)
-    before = Ud.reshape(5, -1).sum(dim=1)
-    tenoaa.step(g_gpu, sch, Ud, dtd, cfl=0.4, ws=ws)
-    torch.cuda.synchronize()
-    assert float(dtd.item()) == dt
-    assert tenoaa.get_status(ws) == 0
-    after = Ud.reshape(5, -1).sum(dim=1)
-    tot = Ud.reshape(5, -1).abs().sum(dim=1)
-    assert float(((after - before).abs() / tot).max()) < 1e-13
-    rho = Ud[0]
-    p = 0.4 * (Ud[4] - 0.5 * (Ud[1] ** 2 + Ud[2] ** 2 + Ud[3] ** 2) / rho)
-    assert float(rho.min()) > 0 and float(p.min()) > 0
