@@ -171,6 +171,28 @@ size_t tenoaa_workspace_bytes(const tenoaa_grid* grid, const tenoaa_scheme* sche
 int tenoaa_rhs(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U, double* dUdt,
                double dt_limiter, uint8_t* flags, void* ws, size_t ws_bytes, void* stream);
 
+/* Size of the buffer tenoaa_rhs_noalloc uses instead of a workspace: 80 MiB
+ * (a right-hand side of up to 2D 1024^2 or 3D 80^3 cells). */
+#define TENOAA_SCRATCH_BYTES ((size_t)80 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * tenoaa_rhs without a caller's workspace.  Its workspace is a buffer of
+ * TENOAA_SCRATCH_BYTES the library holds in device memory, one per GPU, from
+ * the first call on that GPU (made with that GPU current) until the process
+ * ends; the call allocates nothing (nor does it take part in
+ * tenoaa_timing_enable's measurement, whose events would).  Arguments as
+ * tenoaa_rhs, plus
+ * status_dev (device int32, or NULL): receives 0, or 1 if a non-physical
+ * state was read during this call.  Every call on one GPU shares that GPU's
+ * buffer and leaves it holding its face fluxes: calls that overlap on one
+ * GPU (other streams or host threads) race and must be serialised by the
+ * caller.  Returns TENOAA_EWORKSPACE if the grid's right-hand-side workspace
+ * (tenoaa_workspace_bytes(grid, scheme, TENOAA_WS_RHS)) exceeds
+ * TENOAA_SCRATCH_BYTES, and the errors of tenoaa_rhs otherwise. */
+int tenoaa_rhs_noalloc(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
+                       double* dUdt, double dt_limiter, uint8_t* flags, int32_t* status_dev, void* stream);
+
 /* One SSP-RK3 step (Sec. 5, Shu-Osher form) of U in place.  dt_dev is a
  * device double: if it holds a value > 0 on entry that dt is used, otherwise
  * dt = cfl / sum_d (a_d / dx_d) with a_d = max over cells of |u_d| + c is

@@ -11,6 +11,13 @@
 #include "tenoaa.h"
 #include "tenoaa_internal.h"
 
+// The library's own workspace for tenoaa_rhs_noalloc: one buffer of
+// TENOAA_SCRATCH_BYTES on each GPU the library runs on, held until the
+// process ends.  In host code this name is only a stand-in for the symbol:
+// the buffer's device address on a GPU comes from hipGetSymbolAddress with
+// that GPU current, and that address is what kernels and copies are given.
+static __device__ __align__(256) char scratch[TENOAA_SCRATCH_BYTES];
+
 namespace {
 
 // The stage kernels read dt from the workspace scalars; the step adjoint takes
@@ -39,9 +46,14 @@ std::vector<TimedLaunch> g_timed;
 int64_t g_launches[TENOAA_KCLASS_COUNT];
 double g_total_ms[TENOAA_KCLASS_COUNT];
 
+// Set for the duration of a call that must not allocate (event creation
+// allocates): its launches are not timed.
+thread_local bool g_untimed = false;
+
 // Brackets one launch with events on `st` when timing is enabled.
 template <class F>
 hipError_t timed(int cls, hipStream_t st, F&& launch) {
+  if (g_untimed) return launch();
   bool on;
   {
     std::lock_guard<std::mutex> lk(g_timing_mu);
@@ -393,6 +405,40 @@ int rhs_body(const Ctx& c, const double* U, double* dUdt, double dt_limiter, uin
   return update(c, 0, nullptr, nullptr, dUdt);
 }
 
+// The device address of `scratch` on each GPU, from hipGetSymbolAddress with
+// that GPU current (kept after the first call on it).
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[SCRATCH_DEVICES] = {};
+
+int scratch_of_current_device(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev < 0 || dev >= SCRATCH_DEVICES) return TENOAA_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    if (!p || ((uintptr_t)p & 255) != 0) return TENOAA_EUNSUPPORTED;
+    g_scratch[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch[dev];
+  return TENOAA_OK;
+}
+
+__global__ void clear_scalars_kernel(tenoaa::Scalars* S) {
+  if (threadIdx.x == 0) {
+    S->amax_bits[0] = S->amax_bits[1] = S->amax_bits[2] = 0ull;
+    S->status = 0;
+  }
+}
+
+__global__ void status_out_kernel(const tenoaa::Scalars* S, int32_t* out) {
+  if (threadIdx.x == 0) *out = S->status ? 1 : 0;
+}
+
 }  // namespace
 
 namespace tenoaa {
@@ -422,6 +468,35 @@ int tenoaa_rhs(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamm
   if (!U || !dUdt || U == dUdt) return TENOAA_EINVAL;
   if ((rc = begin(c))) return rc;
   return rhs_body(c, U, dUdt, dt_limiter, flags);
+}
+
+int tenoaa_rhs_noalloc(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
+                       double* dUdt, double dt_limiter, uint8_t* flags, int32_t* status_dev, void* stream) {
+  if (!valid_grid(grid, scheme) || !(gamma > 1.0)) return TENOAA_EINVAL;
+  if (!U || !dUdt || U == dUdt) return TENOAA_EINVAL;
+  if (layout(grid, TENOAA_WS_RHS, scheme->positivity != 0).total > (size_t)TENOAA_SCRATCH_BYTES)
+    return TENOAA_EWORKSPACE;
+  char* ws = nullptr;
+  int rc = scratch_of_current_device(&ws);
+  if (rc) return rc;
+  Ctx c;
+  if ((rc = prepare(c, grid, scheme, gamma, ws, (size_t)TENOAA_SCRATCH_BYTES, stream, TENOAA_WS_RHS))) return rc;
+  struct Untimed {
+    Untimed() { g_untimed = true; }
+    ~Untimed() { g_untimed = false; }
+  } untimed;
+  // this call's status and wave speeds start from zero (a kernel, not a
+  // memset, so that the call can be captured in a graph)
+  hipLaunchKernelGGL(clear_scalars_kernel, dim3(1), dim3(64), 0, c.st, c.S);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e);
+  if ((rc = rhs_body(c, U, dUdt, dt_limiter, flags))) return rc;
+  if (status_dev) {
+    hipLaunchKernelGGL(status_out_kernel, dim3(1), dim3(64), 0, c.st, (const tenoaa::Scalars*)c.S, status_dev);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return TENOAA_OK;
 }
 
 int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl, double* U,

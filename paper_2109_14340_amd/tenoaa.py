@@ -23,7 +23,7 @@ EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_step_f
            "tenoaa_get_status", "tenoaa_last_hip_error", "tenoaa_timing_enable", "tenoaa_timing_read",
            "tenoaa_batch_plan_create", "tenoaa_batch_offsets", "tenoaa_batch_run", "tenoaa_batch_get_status",
            "tenoaa_batch_plan_info", "tenoaa_batch_plan_destroy", "tenoaa_advect", "tenoaa_wave_speeds",
-           "tenoaa_rk3_stage", "tenoaa_rhs_vjp_halo", "tenoaa_step_near"]
+           "tenoaa_rk3_stage", "tenoaa_rhs_vjp_halo", "tenoaa_step_near", "tenoaa_rhs_noalloc"]
 KCLASS_SWEEP = (0, 1, 2)
 KCLASS_UPDATE, KCLASS_WAVESPEED = 3, 4
 KCLASS_VJP = (5, 6, 7)
@@ -65,6 +65,8 @@ def load():
         L.tenoaa_step_flags.restype = ctypes.c_int
         L.tenoaa_step_flags.argtypes = [gp, sp, ctypes.c_double, ctypes.c_double, vp, vp, vp, ctypes.c_int32, vp,
                                         ctypes.c_size_t, vp]
+        L.tenoaa_rhs_noalloc.restype = ctypes.c_int
+        L.tenoaa_rhs_noalloc.argtypes = [gp, sp, ctypes.c_double, vp, vp, ctypes.c_double, vp, vp, vp]
         L.tenoaa_step_near.restype = ctypes.c_int
         L.tenoaa_step_near.argtypes = [gp, sp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp, vp,
                                        ctypes.c_double, vp, ctypes.c_size_t, vp]
