@@ -81,19 +81,18 @@ def cpu_baseline(n=72):
                       "cores)" % (n, work, el, model, os.cpu_count() or 0)}
 
 
-def fwd_adj_leg(shape, steps, warmup, U0):
+def fwd_adj_leg(shape, steps, warmup, U0, positivity):
     """Forward step plus its adjoint (tenoaa_step_vjp, which recomputes the
-    stages) on one state, TENO10-AA, LLF, no limiter (the adjoint does not
-    differentiate the limiter), dt from CFL 0.4 then frozen for the adjoint.
-    The 3D state is the Gaussian random field without the blast and cavity
-    spheres, which need the limiter to stay physical."""
+    stages) on one state, TENO10-AA, LLF, dt from CFL 0.4 then frozen for the
+    adjoint.  With positivity 1 the limiter acts in both, its factors frozen
+    in the adjoint like the other decisions."""
     import torch
 
     from paper_2109_14340_amd import tenoaa
 
     dev = U0.device
     grid = tenoaa.make_grid(shape)
-    sch = tenoaa.make_scheme(10, tenoaa.LLF, 0)
+    sch = tenoaa.make_scheme(10, tenoaa.LLF, positivity)
     ws = tenoaa.workspace(grid, sch, tenoaa.WS_STEP, dev)
     wsv = tenoaa.workspace(grid, sch, tenoaa.WS_STEP_VJP, dev)
     U = U0.clone()
@@ -120,7 +119,7 @@ def fwd_adj_leg(shape, steps, warmup, U0):
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t0) / steps * 1e3
     work = 3 * len(shape) * U0[0].numel()
-    return {"grid": list(shape), "fwd_ms": round(res["fwd"], 3), "adj_ms": round(res["adj"], 3),
+    return {"grid": list(shape), "limiter": bool(positivity), "fwd_ms": round(res["fwd"], 3), "adj_ms": round(res["adj"], 3),
             "adj_over_fwd": round(res["adj"] / res["fwd"], 3),
             "value": round(work / ((res["fwd"] + res["adj"]) * 1e-3) / 1e9, 4), "unit": "Gface-recon/s",
             "note": "face reconstructions of the forward step / (step + step VJP time); the forward "
@@ -223,10 +222,11 @@ def slab_leg(U0, pieces=8, steps=5, warmup=1):
                     "exchanges and the maximum of the speeds over the slabs excluded"}
 
 
-def batched_leg(nprob=512, nsteps=20, tune_cache=None):
+def batched_leg(nprob=512, nsteps=20, tune_cache=None, compare=True):
     """The batched workload: nprob 2D problems with n_x, n_y ~ U{64..512},
     TENO8-AA, LLF, outflow, nsteps SSP-RK3 steps each with its own dt, in one
-    persistent graph launch; against the same steps launched per problem."""
+    persistent graph launch; against the same steps launched per problem
+    unless compare is False."""
     import tempfile
 
     import torch
@@ -263,6 +263,7 @@ def batched_leg(nprob=512, nsteps=20, tune_cache=None):
         ev_ms.append(ev[0].elapsed_time(ev[1]))
     if any(plan.status()):
         raise RuntimeError("non-physical state in the batched run")
+    stats = plan.run_stats()
     t_batch = min(times)
     # the run is one graph launch (a clearing kernel and the persistent
     # kernel) on torch's current stream; its event duration is the kernel's
@@ -270,6 +271,19 @@ def batched_leg(nprob=512, nsteps=20, tune_cache=None):
     face_flops = flops.smooth_face_flops(2, 8, 0, False)
     fl_total = face_flops * faces
     achieved = fl_total / (kernel_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None, "kernel": "batch_kernel",
+                "kernel_avg_ms": round(kernel_ms, 3), "algorithmic_flops_per_launch": fl_total,
+                "flop_model": "every reconstruction on the largest stencil (%d flop per face): a lower "
+                              "bound of the work, which the deeper cascade paths raise" % face_flops}
+    res = {"problems": nprob, "steps": nsteps, "cells": sum(nx * ny for nx, ny in sizes),
+           "face_recons": faces, "batched_ms": round(t_batch * 1e3, 2),
+           "value": round(faces / t_batch / 1e9, 4), "unit": "Gface-recon/s",
+           "barrier_wait_share": round(stats["barrier_wait_share"], 4),
+           "wait_per_barrier_us": round(stats["wait_per_barrier_us"], 2)}
+    if not compare:
+        res.update({"plan": plan.info(), "plan_create_s": round(t_plan, 3), "roofline": roofline})
+        return res
 
     # per problem: the same steps through tenoaa_step, one problem after another;
     # a plain pass for the wall time, then a pass with per-kernel events
@@ -296,17 +310,11 @@ def batched_leg(nprob=512, nsteps=20, tune_cache=None):
         ksum += tenoaa.timing_read(k)[1]
     tenoaa.timing_enable(False)
     same = all(torch.equal(plan.unpack(packed, p), Us[p]) for p in range(nprob)) and torch.equal(dts, dtb)
-    return {"problems": nprob, "steps": nsteps, "cells": sum(nx * ny for nx, ny in sizes),
-            "face_recons": faces, "batched_ms": round(t_batch * 1e3, 2),
-            "value": round(faces / t_batch / 1e9, 4), "unit": "Gface-recon/s",
-            "per_problem_wall_ms": round(t_pp * 1e3, 2), "per_problem_kernel_sum_ms": round(ksum, 2),
-            "speedup_vs_wall": round(t_pp / t_batch, 3), "speedup_vs_kernel_sum": round(ksum / 1e3 / t_batch, 3),
-            "bitwise_equal_to_per_problem": bool(same), "plan": plan.info(), "plan_create_s": round(t_plan, 3),
-            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                         "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None, "kernel": "batch_kernel",
-                         "kernel_avg_ms": round(kernel_ms, 3), "algorithmic_flops_per_launch": fl_total,
-                         "flop_model": "every reconstruction on the largest stencil (%d flop per face): a lower "
-                                       "bound of the work, which the deeper cascade paths raise" % face_flops}}
+    res.update({"per_problem_wall_ms": round(t_pp * 1e3, 2), "per_problem_kernel_sum_ms": round(ksum, 2),
+                "speedup_vs_wall": round(t_pp / t_batch, 3), "speedup_vs_kernel_sum": round(ksum / 1e3 / t_batch, 3),
+                "bitwise_equal_to_per_problem": bool(same), "plan": plan.info(), "plan_create_s": round(t_plan, 3),
+                "roofline": roofline})
+    return res
 
 
 def main():
@@ -322,6 +330,8 @@ def main():
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain copy of the state (a kernel of known traffic) for counter runs")
+    ap.add_argument("--only", choices=["batched", "fwd_adj"], default=None,
+                    help="run one side leg alone and print its object (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -335,6 +345,13 @@ def main():
     n = args.n
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.only == "batched":
+        print(json.dumps({"batched": batched_leg(tune_cache=args.tune_cache, compare=False)}), flush=True)
+        return
+    if args.only == "fwd_adj":
+        U3 = torch.from_numpy(inputs.grf_3d(n)).to(dev)
+        print(json.dumps({"fwd_adj": {"3d": fwd_adj_leg((n, n, n), 1, 1, U3, 1)}}), flush=True)
+        return
     grid = tenoaa.make_grid((n, n, n))
     sch = tenoaa.make_scheme(10, tenoaa.LLF, 1)
     U = torch.from_numpy(inputs.grf_3d(n)).to(dev)
@@ -424,10 +441,11 @@ def main():
                      "per_kernel_avg_ms": {k: round(v[1] / max(v[0], 1), 4) for k, v in per.items()}},
     }
     if not args.no_fwd_adj:
-        U3 = torch.from_numpy(inputs.grf_3d(n, spheres=False)).to(dev)
+        # the 3D leg on the headline state (blast and cavity spheres, limiter on)
+        U3 = torch.from_numpy(inputs.grf_3d(n)).to(dev)
         U2 = torch.from_numpy(inputs.grf_2d(512, jump=False)).to(dev)
-        line["fwd_adj"] = {"3d": fwd_adj_leg((n, n, n), 3, 1, U3),
-                           "2d_512_periodic": fwd_adj_leg((512, 512), 20, 3, U2)}
+        line["fwd_adj"] = {"3d": fwd_adj_leg((n, n, n), 3, 1, U3, 1),
+                           "2d_512_periodic": fwd_adj_leg((512, 512), 20, 3, U2, 0)}
         del U3, U2
     if not args.no_slab:
         line["slab_share"] = slab_leg(torch.from_numpy(inputs.grf_3d(n)).to(dev))

@@ -373,6 +373,16 @@ int tenoaa_batch_run(tenoaa_batch_plan* plan, double* U_packed, double* dt_out, 
  * TENOAA_ENONPHYSICAL if any problem was non-physical, else 0. */
 int tenoaa_batch_get_status(tenoaa_batch_plan* plan, void* stream, int32_t* status_out);
 
+/* Synchronises `stream` and reports how the blocks of the last
+ * tenoaa_batch_run spent their time (read from per-block wall-clock counters
+ * the persistent kernel keeps): out (host, n >= 3 entries) receives the share
+ * of the blocks' resident time spent waiting at phase barriers (imbalance
+ * between blocks plus the barrier's own latency), the mean time a block was
+ * resident in seconds, and the mean wait per block and barrier in
+ * microseconds.  Meaningful only after a run that completed; EINVAL for a
+ * null plan or out, or n < 3; EHIP on a HIP failure. */
+int tenoaa_batch_run_stats(tenoaa_batch_plan* plan, void* stream, double* out, int32_t n);
+
 /* Launch choices of a plan: info (host, n >= 10 entries) receives blocks
  * launched, blocks per compute unit, items per queue access, how the choices
  * were made (0 defaults, 1 tuned now, 2 from the cache file), then the x-tile

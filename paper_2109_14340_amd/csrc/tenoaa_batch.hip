@@ -97,6 +97,7 @@ struct BatchArgs {
   double* dt_out;             // [orig][nsteps] or null
   int* status;                // [nprob] non-physical-state words
   unsigned long long* ctl;    // [0] barrier arrivals, [1] abort, [2 + phase] item counters
+  unsigned long long* bstat;  // per block: [2 b] ticks waited at phase barriers, [2 b + 1] ticks resident
   double gamma, cfl;
   int64_t timeout_ticks;
   int32_t nprob, nsteps, splitting, chunk;
@@ -299,7 +300,9 @@ __device__ __forceinline__ void speeds_item(const BatchArgs& B, char* arena, int
   block_max2(arena, amax[0], amax[1], B.amax + (int64_t)p * B.nsteps * 2);
 }
 
-// All blocks arrive; returns false if the launch is being abandoned.
+// All blocks arrive; returns false if the launch is being abandoned.  The
+// ticks thread 0 spends between its arrival and the release are added to the
+// block's wait counter.
 __device__ __forceinline__ bool grid_barrier(const BatchArgs& B, unsigned long long target, int* s_flag) {
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -320,6 +323,7 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs& B, unsigned long l
       }
       __builtin_amdgcn_s_sleep(2);
     }
+    B.bstat[2 * blockIdx.x] += wall_clock64() - t0;
     __threadfence();
     *s_flag = ok;
   }
@@ -336,6 +340,7 @@ void batch_kernel(BatchArgs B) {
   __shared__ __align__(16) char arena[arena_bytes<ORDER>()];
   __shared__ int64_t s_first;
   __shared__ int s_flag;
+  const uint64_t t_start = wall_clock64();
   const int nphase = 1 + 6 * B.nsteps;
   for (int ph = 0; ph < nphase; ++ph) {
     int kind = 0, n = 0, stage = 0;
@@ -377,6 +382,7 @@ void batch_kernel(BatchArgs B) {
     }
     if (ph + 1 < nphase && !grid_barrier(B, (unsigned long long)(ph + 1) * gridDim.x, &s_flag)) return;
   }
+  if (threadIdx.x == 0) B.bstat[2 * blockIdx.x + 1] = wall_clock64() - t_start;
 }
 
 // Uniform state for tuning runs: rho = 1, u = 0.3, v = 0.2, p = 1.
@@ -446,7 +452,9 @@ struct tenoaa_batch_plan {
   unsigned long long* d_amax = nullptr;
   int* d_status = nullptr;
   unsigned long long* d_ctl = nullptr;
-  int64_t nctl = 0;
+  int64_t nctl = 0;        // queue words (nctl_queue) then two per block slot (ncu * max_bpc)
+  int64_t nctl_queue = 0;
+  int rate_khz = 0;        // wall_clock64 ticks per millisecond
   BatchArgs args{};
   InitArgs iargs{};
   hipGraph_t graph = nullptr;
@@ -523,6 +531,7 @@ void fill_args(tenoaa_batch_plan* P, double* U, double* dt_out, int nsteps) {
   a.dt_out = dt_out;
   a.status = P->d_status;
   a.ctl = P->d_ctl;
+  a.bstat = P->d_ctl + P->nctl_queue;
   a.gamma = P->gamma;
   a.cfl = P->cfl;
   a.nprob = P->nprob;
@@ -795,7 +804,9 @@ int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const teno
     s_total += 4 * g.n[0] * g.n[1];
     f_total += 4 * (faces_along2(g, 0) * g.n[1] + faces_along2(g, 1) * g.n[0]);
   }
-  P->nctl = 2 + 1 + 6 * (int64_t)nsteps;
+  P->nctl_queue = 2 + 1 + 6 * (int64_t)nsteps;
+  P->nctl = P->nctl_queue + 2 * (int64_t)P->ncu * P->max_bpc;
+  P->rate_khz = rate_khz > 0 ? rate_khz : 100000;
   e = hipMalloc(&P->d_table, sizeof(BatchProblem) * nprob);
   if (e == hipSuccess) e = hipMalloc(&P->d_pre, sizeof(int64_t) * 2 * (nprob + 1));
   if (e == hipSuccess) e = hipMalloc(&P->d_S, sizeof(double) * s_total);
@@ -882,6 +893,28 @@ int tenoaa_batch_get_status(tenoaa_batch_plan* plan, void* stream, int32_t* stat
   }
   if (abort_word) return TENOAA_ETIMEOUT;
   return any ? TENOAA_ENONPHYSICAL : TENOAA_OK;
+}
+
+int tenoaa_batch_run_stats(tenoaa_batch_plan* plan, void* stream, double* out, int32_t n) {
+  if (!plan || !out || n < 3) return TENOAA_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nblk = plan->ncu * plan->bpc;
+  std::vector<unsigned long long> b(2 * (size_t)nblk);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e == hipSuccess)
+    e = hipMemcpy(b.data(), plan->d_ctl + plan->nctl_queue, sizeof(unsigned long long) * b.size(),
+                  hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e);
+  double wait = 0.0, resident = 0.0;
+  for (int i = 0; i < nblk; ++i) {
+    wait += (double)b[2 * i];
+    resident += (double)b[2 * i + 1];
+  }
+  const double nbar = 6.0 * plan->nsteps;
+  out[0] = resident > 0.0 ? wait / resident : 0.0;
+  out[1] = resident / nblk / plan->rate_khz * 1e-3;
+  out[2] = wait / nblk / nbar / plan->rate_khz * 1e3;
+  return TENOAA_OK;
 }
 
 int tenoaa_batch_plan_info(const tenoaa_batch_plan* plan, int32_t* info, int32_t n) {

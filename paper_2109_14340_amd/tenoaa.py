@@ -22,7 +22,7 @@ FLAGS_NONE, FLAGS_RECORD, FLAGS_REPLAY = 0, 1, 2
 EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_step_flags", "tenoaa_rhs_vjp", "tenoaa_step_vjp",
            "tenoaa_get_status", "tenoaa_last_hip_error", "tenoaa_timing_enable", "tenoaa_timing_read",
            "tenoaa_batch_plan_create", "tenoaa_batch_offsets", "tenoaa_batch_run", "tenoaa_batch_get_status",
-           "tenoaa_batch_plan_info", "tenoaa_batch_plan_destroy", "tenoaa_advect", "tenoaa_wave_speeds",
+           "tenoaa_batch_plan_info", "tenoaa_batch_run_stats", "tenoaa_batch_plan_destroy", "tenoaa_advect", "tenoaa_wave_speeds",
            "tenoaa_rk3_stage", "tenoaa_rhs_vjp_halo", "tenoaa_step_near", "tenoaa_rhs_noalloc"]
 KCLASS_SWEEP = (0, 1, 2)
 KCLASS_UPDATE, KCLASS_WAVESPEED = 3, 4
@@ -94,6 +94,8 @@ def load():
         L.tenoaa_batch_get_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
         L.tenoaa_batch_plan_info.restype = ctypes.c_int
         L.tenoaa_batch_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+        L.tenoaa_batch_run_stats.restype = ctypes.c_int
+        L.tenoaa_batch_run_stats.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
         L.tenoaa_batch_plan_destroy.restype = ctypes.c_int
         L.tenoaa_batch_plan_destroy.argtypes = [vp]
         L.tenoaa_advect.restype = ctypes.c_int
@@ -475,6 +477,14 @@ class BatchPlan:
         v = list(buf)
         return {"blocks": v[0], "blocks_per_cu": v[1], "chunk": v[2], "chosen": ("defaults", "tuned", "cache")[v[3]],
                 "tile_x": v[4:7], "tile_y": v[7:10]}
+
+    def run_stats(self):
+        """Synchronises; barrier figures of the last run: the share of the
+        blocks' resident time spent waiting at phase barriers, the mean time a
+        block was resident (s) and the mean wait per block and barrier (us)."""
+        buf = (ctypes.c_double * 3)()
+        _check(load().tenoaa_batch_run_stats(self._h, _stream(), buf, 3), "tenoaa_batch_run_stats")
+        return {"barrier_wait_share": buf[0], "resident_s": buf[1], "wait_per_barrier_us": buf[2]}
 
     def pack(self, states, device="cuda"):
         """Packed float64 device tensor of the problems' (4, 1, ny, nx) states."""

@@ -84,6 +84,10 @@ def test_batch_bitwise_equals_per_problem(tiles, tmp_path):
     if tiles == "alternate":
         assert info["chosen"] == "cache" and info["tile_x"] == [1, 1, 1] and info["chunk"] == 3
     assert st == [0] * len(grids)
+    rs = plan.run_stats()
+    print(rs)
+    # every block waits at each of the 6 * nsteps barriers, and for less than it was resident
+    assert 0.0 < rs["barrier_wait_share"] < 1.0 and rs["resident_s"] > 0.0 and rs["wait_per_barrier_us"] > 0.0
     ref, dtr = _per_problem(grids, states, sch, nsteps)
     _assert_same(plan, packed, dtb, ref, dtr)
 
