@@ -210,8 +210,8 @@ int tenoaa_step(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gam
  * flags: NULL to freeze the decisions taken at U, or a flag array (layout
  * above, e.g. recorded by tenoaa_rhs at another state) whose decisions are
  * used instead.  The limiter is not part of the differentiated map (it acts
- * only with a dt).  U_bar is accumulated with FP64 atomics, so its last bits
- * can differ between runs.  U_bar must not alias U or dUdt_bar. */
+ * only with a dt).  Every sum is taken in a fixed order, so U_bar is the
+ * same bit for bit from run to run.  U_bar must not alias U or dUdt_bar. */
 int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
                    const double* dUdt_bar, double* U_bar, const uint8_t* flags, void* ws, size_t ws_bytes,
                    void* stream);
@@ -226,7 +226,7 @@ int tenoaa_rhs_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double 
  * the same cells.  Entries of other sides are ignored.  U_bar covers the
  * piece's own cells as in tenoaa_rhs_vjp; with the halos of a piece's
  * neighbours summed in, the pieces give the whole grid's adjoint (up to the
- * order of the atomic sums).  Same errors as tenoaa_rhs_vjp, and
+ * order of the sums).  Same errors as tenoaa_rhs_vjp, and
  * TENOAA_EINVAL for a null halo_bar or a halo side without its pointer. */
 int tenoaa_rhs_vjp_halo(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,
                         const double* dUdt_bar, double* U_bar, const uint8_t* flags, double* const* halo_bar,

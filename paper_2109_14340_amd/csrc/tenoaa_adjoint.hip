@@ -41,12 +41,11 @@ hipError_t launch_sweep_vjp(int order, int ndim, int dir, const AdjointArgs& a, 
   // the Roe flux's one-sided fields and the ghost rules of prescribed sides
   // in a variant of their own (whole tiles only), which the common case does
   // not carry.  The common case sends a remainder of at most SWEEP_TAIL_TN
-  // faces beyond the last whole 64-face tile of an x sweep (non-periodic
-  // directions have n + 1) to one-wave tail tiles; in y and z a 16-face
-  // tile more costs less than tail tiles, whose LDS per cell is as large
+  // faces beyond the last whole 64-face tile of a direction (non-periodic
+  // directions have n + 1) to one-wave tail tiles
   if (a.splitting == TENOAA_ROE || a.bcv[0] || a.bcv[1]) return launch_vjp_general(order, ndim, dir, a, st);
-  const int64_t rem = a.nf % TENOAA_ADJ_TN_X;
-  const bool tail = ndim > 1 && dir == 0 && rem > 0 && rem <= SWEEP_TAIL_TN;
+  const int64_t rem = a.nf % (dir == 0 ? TENOAA_ADJ_TN_X : TENOAA_ADJ_TN_YZ);
+  const bool tail = ndim > 1 && rem > 0 && rem <= SWEEP_TAIL_TN;
   const int64_t whole = tail ? a.nf - rem : a.nf;
   if (whole > 0) {
     const hipError_t e = launch_vjp_kind<false>(order, ndim, dir, a, whole, st);

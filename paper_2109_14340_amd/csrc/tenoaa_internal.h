@@ -73,19 +73,20 @@ struct GhostSpeedArgs {
 struct AdjointArgs {
   const double* U = nullptr;       // state at which the right-hand side is differentiated
   const double* R = nullptr;       // seed: adjoint of dU/dt, layout of U
-  double* Ubar = nullptr;          // accumulated with atomics (caller zeroes it)
+  double* Ubar = nullptr;          // accumulated in a fixed order (caller zeroes it)
   const uint8_t* flags = nullptr;  // decisions of this direction's forward sweep at U, [nvar][2][nft]
   const double* fh = nullptr;      // per-field fluxes of that sweep, [nvar][nft]
   const double* theta = nullptr;   // the sweep's limiter factors per face, or null (no limiter)
   const double* bcv[2] = {nullptr, nullptr};  // boundary values of the low/high side (Dirichlet, inflow, halo), else null
-  double* hbar[2] = {nullptr, nullptr};       // adjoints of the low/high halo cells (accumulated with atomics), or null
+  double* hbar[2] = {nullptr, nullptr};       // adjoints of the low/high halo cells (accumulated), or null
   int64_t nft = 0;
-  int64_t f_begin = 0;  // first face along the direction of this launch's tiles
+  int64_t f_begin = 0;     // first face along the direction of this launch's tiles
+  int64_t tile_first = 0;  // block x of a launch runs tile tile_first + x * tile_step (tiles of TN faces from f_begin)
   int64_t n[3] = {0, 0, 0};
   int64_t nf = 0;
   int bc_lo = 0, bc_hi = 0;
   int splitting = 0;
-  int pad = 0;
+  int tile_step = 1;
   double gamma = 0.0;
   double dx = 0.0;
 };
@@ -102,7 +103,7 @@ void record_hip_error(hipError_t e);
 hipError_t launch_sweep_vjp(int order, int ndim, int dir, const AdjointArgs& a, hipStream_t st);
 // The reverse sweep's general variant (Roe flux, Dirichlet or inflow sides)
 // over all faces, and the common variant's one-wave tail tiles over the faces
-// [a.f_begin, a.nf) of a 2D or 3D x sweep.
+// [a.f_begin, a.nf) of a 2D or 3D sweep.
 hipError_t launch_vjp_general(int order, int ndim, int dir, const AdjointArgs& a, hipStream_t st);
 hipError_t launch_vjp_tail(int order, int ndim, int dir, const AdjointArgs& a, hipStream_t st);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st);

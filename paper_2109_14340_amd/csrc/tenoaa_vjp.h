@@ -14,17 +14,25 @@
 //
 // The forward sweep of the same direction runs first and leaves, per face,
 // the decision bytes and the per-field fluxes fh_s.  Per block: the tile of
-// cells is staged exactly as in the forward sweep; each thread takes one face,
-// recomputes the Roe average, eigenvectors, projections and splitting speeds,
-// then runs the reverse pass and scatters the adjoints of the window cells'
-// conserved states, physical fluxes and primitive quantities into LDS
-// accumulators (ds_add_f64).  After a barrier the cell-level reverse
-// pass turns those into conserved-state adjoints, maps ghost cells back to
-// their interior source (with the momentum sign flips of wall conditions) and
-// adds them to U_bar with global FP64 atomics (a Dirichlet ghost through the
-// Jacobian of its reflection rule; an inflow ghost is a constant; a halo
-// cell, a neighbour piece's, goes to the caller's halo-adjoint buffer), so
-// the summation order - and the last bits of U_bar - can vary between runs.
+// cells is staged with the forward sweep's arithmetic; each thread takes one
+// face, recomputes the Roe average, eigenvectors, projections and splitting
+// speeds, then runs the reverse pass and scatters the adjoints of the window
+// cells' conserved states, physical fluxes and primitive quantities into LDS
+// accumulators (ds_add_f64).  After a barrier the cell-level reverse pass
+// turns those into conserved-state adjoints, maps ghost cells back to their
+// interior source (with the momentum sign flips of wall conditions) and adds
+// them to U_bar (a Dirichlet ghost through the Jacobian of its reflection
+// rule; an inflow ghost is a constant; a halo cell, a neighbour piece's, goes
+// to the caller's halo-adjoint buffer).
+//
+// Every sum is taken in a fixed order, so U_bar is the same bit for bit from
+// run to run: a wave holds whole pencils of its tile (the LDS records are
+// pencil-major in every direction), so each LDS accumulator is added to by
+// one wave only, in program order; a ghost position whose source is a domain
+// cell of the same tile is summed into that cell's adjoint in window order
+// before one add to U_bar; and the tiles of a direction run in launches of
+// alternating tiles (the periodic wrap's neighbours apart), so that no two
+// tiles of one launch add to the same cell.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -41,10 +49,10 @@
 #define TENOAA_ADJ_TT_X 2
 #endif
 #ifndef TENOAA_ADJ_TN_YZ
-#define TENOAA_ADJ_TN_YZ 16
+#define TENOAA_ADJ_TN_YZ 64
 #endif
 #ifndef TENOAA_ADJ_TT_YZ
-#define TENOAA_ADJ_TT_YZ 8
+#define TENOAA_ADJ_TT_YZ 2
 #endif
 #ifndef TENOAA_ADJ_WAVES_PER_EU
 #define TENOAA_ADJ_WAVES_PER_EU 0
@@ -114,8 +122,11 @@ void sweep_vjp_kernel(AdjointArgs A) {
   constexpr int AX_A = (DIR == 0) ? 1 : 0;
   constexpr int AX_B = (DIR == 2) ? 1 : 2;
   using Fr = Frame<NDIM, DIR>;
+  // a wave holds whole pencils (the fixed order of the LDS sums)
+  static_assert(TN <= 64 && 64 % TN == 0 && (TT * TN) % 64 == 0, "tile must give each wave whole pencils");
 
-  // forward per-cell records (as in the forward sweep)
+  // forward per-cell records (as in the forward sweep), pencil-major: cell nn
+  // of pencil tt at tt * NC + nn
   __shared__ double2 sWF[NV][NCT];
   __shared__ double sUn[NCT], sC[NCT], sSr[NCT], sH[NCT];
   __shared__ double sUt[NT][NCT];
@@ -130,18 +141,15 @@ void sweep_vjp_kernel(AdjointArgs A) {
   const int64_t nA = A.n[AX_A];
   const int64_t stride[3] = {1, A.n[0], A.n[0] * A.n[1]};
   const int64_t ncell = A.n[0] * A.n[1] * A.n[2];
-  const int64_t f0 = A.f_begin + (int64_t)blockIdx.x * TN;
+  const int64_t f0 = A.f_begin + (A.tile_first + (int64_t)blockIdx.x * A.tile_step) * TN;
   const int64_t t0 = (int64_t)blockIdx.y * TT;
   const int64_t bcoord = blockIdx.z;
   const double gam = A.gamma;
   const double gm1 = gam - 1.0;
 
-  // ghost mapping of tile cell ct, as in the forward sweep: the source cell
-  // along the normal, the boundary kind that makes it a ghost (-1 for a
-  // domain cell, a periodic or outflow copy, or a cell beyond the G ghost
-  // layers that no face reads), the side and the ghost layer 1..G
-  auto map_cell = [&](int ct, int64_t& t, int64_t& l, int& gbc, int& side, int64_t& layer) {
-    int tt, nn;
+  // pencil and position of the ct-th cell a thread stages: along the pencil
+  // in x, across the pencils (consecutive in memory) in y and z
+  auto cell_of = [&](int ct, int& tt, int& nn) {
     if (DIR == 0) {
       tt = ct / NC;
       nn = ct % NC;
@@ -149,6 +157,12 @@ void sweep_vjp_kernel(AdjointArgs A) {
       tt = ct % TT;
       nn = ct / TT;
     }
+  };
+  // ghost mapping of the tile cell at (tt, nn), as in the forward sweep: the
+  // source cell along the normal, the boundary kind that makes it a ghost (-1
+  // for a domain cell, a periodic or outflow copy, or a cell beyond the G
+  // ghost layers that no face reads), the side and the ghost layer 1..G
+  auto map_cell = [&](int tt, int nn, int64_t& t, int64_t& l, int& gbc, int& side, int64_t& layer) {
     t = t0 + tt;
     l = f0 - G + nn;
     gbc = -1;
@@ -172,10 +186,13 @@ void sweep_vjp_kernel(AdjointArgs A) {
   const int64_t plane = nA * A.n[AX_B];
   auto face_vals = [&](int side, int64_t t) { return A.bcv[side] + t + nA * bcoord; };
 
-  for (int ct = threadIdx.x; ct < NCT; ct += NTH) {
+  for (int cs = threadIdx.x; cs < NCT; cs += NTH) {
+    int tt0, nn0;
+    cell_of(cs, tt0, nn0);
+    const int ct = tt0 * NC + nn0;
     int64_t t, l, layer;
     int gbc, side;
-    map_cell(ct, t, l, gbc, side, layer);
+    map_cell(tt0, nn0, t, l, gbc, side, layer);
     if (t >= nA) t = nA - 1;
     const int64_t off = l * stride[DIR] + t * stride[AX_A] + bcoord * stride[AX_B];
     double Wc[NV];
@@ -229,19 +246,13 @@ void sweep_vjp_kernel(AdjointArgs A) {
   }
   __syncthreads();
 
-  int tt, fn;
-  if (DIR == 0) {
-    tt = threadIdx.x / TN;
-    fn = threadIdx.x % TN;
-  } else {
-    tt = threadIdx.x % TT;
-    fn = threadIdx.x / TT;
-  }
+  const int tt = threadIdx.x / TN;
+  const int fn = threadIdx.x % TN;
   const int64_t f = f0 + fn;
   const int64_t t = t0 + tt;
   const bool active = (f < A.nf) && (t < nA);
-  const int lbase = (DIR == 0) ? tt * NC + fn : fn * TT + tt;
-  constexpr int LSTEP = (DIR == 0) ? 1 : TT;
+  const int lbase = tt * NC + fn;
+  constexpr int LSTEP = 1;
   const int ia = lbase + (G - 1) * LSTEP, ib = lbase + G * LSTEP;
 
   int64_t flin = 0;
@@ -572,13 +583,22 @@ void sweep_vjp_kernel(AdjointArgs A) {
   }
   __syncthreads();
 
-  // ---- cell-level reverse pass and scatter to U_bar
-  for (int ct = threadIdx.x; ct < NCT; ct += NTH) {
+  // ---- cell-level reverse pass: the conserved-state adjoint Ub of the tile
+  // cell at (ttc, nn) with respect to the state it is read from (the source
+  // cell, a wall ghost's sign flips undone, a Dirichlet ghost's mirror cell
+  // through its rule, or a halo cell); false if it adds nothing (a pencil
+  // beyond the grid, an inflow ghost, which does not depend on U, a halo side
+  // without its buffer, or a position beyond the G ghost layers, which no
+  // face reads)
+  auto cell_adjoint = [&](int ttc, int nn, double (&Ub)[NV]) -> bool {
+    const int ct = ttc * NC + nn;
     int64_t tc, l, layer;
     int gbc, side;
-    map_cell(ct, tc, l, gbc, side, layer);
-    if (tc >= nA || (GENERAL && gbc == TENOAA_BC_INFLOW)) continue;  // an inflow ghost does not depend on U
-    if (GENERAL && gbc == TENOAA_BC_HALO && !A.hbar[side]) continue;
+    map_cell(ttc, nn, tc, l, gbc, side, layer);
+    const int64_t lraw = f0 - G + nn;
+    if (tc >= nA || ((lraw < 0 || lraw >= nN) && layer > G)) return false;
+    if (GENERAL && gbc == TENOAA_BC_INFLOW) return false;
+    if (GENERAL && gbc == TENOAA_BC_HALO && !A.hbar[side]) return false;
     const double2 w0 = sWF[0][ct];
     const double rho = w0.x;
     const double E = sWF[NV - 1][ct].x;
@@ -636,19 +656,12 @@ void sweep_vjp_kernel(AdjointArgs A) {
       m_b[k] += u_b[k] / rho;
       rho_b -= u_b[k] * u[k] / rho;
     });
-    // back to axis order, undo the wall sign flips, add to the source cell
-    double Ub[NV];
+    // back to axis order, undo the wall sign flips
     Ub[0] = rho_b;
     Ub[NV - 1] = E_b;
     unroll<NDIM>([&](auto a) { Ub[1 + a] = m_b[Fr::slot_of_axis(decltype(a)::value)]; });
     if (gbc == TENOAA_BC_SYMMETRY) Ub[1 + DIR] = -Ub[1 + DIR];
     if (gbc == TENOAA_BC_NOSLIP) unroll<NDIM>([&](auto k) { Ub[1 + k] = -Ub[1 + k]; });
-    if (GENERAL && gbc == TENOAA_BC_HALO) {
-      // a neighbour piece's cell: its adjoint goes back to that piece
-      double* hb = A.hbar[side] + tc + nA * bcoord + (layer - 1) * NV * plane;
-      unroll<NV>([&](auto cc) { unsafeAtomicAdd(&hb[cc * plane], Ub[cc]); });
-      continue;
-    }
     const int64_t off = l * stride[DIR] + tc * stride[AX_A] + bcoord * stride[AX_B];
     if (GENERAL && gbc == TENOAA_BC_DIRICHLET) {
       // through the ghost rule (rho, u, p)_g = 2 (rho, u, p)_face - (rho, u, p)_m
@@ -682,19 +695,126 @@ void sweep_vjp_kernel(AdjointArgs A) {
       });
       unroll<NV>([&](auto cc) { Ub[cc] = Um[cc]; });
     }
+    return true;
+  };
+  // adds Ub to where the tile cell at (ttc, nn) is read from: U_bar, or for a
+  // halo cell (a neighbour piece's) the caller's halo-adjoint buffer.  The
+  // adds are atomic, at L2, so that the tiles of later launches and the ghost
+  // round below see them; their order is fixed as described at the top of
+  // this file.
+  auto add_to_source = [&](int ttc, int nn, const double (&Ub)[NV]) {
+    int64_t tc, l, layer;
+    int gbc, side;
+    map_cell(ttc, nn, tc, l, gbc, side, layer);
+    if (GENERAL && gbc == TENOAA_BC_HALO) {
+      double* hb = A.hbar[side] + tc + nA * bcoord + (layer - 1) * NV * plane;
+      unroll<NV>([&](auto cc) { unsafeAtomicAdd(&hb[cc * plane], Ub[cc]); });
+      return;
+    }
+    const int64_t off = l * stride[DIR] + tc * stride[AX_A] + bcoord * stride[AX_B];
     unroll<NV>([&](auto cc) { unsafeAtomicAdd(&A.Ubar[cc * ncell + off], Ub[cc]); });
+  };
+  // every tile cell's adjoint in parallel.  A ghost position whose source is
+  // a domain cell of this tile (outflow, wall and Dirichlet ghosts, a
+  // periodic image the window wraps onto) is folded into that cell's sum
+  // after a barrier - the cell's own adjoint first, then the ghosts in window
+  // order - and the sum goes to U_bar.  Every other adjoint goes at once:
+  // domain cells of a tile with nothing to fold (distinct cells, and no other
+  // tile of this launch touches them), periodic images in another tile, halo
+  // cells.  The adjoints to fold wait in the LDS accumulator slots: aW the
+  // adjoint, aC the window position + 1 of the cell it folds into (0: none).
+  const int64_t lo_w = f0 - G;  // raw position of window cell 0
+  auto folds = [&](int bc) {
+    return bc == TENOAA_BC_PERIODIC ? nN < NC : (bc != TENOAA_BC_HALO && bc != TENOAA_BC_INFLOW);
+  };
+  const bool ghosts = (lo_w < 0 && folds(A.bc_lo)) || (lo_w + NC > nN && folds(A.bc_hi));
+  auto fold_pos = [&](int ttc, int nn) -> int {
+    int64_t tc, l, layer;
+    int gbc, side;
+    map_cell(ttc, nn, tc, l, gbc, side, layer);
+    if (GENERAL && gbc == TENOAA_BC_HALO) return -1;
+    const int64_t q = l - lo_w;
+    return (q >= 0 && q < NC) ? (int)q : -1;
+  };
+  for (int cs = threadIdx.x; cs < NCT; cs += NTH) {
+    int ttc, nn;
+    cell_of(cs, ttc, nn);
+    const int ct = ttc * NC + nn;
+    const int64_t l = lo_w + nn;
+    double Ub[NV];
+    const bool has = cell_adjoint(ttc, nn, Ub);
+    if (!ghosts) {
+      if (has) add_to_source(ttc, nn, Ub);
+      continue;
+    }
+    int q = -1;
+    if (has) {
+      q = (l >= 0 && l < nN) ? nn : fold_pos(ttc, nn);
+      if (q < 0) add_to_source(ttc, nn, Ub);
+    }
+    unroll<NV>([&](auto cc) { aW[cc][ct] = Ub[cc]; });
+    aC[ct] = (double)(q + 1);
+  }
+  if (ghosts) {
+    __syncthreads();
+    // ghost positions of the window: [0, gl) low side, [gh, NC) high side
+    const int gl = lo_w < 0 ? (int)(-lo_w < NC ? -lo_w : NC) : 0;
+    const int gh = lo_w + NC > nN ? (int)(nN - lo_w > 0 ? nN - lo_w : 0) : NC;
+    for (int cs = threadIdx.x; cs < NCT; cs += NTH) {
+      int ttc, nn;
+      cell_of(cs, ttc, nn);
+      const int64_t l = lo_w + nn;
+      const int ct = ttc * NC + nn;
+      if (l < 0 || l >= nN || aC[ct] == 0.0) continue;
+      double Ub[NV];
+      unroll<NV>([&](auto cc) { Ub[cc] = aW[cc][ct]; });
+      const double me = (double)(nn + 1);
+      for (int g = 0; g < NC; ++g) {
+        if (g == gl && gl < gh) g = gh;  // skip the domain positions
+        if (g >= NC) break;
+        const int cg = ttc * NC + g;
+        if (aC[cg] == me) unroll<NV>([&](auto cc) { Ub[cc] += aW[cc][cg]; });
+      }
+      add_to_source(ttc, nn, Ub);
+    }
   }
 }
 
 // The reverse sweep over the faces [a.f_begin, f_end) of a direction in
-// tiles of TT pencils x TN faces.
+// tiles of TT pencils x TN faces, in launches of tiles that share no cell: a
+// tile's window reaches into its neighbours' only (TN >= 2 G - 1), so the
+// even tiles, then the odd ones.  Along a periodic direction the wrap makes
+// the first and the last tile neighbours (with an odd count, the last runs on
+// its own); when the cells from the last tile's start to the end of the
+// direction are fewer than 2 G - 1, it also joins the first tile to the one
+// before the last and the second to the last, and the last two run on their own.
 template <int ORDER, int NDIM, int DIR, int TT, int TN, bool GENERAL>
 hipError_t launch_vjp_tiles(const AdjointArgs& a, int64_t f_end, hipStream_t st) {
   constexpr int AX_A = (DIR == 0) ? 1 : 0;
   constexpr int AX_B = (DIR == 2) ? 1 : 2;
-  dim3 grid((unsigned)((f_end - a.f_begin + TN - 1) / TN), (unsigned)((a.n[AX_A] + TT - 1) / TT), (unsigned)a.n[AX_B]);
-  hipLaunchKernelGGL((sweep_vjp_kernel<ORDER, NDIM, DIR, TT, TN, GENERAL>), grid, dim3(TT * TN), 0, st, a);
-  return hipGetLastError();
+  const int64_t ntile = (f_end - a.f_begin + TN - 1) / TN;
+  // narrower tiles (the tail's) come one per pencil
+  if (TN < ORDER - 1 && ntile > 1) return hipErrorInvalidValue;
+  // tiles [body, ntile) run one per launch; the rest alternate
+  int64_t body = ntile;
+  if (a.bc_lo == TENOAA_BC_PERIODIC && ntile >= 2) {
+    const bool short_last = a.f_begin != 0 || a.n[DIR] - (ntile - 1) * TN < ORDER - 1;
+    body = short_last ? ntile - 2 : (ntile % 2 == 0 ? ntile : ntile - 1);
+  }
+  const int64_t first[4] = {0, 1, body, body + 1};
+  const int64_t count[4] = {(body + 1) / 2, body / 2, ntile - body, ntile - body - 1};
+  for (int c = 0; c < 4; ++c) {
+    if (count[c] <= 0) continue;
+    AdjointArgs b = a;
+    b.tile_first = first[c];
+    b.tile_step = 2;
+    const unsigned nb = (unsigned)(c < 2 ? count[c] : 1);
+    dim3 grid(nb, (unsigned)((a.n[AX_A] + TT - 1) / TT), (unsigned)a.n[AX_B]);
+    hipLaunchKernelGGL((sweep_vjp_kernel<ORDER, NDIM, DIR, TT, TN, GENERAL>), grid, dim3(TT * TN), 0, st, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // The whole-tile shapes: x (and 1D) TENOAA_ADJ_TT_X x TENOAA_ADJ_TN_X, y and

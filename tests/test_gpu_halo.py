@@ -180,7 +180,7 @@ def test_pieces_rhs_vjp_sum_to_whole(case, splitting):
     """The adjoint of a split right-hand side: each piece's tenoaa_rhs_vjp_halo
     gives the adjoint of its own cells and of its halo cells; adding every
     halo adjoint to the neighbour's cells it came from gives the whole grid's
-    tenoaa_rhs_vjp (up to the order of the atomic sums)."""
+    tenoaa_rhs_vjp (up to the order of the sums)."""
     shape, d, cuts = CUTS[case]
     order, G = 10, 5
     U = torch.from_numpy(_state(shape)).cuda()
@@ -211,7 +211,7 @@ def test_pieces_step_adjoint_equals_whole(case):
     tenoaa_rhs_vjp_halo with the stages' transposes (the chain
     tenoaa_step_vjp runs in one piece) and a reverse halo exchange per stage,
     equals the whole grid's tenoaa_step_vjp (limiter off; up to the order of
-    the atomic sums)."""
+    the sums)."""
     shape, d, cuts = CUTS[case]
     order, G = 10, 5
     ax = _ax(4, d)
