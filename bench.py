@@ -280,7 +280,8 @@ def batched_leg(nprob=512, nsteps=20, tune_cache=None, compare=True):
            "face_recons": faces, "batched_ms": round(t_batch * 1e3, 2),
            "value": round(faces / t_batch / 1e9, 4), "unit": "Gface-recon/s",
            "barrier_wait_share": round(stats["barrier_wait_share"], 4),
-           "wait_per_barrier_us": round(stats["wait_per_barrier_us"], 2)}
+           "wait_per_barrier_us": round(stats["wait_per_barrier_us"], 2),
+           "sweep_item_share": round(stats["sweep_share"], 4), "cell_item_share": round(stats["cell_share"], 4)}
     if not compare:
         res.update({"plan": plan.info(), "plan_create_s": round(t_plan, 3), "roofline": roofline})
         return res

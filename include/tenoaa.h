@@ -375,12 +375,14 @@ int tenoaa_batch_get_status(tenoaa_batch_plan* plan, void* stream, int32_t* stat
 
 /* Synchronises `stream` and reports how the blocks of the last
  * tenoaa_batch_run spent their time (read from per-block wall-clock counters
- * the persistent kernel keeps): out (host, n >= 3 entries) receives the share
+ * the persistent kernel keeps): out (host, n >= 5 entries) receives the share
  * of the blocks' resident time spent waiting at phase barriers (imbalance
  * between blocks plus the barrier's own latency), the mean time a block was
- * resident in seconds, and the mean wait per block and barrier in
- * microseconds.  Meaningful only after a run that completed; EINVAL for a
- * null plan or out, or n < 3; EHIP on a HIP failure. */
+ * resident in seconds, the mean wait per block and barrier in microseconds,
+ * and the shares of the resident time spent in sweep items and in update and
+ * wave-speed items (the rest: taking items from the queue).  Meaningful only
+ * after a run that completed; EINVAL for a null plan or out, or n < 5; EHIP
+ * on a HIP failure. */
 int tenoaa_batch_run_stats(tenoaa_batch_plan* plan, void* stream, double* out, int32_t n);
 
 /* Launch choices of a plan: info (host, n >= 10 entries) receives blocks

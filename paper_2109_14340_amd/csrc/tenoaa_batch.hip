@@ -97,7 +97,8 @@ struct BatchArgs {
   double* dt_out;             // [orig][nsteps] or null
   int* status;                // [nprob] non-physical-state words
   unsigned long long* ctl;    // [0] barrier arrivals, [1] abort, [2 + phase] item counters
-  unsigned long long* bstat;  // per block: [2 b] ticks waited at phase barriers, [2 b + 1] ticks resident
+  unsigned long long* bstat;  // per block b, ticks: [4 b] waited at phase barriers, [4 b + 1] resident,
+                              // [4 b + 2] in sweep items, [4 b + 3] in update and wave-speed items
   double gamma, cfl;
   int64_t timeout_ticks;
   int32_t nprob, nsteps, splitting, chunk;
@@ -323,7 +324,7 @@ __device__ __forceinline__ bool grid_barrier(const BatchArgs& B, unsigned long l
       }
       __builtin_amdgcn_s_sleep(2);
     }
-    B.bstat[2 * blockIdx.x] += wall_clock64() - t0;
+    B.bstat[4 * blockIdx.x] += wall_clock64() - t0;
     __threadfence();
     *s_flag = ok;
   }
@@ -341,6 +342,7 @@ void batch_kernel(BatchArgs B) {
   __shared__ int64_t s_first;
   __shared__ int s_flag;
   const uint64_t t_start = wall_clock64();
+  uint64_t t_sweep = 0, t_cell = 0;  // thread 0's ticks in the items of each kind
   const int nphase = 1 + 6 * B.nsteps;
   for (int ph = 0; ph < nphase; ++ph) {
     int kind = 0, n = 0, stage = 0;
@@ -363,6 +365,7 @@ void batch_kernel(BatchArgs B) {
       const int64_t first = s_first;
       if (first >= total) break;
       const int64_t last = (first + B.chunk < total) ? first + B.chunk : total;
+      const uint64_t t_items = wall_clock64();
       for (int64_t it = first; it < last; ++it) {
         if (it > first) __syncthreads();
         const int p = find_problem(pre, B.nprob, it);
@@ -379,10 +382,15 @@ void batch_kernel(BatchArgs B) {
           update_item<3, BV>(B, arena, p, k, n);
         }
       }
+      if (threadIdx.x == 0) (kind == 1 ? t_sweep : t_cell) += wall_clock64() - t_items;
     }
     if (ph + 1 < nphase && !grid_barrier(B, (unsigned long long)(ph + 1) * gridDim.x, &s_flag)) return;
   }
-  if (threadIdx.x == 0) B.bstat[2 * blockIdx.x + 1] = wall_clock64() - t_start;
+  if (threadIdx.x == 0) {
+    B.bstat[4 * blockIdx.x + 1] = wall_clock64() - t_start;
+    B.bstat[4 * blockIdx.x + 2] = t_sweep;
+    B.bstat[4 * blockIdx.x + 3] = t_cell;
+  }
 }
 
 // Uniform state for tuning runs: rho = 1, u = 0.3, v = 0.2, p = 1.
@@ -805,7 +813,7 @@ int tenoaa_batch_plan_create(const tenoaa_grid* grids, int32_t nprob, const teno
     f_total += 4 * (faces_along2(g, 0) * g.n[1] + faces_along2(g, 1) * g.n[0]);
   }
   P->nctl_queue = 2 + 1 + 6 * (int64_t)nsteps;
-  P->nctl = P->nctl_queue + 2 * (int64_t)P->ncu * P->max_bpc;
+  P->nctl = P->nctl_queue + 4 * (int64_t)P->ncu * P->max_bpc;
   P->rate_khz = rate_khz > 0 ? rate_khz : 100000;
   e = hipMalloc(&P->d_table, sizeof(BatchProblem) * nprob);
   if (e == hipSuccess) e = hipMalloc(&P->d_pre, sizeof(int64_t) * 2 * (nprob + 1));
@@ -896,24 +904,29 @@ int tenoaa_batch_get_status(tenoaa_batch_plan* plan, void* stream, int32_t* stat
 }
 
 int tenoaa_batch_run_stats(tenoaa_batch_plan* plan, void* stream, double* out, int32_t n) {
-  if (!plan || !out || n < 3) return TENOAA_EINVAL;
+  if (!plan || !out || n < 5) return TENOAA_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int nblk = plan->ncu * plan->bpc;
-  std::vector<unsigned long long> b(2 * (size_t)nblk);
+  std::vector<unsigned long long> b(4 * (size_t)nblk);
   hipError_t e = hipStreamSynchronize(st);
   if (e == hipSuccess)
     e = hipMemcpy(b.data(), plan->d_ctl + plan->nctl_queue, sizeof(unsigned long long) * b.size(),
                   hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail_hip(e);
-  double wait = 0.0, resident = 0.0;
+  double wait = 0.0, resident = 0.0, sweep = 0.0, cell = 0.0;
   for (int i = 0; i < nblk; ++i) {
-    wait += (double)b[2 * i];
-    resident += (double)b[2 * i + 1];
+    wait += (double)b[4 * i];
+    resident += (double)b[4 * i + 1];
+    sweep += (double)b[4 * i + 2];
+    cell += (double)b[4 * i + 3];
   }
   const double nbar = 6.0 * plan->nsteps;
-  out[0] = resident > 0.0 ? wait / resident : 0.0;
+  const double r = resident > 0.0 ? 1.0 / resident : 0.0;
+  out[0] = wait * r;
   out[1] = resident / nblk / plan->rate_khz * 1e-3;
   out[2] = wait / nblk / nbar / plan->rate_khz * 1e3;
+  out[3] = sweep * r;
+  out[4] = cell * r;
   return TENOAA_OK;
 }
 

@@ -479,12 +479,15 @@ class BatchPlan:
                 "tile_x": v[4:7], "tile_y": v[7:10]}
 
     def run_stats(self):
-        """Synchronises; barrier figures of the last run: the share of the
-        blocks' resident time spent waiting at phase barriers, the mean time a
-        block was resident (s) and the mean wait per block and barrier (us)."""
-        buf = (ctypes.c_double * 3)()
-        _check(load().tenoaa_batch_run_stats(self._h, _stream(), buf, 3), "tenoaa_batch_run_stats")
-        return {"barrier_wait_share": buf[0], "resident_s": buf[1], "wait_per_barrier_us": buf[2]}
+        """Synchronises; where the blocks of the last run spent their resident
+        time: shares waiting at phase barriers, in sweep items and in update
+        and wave-speed items (the rest: taking items from the queue), the
+        mean time a block was resident (s) and the mean wait per block and
+        barrier (us)."""
+        buf = (ctypes.c_double * 5)()
+        _check(load().tenoaa_batch_run_stats(self._h, _stream(), buf, 5), "tenoaa_batch_run_stats")
+        return {"barrier_wait_share": buf[0], "resident_s": buf[1], "wait_per_barrier_us": buf[2],
+                "sweep_share": buf[3], "cell_share": buf[4]}
 
     def pack(self, states, device="cuda"):
         """Packed float64 device tensor of the problems' (4, 1, ny, nx) states."""

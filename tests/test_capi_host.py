@@ -210,7 +210,7 @@ def test_batch_plan_rejects_bad_arguments():
     assert L.tenoaa_batch_run(None, vp(256), None, None) == -1
     assert L.tenoaa_batch_get_status(None, None, None) == -1
     assert L.tenoaa_batch_plan_info(None, None, 10) == -1
-    assert L.tenoaa_batch_run_stats(None, None, None, 3) == -1
+    assert L.tenoaa_batch_run_stats(None, None, None, 5) == -1
     assert L.tenoaa_batch_plan_destroy(None) == -1
 
 

@@ -88,6 +88,8 @@ def test_batch_bitwise_equals_per_problem(tiles, tmp_path):
     print(rs)
     # every block waits at each of the 6 * nsteps barriers, and for less than it was resident
     assert 0.0 < rs["barrier_wait_share"] < 1.0 and rs["resident_s"] > 0.0 and rs["wait_per_barrier_us"] > 0.0
+    assert 0.0 < rs["sweep_share"] < 1.0 and 0.0 < rs["cell_share"] < 1.0
+    assert rs["barrier_wait_share"] + rs["sweep_share"] + rs["cell_share"] <= 1.0
     ref, dtr = _per_problem(grids, states, sch, nsteps)
     _assert_same(plan, packed, dtb, ref, dtr)
 
