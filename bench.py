@@ -108,8 +108,21 @@ def fwd_adj_leg(shape, steps, warmup, U0, positivity):
     def adj():
         tenoaa.step_vjp(grid, sch, U0, dt, bar, gamma=1.4, out=out, ws=wsv)
 
+    # the taped pair: the step keeps its stage states and records (one
+    # TENOAA_WS_STEP_TAPE workspace), the adjoint runs only the reverse sweeps
+    wst = tenoaa.workspace(grid, sch, tenoaa.WS_STEP_TAPE, dev)
+    dtt = torch.zeros(1, dtype=torch.float64, device=dev)
+    Ut = torch.empty_like(U0)
+
+    def fwd_tape():
+        dtt.zero_()
+        tenoaa.step_tape(grid, sch, U0, dtt, gamma=1.4, cfl=0.4, out=Ut, ws=wst)
+
+    def adj_tape():
+        tenoaa.step_vjp_tape(grid, sch, U0, dtt, bar, wst, gamma=1.4, out=out)
+
     res = {}
-    for name, fn in (("fwd", fwd), ("adj", adj)):
+    for name, fn in (("fwd", fwd), ("adj", adj), ("fwd_tape", fwd_tape), ("adj_tape", adj_tape)):
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -123,7 +136,12 @@ def fwd_adj_leg(shape, steps, warmup, U0, positivity):
             "adj_over_fwd": round(res["adj"] / res["fwd"], 3),
             "value": round(work / ((res["fwd"] + res["adj"]) * 1e-3) / 1e9, 4), "unit": "Gface-recon/s",
             "note": "face reconstructions of the forward step / (step + step VJP time); the forward "
-                    "copy of the input state is inside fwd_ms"}
+                    "copy of the input state is inside fwd_ms",
+            "tape": {"fwd_ms": round(res["fwd_tape"], 3), "adj_ms": round(res["adj_tape"], 3),
+                     "value": round(work / ((res["fwd_tape"] + res["adj_tape"]) * 1e-3) / 1e9, 4),
+                     "workspace_bytes": int(wst.numel()),
+                     "note": "tenoaa_step_tape (the step keeping its stage states and records) + "
+                             "tenoaa_step_vjp_tape (reverse sweeps only), bit-identical to the pair above"}}
 
 
 def slab_leg(U0, pieces=8, steps=5, warmup=1):

@@ -106,8 +106,10 @@ enum {
  * whose recorded byte is 0 is not reconstructed. */
 enum { TENOAA_LLF = 0, TENOAA_RUSANOV = 1, TENOAA_ROE = 2 };
 
-/* Workspace purposes for tenoaa_workspace_bytes. */
-enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1, TENOAA_WS_RHS_VJP = 2, TENOAA_WS_STEP_VJP = 3 };
+/* Workspace purposes for tenoaa_workspace_bytes: tenoaa_rhs (and the split-
+ * grid pieces), tenoaa_step, tenoaa_rhs_vjp, tenoaa_step_vjp, and the taped
+ * step (tenoaa_step_tape and tenoaa_step_vjp_tape). */
+enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1, TENOAA_WS_RHS_VJP = 2, TENOAA_WS_STEP_VJP = 3, TENOAA_WS_STEP_TAPE = 4 };
 
 /* Uniform cell-centred grid: cell i of direction d has centre (i + 1/2) dx[d].
  * n[d] >= order/2 for d < ndim and n[d] == 1 otherwise; dx[d] > 0; in 2D
@@ -132,8 +134,9 @@ enum { TENOAA_WS_RHS = 0, TENOAA_WS_STEP = 1, TENOAA_WS_RHS_VJP = 2, TENOAA_WS_S
  * array than this is undefined behaviour (the library cannot check device
  * allocations).  The batch plan takes Dirichlet and inflow sides with one
  * value set (used by every step of a run) and without the Roe flux, and
- * rejects other cases with TENOAA_EUNSUPPORTED; tenoaa_rhs_vjp and
- * tenoaa_step_vjp reject halo sides (tenoaa_rhs_vjp_halo takes them).  The adjoint entry points differentiate a Dirichlet
+ * rejects other cases with TENOAA_EUNSUPPORTED; tenoaa_rhs_vjp,
+ * tenoaa_step_vjp and the taped step reject halo sides (tenoaa_rhs_vjp_halo
+ * takes them).  The adjoint entry points differentiate a Dirichlet
  * ghost through its reflection rule (the face values are constants), take
  * inflow ghosts as constants, and read set s in stage s as the step does. */
 typedef struct {
@@ -245,6 +248,32 @@ int tenoaa_rhs_vjp_halo(const tenoaa_grid* grid, const tenoaa_scheme* scheme, do
 int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* Un,
                     const double* dt_dev, const double* Unp1_bar, double* Un_bar, const uint8_t* flags3, void* ws,
                     size_t ws_bytes, void* stream);
+
+/* One SSP-RK3 step (Sec. 5) that keeps what its adjoint needs: Unp1 =
+ * U^{n+1} from Un, bit for bit what tenoaa_step gives on a copy of Un (same
+ * dt rule: *dt_dev <= 0 on entry takes dt from the CFL condition and stores
+ * it there, a positive value is used as given; the same limits on cfl), and
+ * ws (TENOAA_WS_STEP_TAPE bytes) left holding the step's tape: the two
+ * intermediate stage states and every stage's decisions, per-field fluxes
+ * and limiter factors.  tenoaa_step_vjp_tape then runs only the reverse
+ * sweeps, where tenoaa_step_vjp recomputes the stages first.  The tape is
+ * two states plus about 5 (1D) to 7 (3D) doubles per face, direction and
+ * stage (the whole workspace is 14 GB for a 256^3 TENO10-AA step with the
+ * limiter), kept as long as the caller keeps ws.  Unp1 must not alias Un.  EINVAL for null
+ * pointers or a bad cfl, EWORKSPACE, EUNSUPPORTED for halo sides. */
+int tenoaa_step_tape(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl,
+                     const double* Un, double* dt_dev, double* Unp1, void* ws, size_t ws_bytes, void* stream);
+
+/* The vector-Jacobian product of the step whose tape tenoaa_step_tape left
+ * in ws: Un_bar (overwritten) = (d U^{n+1} / d Un)^T Unp1_bar with every
+ * decision, limiter factor and dt frozen as in tenoaa_step_vjp (equal to it
+ * bit for bit).  Un and dt_dev must be the step's own (unchanged since the
+ * tape was taken; the tape is not checked against them); the tape stays
+ * whole, so several seeds may use it.  Un_bar must not alias Un or
+ * Unp1_bar.  Same errors as tenoaa_step_vjp. */
+int tenoaa_step_vjp_tape(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* Un,
+                         const double* dt_dev, const double* Unp1_bar, double* Un_bar, void* ws, size_t ws_bytes,
+                         void* stream);
 
 /* Wave speeds a_d = max (|u_d| + c) over the cells of U and the first ghost
  * layer of every side with prescribed or halo values (value set 0), d <

@@ -8,7 +8,11 @@ decisions are frozen at the states the forward pass visited.  Only every
 `checkpoint_every`-th state is kept: the backward pass recomputes each
 segment from its checkpoint (bitwise the same states, since the kernels are
 deterministic and dt is replayed) and chains `tenoaa_step_vjp` backwards
-through it.
+through it.  With `tape=True` the recomputation keeps each step's tape
+(`tenoaa_step_tape`: the stage states and every stage's decisions and
+fluxes, one workspace per step of the segment) and the reverse pass runs
+`tenoaa_step_vjp_tape`, which skips the stage recomputation inside each
+step's adjoint; the gradient is the same bit for bit.
 """
 import torch
 
@@ -17,7 +21,7 @@ from . import tenoaa
 
 class _RK3Trajectory(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, U0, grid, scheme, gamma, cfl, nsteps, every):
+    def forward(ctx, U0, grid, scheme, gamma, cfl, nsteps, every, tape):
         if nsteps < 1 or every < 1:
             raise ValueError("nsteps and checkpoint_every must be positive")
         U = U0.detach().clone()
@@ -29,7 +33,7 @@ class _RK3Trajectory(torch.autograd.Function):
             if (n + 1) % every == 0 and n + 1 < nsteps:
                 ckpts.append(U.clone())
         ctx.grid, ctx.scheme, ctx.gamma, ctx.cfl = grid, scheme, gamma, cfl
-        ctx.nsteps, ctx.every = nsteps, every
+        ctx.nsteps, ctx.every, ctx.tape = nsteps, every, tape
         ctx.save_for_backward(dts, *ckpts)
         return U
 
@@ -46,6 +50,19 @@ class _RK3Trajectory(torch.autograd.Function):
             s0 = seg * ctx.every
             s1 = min(s0 + ctx.every, ctx.nsteps)
             states = [ckpts[seg]]
+            if ctx.tape:
+                tapes = []
+                for n in range(s0, s1):
+                    U, wt = tenoaa.step_tape(grid, scheme, states[-1], dts[n:n + 1], gamma=gamma, cfl=ctx.cfl)
+                    tapes.append(wt)
+                    if n + 1 < s1:
+                        states.append(U)
+                for n in reversed(range(s0, s1)):
+                    tenoaa.step_vjp_tape(grid, scheme, states[n - s0], dts[n:n + 1], bar, tapes[n - s0],
+                                         gamma=gamma, out=nxt)
+                    bar, nxt = nxt, bar
+                    tapes[n - s0] = None
+                continue
             U = ckpts[seg].clone()
             for n in range(s0, s1 - 1):
                 tenoaa.step(grid, scheme, U, dts[n:n + 1], gamma=gamma, cfl=ctx.cfl, ws=ws)
@@ -53,12 +70,15 @@ class _RK3Trajectory(torch.autograd.Function):
             for n in reversed(range(s0, s1)):
                 tenoaa.step_vjp(grid, scheme, states[n - s0], dts[n:n + 1], bar, gamma=gamma, out=nxt, ws=ws_vjp)
                 bar, nxt = nxt, bar
-        return bar, None, None, None, None, None, None
+        return bar, None, None, None, None, None, None, None
 
 
-def rk3_trajectory(U0, grid, scheme, nsteps, checkpoint_every=10, gamma=1.4, cfl=0.4):
-    """Final state after nsteps SSP-RK3 steps; differentiable w.r.t. U0."""
-    return _RK3Trajectory.apply(U0, grid, scheme, gamma, cfl, nsteps, checkpoint_every)
+def rk3_trajectory(U0, grid, scheme, nsteps, checkpoint_every=10, gamma=1.4, cfl=0.4, tape=False):
+    """Final state after nsteps SSP-RK3 steps; differentiable w.r.t. U0.
+    tape: keep each recomputed step's tape in the backward pass (one
+    WS_STEP_TAPE workspace per step of a segment) instead of recomputing the
+    stages inside every step's adjoint."""
+    return _RK3Trajectory.apply(U0, grid, scheme, gamma, cfl, nsteps, checkpoint_every, tape)
 
 
 def record_trajectory(U0, grid, scheme, nsteps, gamma=1.4, cfl=0.4):

@@ -157,7 +157,8 @@ Layout layout(const tenoaa_grid* g, int which, bool limiter = false) {
   }
   // decisions and per-field fluxes of every direction, for one stage (RHS_VJP)
   // or the three stages of a step (STEP_VJP)
-  const int nstage = which == TENOAA_WS_STEP_VJP ? 3 : (which == TENOAA_WS_RHS_VJP ? 1 : 0);
+  const bool step_adj = which == TENOAA_WS_STEP_VJP || which == TENOAA_WS_STEP_TAPE;
+  const int nstage = step_adj ? 3 : (which == TENOAA_WS_RHS_VJP ? 1 : 0);
   for (int st = 0; st < 3; ++st) {
     for (int d = 0; d < 3; ++d) {
       L.vjp[st][d] = off;
@@ -173,6 +174,7 @@ Layout layout(const tenoaa_grid* g, int which, bool limiter = false) {
   const size_t state = align256((size_t)nv * (size_t)ncell * sizeof(double));
   if (which == TENOAA_WS_STEP) off += state;
   if (which == TENOAA_WS_STEP_VJP) off += 4 * state;  // U1, U2 (later B1), V, B2
+  if (which == TENOAA_WS_STEP_TAPE) off += 5 * state;  // U1, U2, V, B2, B1: the tape stays whole
   L.state_bytes = state;
   L.total = off;
   return L;
@@ -388,6 +390,49 @@ int prepare(Ctx& c, const tenoaa_grid* g, const tenoaa_scheme* s, double gamma, 
 // First device work of an entry point, after every argument check passed.
 int begin(const Ctx&) { return TENOAA_OK; }
 
+// The three stages of a step from Un with the speeds, dt and limiter weights
+// already in c.S: the sweeps of each stage record (or, with flags3, replay)
+// their decisions, per-field fluxes and limiter factors into the adjoint
+// slots; U1 -> S1, U2 -> S2; with Unp1 non-null also stage 3 -> Unp1 (the
+// arithmetic of tenoaa_step, so the result is the same bit for bit).
+int recorded_stages(const Ctx& c, const double* Un, double* S1, double* S2, const uint8_t* flags3, double* Unp1,
+                    bool limit) {
+  const int64_t nfl = flag_count(c.g);
+  auto stage_flags = [&](int st) { return flags3 ? flags3 + st * nfl : nullptr; };
+  int rc;
+  if ((rc = recorded_sweeps(c, Un, 0, stage_flags(0), limit))) return rc;
+  if ((rc = update(c, 1, Un, nullptr, S1))) return rc;
+  if ((rc = recorded_sweeps(c, S1, 1, stage_flags(1), limit))) return rc;
+  if ((rc = update(c, 2, Un, S1, S2))) return rc;
+  if ((rc = recorded_sweeps(c, S2, 2, stage_flags(2), limit))) return rc;
+  return Unp1 ? update(c, 3, Un, S2, Unp1) : TENOAA_OK;
+}
+
+// The reverse of the three stages from what recorded_stages left (S1, S2 and
+// the adjoint slots): Un_bar = (d U^{n+1} / d Un)^T Unp1_bar.  Scratch: the
+// workspace's V and B2 slots and B1 (which may be the S2 slot: it is written
+// after the stage-3 reverse sweep has read S2).
+int reverse_stages(const Ctx& c, const double* Un, const double* S1, const double* S2, const double* dt_dev,
+                   const double* Unp1_bar, double* Un_bar, double* B1, bool limit) {
+  const int64_t N = (int64_t)(c.g->ndim + 2) * c.g->n[0] * c.g->n[1] * c.g->n[2];
+  double* V = reinterpret_cast<double*>(c.ws + c.L.stage + 2 * c.L.state_bytes);
+  double* B2 = reinterpret_cast<double*>(c.ws + c.L.stage + 3 * c.L.state_bytes);
+  int rc;
+  hipError_t e;
+  // B2 = 2/3 B3 + 2/3 dt J(U2)^T B3
+  if ((rc = rhs_vjp(c, S2, Unp1_bar, V, 2, limit))) return rc;
+  if ((e = tenoaa::launch_axpdtz(B2, 2.0 / 3.0, Unp1_bar, 2.0 / 3.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
+  // B1 = 1/4 B2 + 1/4 dt J(U1)^T B2
+  if ((rc = rhs_vjp(c, S1, B2, V, 1, limit))) return rc;
+  if ((e = tenoaa::launch_axpdtz(B1, 0.25, B2, 0.25, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
+  // Bn = 1/3 B3 + 3/4 B2 + B1 + dt J(Un)^T B1
+  if ((rc = rhs_vjp(c, Un, B1, V, 0, limit))) return rc;
+  if ((e = tenoaa::launch_axpbypcz(Un_bar, 1.0 / 3.0, Unp1_bar, 0.75, B2, 1.0, B1, N, c.st)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = tenoaa::launch_axpdtz(Un_bar, 1.0, Un_bar, 1.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
+  return TENOAA_OK;
+}
+
 // One right-hand side (tenoaa_rhs after its argument checks).
 int rhs_body(const Ctx& c, const double* U, double* dUdt, double dt_limiter, uint8_t* flags) {
   const tenoaa_grid* grid = c.g;
@@ -456,7 +501,7 @@ extern "C" {
 
 size_t tenoaa_workspace_bytes(const tenoaa_grid* grid, const tenoaa_scheme* scheme, int32_t which) {
   if (!valid_grid(grid, scheme)) return 0;
-  if (which < TENOAA_WS_RHS || which > TENOAA_WS_STEP_VJP) return 0;
+  if (which < TENOAA_WS_RHS || which > TENOAA_WS_STEP_TAPE) return 0;
   return layout(grid, which, scheme->positivity != 0).total;
 }
 
@@ -627,12 +672,8 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
   if (tenoaa::has_halo(grid)) return TENOAA_EUNSUPPORTED;
   const bool limit = scheme->positivity != 0;
   if ((rc = begin(c))) return rc;
-  const int64_t N = (int64_t)(grid->ndim + 2) * grid->n[0] * grid->n[1] * grid->n[2];
   double* S1 = reinterpret_cast<double*>(c.ws + c.L.stage);
   double* S2 = reinterpret_cast<double*>(c.ws + c.L.stage + c.L.state_bytes);
-  double* V = reinterpret_cast<double*>(c.ws + c.L.stage + 2 * c.L.state_bytes);
-  double* B2 = reinterpret_cast<double*>(c.ws + c.L.stage + 3 * c.L.state_bytes);
-  double* B1 = S2;
   hipError_t e;
   // recompute the stages, recording each stage's decisions and per-field
   // fluxes: U1 = Un + dt L(Un), U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1), and the
@@ -651,25 +692,47 @@ int tenoaa_step_vjp(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double
     e = hipGetLastError();
   }
   if (e != hipSuccess) return hip_fail(e);
-  const int64_t nfl = flag_count(grid);
-  auto stage_flags = [&](int st) { return flags3 ? flags3 + st * nfl : nullptr; };
-  if ((rc = recorded_sweeps(c, Un, 0, stage_flags(0), limit))) return rc;
-  if ((rc = update(c, 1, Un, nullptr, S1))) return rc;
-  if ((rc = recorded_sweeps(c, S1, 1, stage_flags(1), limit))) return rc;
-  if ((rc = update(c, 2, Un, S1, S2))) return rc;
-  if ((rc = recorded_sweeps(c, S2, 2, stage_flags(2), limit))) return rc;
-  // reverse: B2 = 2/3 B3 + 2/3 dt J(U2)^T B3
-  if ((rc = rhs_vjp(c, S2, Unp1_bar, V, 2, limit))) return rc;
-  if ((e = tenoaa::launch_axpdtz(B2, 2.0 / 3.0, Unp1_bar, 2.0 / 3.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
-  // B1 = 1/4 B2 + 1/4 dt J(U1)^T B2
-  if ((rc = rhs_vjp(c, S1, B2, V, 1, limit))) return rc;
-  if ((e = tenoaa::launch_axpdtz(B1, 0.25, B2, 0.25, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
-  // Bn = 1/3 B3 + 3/4 B2 + B1 + dt J(Un)^T B1
-  if ((rc = rhs_vjp(c, Un, B1, V, 0, limit))) return rc;
-  if ((e = tenoaa::launch_axpbypcz(Un_bar, 1.0 / 3.0, Unp1_bar, 0.75, B2, 1.0, B1, N, c.st)) != hipSuccess)
-    return hip_fail(e);
-  if ((e = tenoaa::launch_axpdtz(Un_bar, 1.0, Un_bar, 1.0, dt_dev, V, N, c.st)) != hipSuccess) return hip_fail(e);
-  return TENOAA_OK;
+  if ((rc = recorded_stages(c, Un, S1, S2, flags3, nullptr, limit))) return rc;
+  // the second stage state's slot holds B1 once the stage-3 reverse sweep has read it
+  return reverse_stages(c, Un, S1, S2, dt_dev, Unp1_bar, Un_bar, S2, limit);
+}
+
+int tenoaa_step_tape(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, double cfl,
+                     const double* Un, double* dt_dev, double* Unp1, void* ws, size_t ws_bytes, void* stream) {
+  Ctx c;
+  int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP_TAPE);
+  if (rc) return rc;
+  if (!Un || !dt_dev || !Unp1 || Unp1 == Un) return TENOAA_EINVAL;
+  if (!(cfl > 0.0) || cfl > 1.0) return TENOAA_EINVAL;
+  if (scheme->positivity && cfl > 0.5) return TENOAA_EINVAL;
+  if (tenoaa::has_halo(grid)) return TENOAA_EUNSUPPORTED;
+  const bool limit = scheme->positivity != 0;
+  if ((rc = begin(c))) return rc;
+  double* S1 = reinterpret_cast<double*>(c.ws + c.L.stage);
+  double* S2 = reinterpret_cast<double*>(c.ws + c.L.stage + c.L.state_bytes);
+  // the speeds, dt and limiter weights as tenoaa_step takes them
+  hipError_t e = timed(TENOAA_KCLASS_WAVESPEED, c.st, [&] {
+    hipError_t r = wave_speeds(c, Un);
+    if (r == hipSuccess) r = tenoaa::launch_finalize_dt(c.S, grid->ndim, grid->dx, cfl, dt_dev, 0.0, c.st);
+    return r;
+  });
+  if (e != hipSuccess) return hip_fail(e);
+  return recorded_stages(c, Un, S1, S2, nullptr, Unp1, limit);
+}
+
+int tenoaa_step_vjp_tape(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* Un,
+                         const double* dt_dev, const double* Unp1_bar, double* Un_bar, void* ws, size_t ws_bytes,
+                         void* stream) {
+  Ctx c;
+  int rc = prepare(c, grid, scheme, gamma, ws, ws_bytes, stream, TENOAA_WS_STEP_TAPE);
+  if (rc) return rc;
+  if (!Un || !dt_dev || !Unp1_bar || !Un_bar || Un_bar == Unp1_bar || Un_bar == Un) return TENOAA_EINVAL;
+  if (tenoaa::has_halo(grid)) return TENOAA_EUNSUPPORTED;
+  if ((rc = begin(c))) return rc;
+  double* S1 = reinterpret_cast<double*>(c.ws + c.L.stage);
+  double* S2 = reinterpret_cast<double*>(c.ws + c.L.stage + c.L.state_bytes);
+  double* B1 = reinterpret_cast<double*>(c.ws + c.L.stage + 4 * c.L.state_bytes);
+  return reverse_stages(c, Un, S1, S2, dt_dev, Unp1_bar, Un_bar, B1, scheme->positivity != 0);
 }
 
 int tenoaa_wave_speeds(const tenoaa_grid* grid, const tenoaa_scheme* scheme, double gamma, const double* U,

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libtenoaa.so")
 
 BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY, BC_NOSLIP, BC_DIRICHLET, BC_INFLOW, BC_HALO = 0, 1, 2, 3, 4, 5, 6
 LLF, RUSANOV, ROE = 0, 1, 2
-WS_RHS, WS_STEP, WS_RHS_VJP, WS_STEP_VJP = 0, 1, 2, 3
+WS_RHS, WS_STEP, WS_RHS_VJP, WS_STEP_VJP, WS_STEP_TAPE = 0, 1, 2, 3, 4
 ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EHIP", -4: "ENONPHYSICAL", -5: "EWORKSPACE", -6: "ETIMEOUT"}
 
 FLAGS_NONE, FLAGS_RECORD, FLAGS_REPLAY = 0, 1, 2
@@ -23,7 +23,8 @@ EXPORTS = ["tenoaa_workspace_bytes", "tenoaa_rhs", "tenoaa_step", "tenoaa_step_f
            "tenoaa_get_status", "tenoaa_last_hip_error", "tenoaa_timing_enable", "tenoaa_timing_read",
            "tenoaa_batch_plan_create", "tenoaa_batch_offsets", "tenoaa_batch_run", "tenoaa_batch_get_status",
            "tenoaa_batch_plan_info", "tenoaa_batch_run_stats", "tenoaa_batch_plan_destroy", "tenoaa_advect", "tenoaa_wave_speeds",
-           "tenoaa_rk3_stage", "tenoaa_rhs_vjp_halo", "tenoaa_step_near", "tenoaa_rhs_noalloc"]
+           "tenoaa_rk3_stage", "tenoaa_rhs_vjp_halo", "tenoaa_step_near", "tenoaa_rhs_noalloc",
+           "tenoaa_step_tape", "tenoaa_step_vjp_tape"]
 KCLASS_SWEEP = (0, 1, 2)
 KCLASS_UPDATE, KCLASS_WAVESPEED = 3, 4
 KCLASS_VJP = (5, 6, 7)
@@ -74,6 +75,10 @@ def load():
         L.tenoaa_rhs_vjp.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.tenoaa_step_vjp.restype = ctypes.c_int
         L.tenoaa_step_vjp.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tenoaa_step_tape.restype = ctypes.c_int
+        L.tenoaa_step_tape.argtypes = [gp, sp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.tenoaa_step_vjp_tape.restype = ctypes.c_int
+        L.tenoaa_step_vjp_tape.argtypes = [gp, sp, ctypes.c_double, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.tenoaa_get_status.restype = ctypes.c_int
         L.tenoaa_get_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
         L.tenoaa_last_hip_error.restype = ctypes.c_int
@@ -344,6 +349,38 @@ def step_vjp(grid, scheme, Un, dt_dev, Unp1_bar, gamma=1.4, out=None, ws=None, f
     rc = load().tenoaa_step_vjp(ctypes.byref(grid), ctypes.byref(scheme), gamma, _ptr(Un), _ptr(dt_dev),
                                 _ptr(Unp1_bar), _ptr(out), _ptr(flags3), _ptr(ws), ws.numel(), _stream())
     _check(rc, "tenoaa_step_vjp")
+    return out
+
+
+def step_tape(grid, scheme, Un, dt_dev, gamma=1.4, cfl=0.4, out=None, ws=None):
+    """One SSP-RK3 step of Un into `out` (Un kept), as tenoaa_step computes it,
+    leaving its tape in `ws` (a WS_STEP_TAPE workspace) for step_vjp_tape:
+    returns (out, ws)."""
+    import torch
+    _check_state(Un, grid)
+    _check_boundary_values(grid, scheme)
+    if out is None:
+        out = torch.empty_like(Un)
+    if ws is None:
+        ws = workspace(grid, scheme, WS_STEP_TAPE, Un.device)
+    rc = load().tenoaa_step_tape(ctypes.byref(grid), ctypes.byref(scheme), gamma, cfl, _ptr(Un), _ptr(dt_dev),
+                                 _ptr(out), _ptr(ws), ws.numel(), _stream())
+    _check(rc, "tenoaa_step_tape")
+    return out, ws
+
+
+def step_vjp_tape(grid, scheme, Un, dt_dev, Unp1_bar, ws, gamma=1.4, out=None):
+    """step_vjp from the tape step_tape(Un, dt_dev) left in `ws` (no
+    recomputation of the stages)."""
+    import torch
+    _check_state(Un, grid)
+    _check_state(Unp1_bar, grid)
+    _check_boundary_values(grid, scheme)
+    if out is None:
+        out = torch.empty_like(Un)
+    rc = load().tenoaa_step_vjp_tape(ctypes.byref(grid), ctypes.byref(scheme), gamma, _ptr(Un), _ptr(dt_dev),
+                                     _ptr(Unp1_bar), _ptr(out), _ptr(ws), ws.numel(), _stream())
+    _check(rc, "tenoaa_step_vjp_tape")
     return out
 
 

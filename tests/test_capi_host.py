@@ -214,6 +214,28 @@ def test_batch_plan_rejects_bad_arguments():
     assert L.tenoaa_batch_plan_destroy(None) == -1
 
 
+def test_step_tape_arguments_checked():
+    """The taped step and its adjoint check their pointers, aliasing, cfl and
+    workspace size before any device work; its workspace holds one state
+    more than the recomputing step adjoint's."""
+    L = tenoaa.load()
+    vp = ctypes.c_void_p
+    g = tenoaa.make_grid((64, 48))
+    s = tenoaa.make_scheme(10, tenoaa.LLF, 1)
+    big = L.tenoaa_workspace_bytes(ctypes.byref(g), ctypes.byref(s), tenoaa.WS_STEP_TAPE)
+    small = L.tenoaa_workspace_bytes(ctypes.byref(g), ctypes.byref(s), tenoaa.WS_STEP_VJP)
+    assert big == small + 4 * 64 * 48 * 8  # one more state (nvar 4, 64 x 48 cells)
+    assert L.tenoaa_workspace_bytes(ctypes.byref(g), ctypes.byref(s), 5) == 0
+    ws, u, v, dt = vp(1 << 20), vp(2 << 20), vp(3 << 20), vp(4 << 20)
+    gr, sc = ctypes.byref(g), ctypes.byref(s)
+    assert L.tenoaa_step_tape(gr, sc, 1.4, 0.4, None, dt, v, ws, big, None) == -1
+    assert L.tenoaa_step_tape(gr, sc, 1.4, 0.4, u, dt, u, ws, big, None) == -1  # out aliases Un
+    assert L.tenoaa_step_tape(gr, sc, 1.4, 0.6, u, dt, v, ws, big, None) == -1  # cfl > 0.5 with the limiter
+    assert L.tenoaa_step_tape(gr, sc, 1.4, 0.4, u, dt, v, ws, big - 256, None) == -5  # workspace too small
+    assert L.tenoaa_step_vjp_tape(gr, sc, 1.4, u, dt, v, v, ws, big, None) == -1  # Un_bar aliases the seed
+    assert L.tenoaa_step_vjp_tape(gr, sc, 1.4, u, dt, v, None, ws, big, None) == -1
+
+
 def test_batch_cache_key_buckets():
     s = tenoaa.make_scheme(8)
     grids = [tenoaa.make_grid((n, 64)) for n in (64, 160, 161, 320, 321, 512)]
