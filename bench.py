@@ -78,7 +78,94 @@ def cpu_baseline(n=72):
     return {"value": work / el / 1e9, "unit": "Gface-recon/s", "cores": 1, "kind": "oracle",
             "sample": "one SSP-RK3 step (TENO10-AA, LLF, limiter, CFL 0.4) of the same recipe on a "
                       "%d^3 periodic grid: %d face reconstructions in %.2f s, one thread of %s (%d visible "
-                      "cores)" % (n, work, el, model, os.cpu_count() or 0)}
+                      "cores)" % (n, work, el, model, os.cpu_count() or 0),
+            "legs": cpu_legs()}
+
+
+def cpu_legs():
+    """The oracle on the other workloads (bounded samples), single-threaded:
+    the 1D shock tube (100 steps at N = 256, TENO8-AA, outflow: the whole
+    workload), one 2D right-hand side with TENO8-AA and with TENO10-AA on a
+    512^2 sample of the 1024^2 recipe, and the forward-mode step derivative
+    (the oracle's adjoint check) of one TENO10-AA step on a 256^2 sample of
+    the 512^2 adjoint recipe."""
+    import numpy as np
+    import oracle
+    from paper_2109_14340_amd import inputs
+
+    out = {}
+    U = inputs.shock_tube_1d(256)
+    g = oracle.make_grid((256,), [1.0 / 256], [1], [1])
+    t = time.perf_counter()
+    for _ in range(100):
+        U, _, _, _ = oracle.step(g, U, order=8, splitting=0, cfl=0.4)
+    el = time.perf_counter() - t
+    out["1d_256_teno8_100_steps"] = {"s": round(el, 3), "value": 3 * 257 * 100 / el / 1e9, "unit": "Gface-recon/s"}
+    n = 512
+    U = inputs.grf_2d(1024)[:, :, :n, :n].copy()
+    g = oracle.make_grid((n, n), [1.0 / 1024] * 2, [0, 0])
+    for order in (8, 10):
+        t = time.perf_counter()
+        oracle.rhs(g, U, order=order, splitting=0, want_flags=False)
+        el = time.perf_counter() - t
+        out["2d_%d_sample_rhs_teno%d" % (n, order)] = {"s": round(el, 3), "value": 2 * n * n / el / 1e9,
+                                                       "unit": "Gface-recon/s"}
+    n = 256
+    U = inputs.grf_2d(512, jump=False)[:, :, :n, :n].copy()
+    g = oracle.make_grid((n, n), [1.0 / 512] * 2, [0, 0])
+    _, dt, fl3, _ = oracle.step(g, U, order=10, splitting=0, cfl=0.4, want_flags=True)
+    V = np.random.default_rng(0).standard_normal(U.shape)
+    t = time.perf_counter()
+    oracle.step_jvp(g, U, V, dt, fl3, order=10, splitting=0)
+    el = time.perf_counter() - t
+    out["2d_%d_sample_step_jvp_teno10" % n] = {"s": round(el, 3), "value": 3 * 2 * n * n / el / 1e9,
+                                               "unit": "Gface-recon/s"}
+    return out
+
+
+def gpu_legs(dev):
+    """The other workloads on the GPU: the 1D shock tube (100 steps at
+    N = 256, TENO8-AA, outflow) and one 2D 1024^2 right-hand side with
+    TENO8-AA and with TENO10-AA (periodic)."""
+    import torch
+
+    from paper_2109_14340_amd import inputs, tenoaa
+
+    out = {}
+    grid = tenoaa.make_grid((256,), bc_lo=[tenoaa.BC_OUTFLOW], bc_hi=[tenoaa.BC_OUTFLOW])
+    sch = tenoaa.make_scheme(8, tenoaa.LLF, 0)
+    U0 = torch.from_numpy(inputs.shock_tube_1d(256)).to(dev)
+    ws = tenoaa.workspace(grid, sch, tenoaa.WS_STEP, dev)
+    dts = torch.zeros(100, dtype=torch.float64, device=dev)
+    for rep_ in range(2):
+        U = U0.clone()
+        dts.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(100):
+            tenoaa.step(grid, sch, U, dts[k:k + 1], cfl=0.4, ws=ws)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+    out["1d_256_teno8_100_steps"] = {"ms": round(el * 1e3, 3), "value": 3 * 257 * 100 / el / 1e9,
+                                     "unit": "Gface-recon/s", "note": "launch-bound: 1,542 faces per sweep"}
+    n = 1024
+    U = torch.from_numpy(inputs.grf_2d(n)).to(dev)
+    grid = tenoaa.make_grid((n, n))
+    for order in (8, 10):
+        sch = tenoaa.make_scheme(order, tenoaa.LLF, 0)
+        ws = tenoaa.workspace(grid, sch, tenoaa.WS_RHS, dev)
+        out_t = torch.empty_like(U)
+        for _ in range(2):
+            tenoaa.rhs(grid, sch, U, out=out_t, ws=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(10):
+            tenoaa.rhs(grid, sch, U, out=out_t, ws=ws)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t) / 10
+        out["2d_1024_rhs_teno%d" % order] = {"ms": round(el * 1e3, 4), "value": 2 * n * n / el / 1e9,
+                                              "unit": "Gface-recon/s"}
+    return out
 
 
 def fwd_adj_leg(shape, steps, warmup, U0, positivity):
@@ -468,6 +555,8 @@ def main():
         del U3, U2
     if not args.no_slab:
         line["slab_share"] = slab_leg(torch.from_numpy(inputs.grf_3d(n)).to(dev))
+    if not args.no_fwd_adj:
+        line["other_workloads"] = gpu_legs(dev)
     if not args.no_batched:
         line["batched"] = batched_leg(tune_cache=args.tune_cache)
     if not args.no_cpu_baseline:

@@ -165,3 +165,21 @@ def test_step_vjp_3d_256_probes_against_oracle():
         print("probe", (i, j, k, q), "oracle (J V)_c %.15e  <S^T e_c, V> %.15e  rel %.2e"
               % (lhs, rhs, abs(lhs - rhs) / ref))
         assert abs(lhs - rhs) <= 1e-11 * ref
+
+
+def test_rhs_vjp_bitwise_repeatable_prescribed_sides():
+    """Dirichlet ghosts fold into their mirror cells through the reflection
+    rule's Jacobian (the general kernel variant); inflow ghosts add nothing."""
+    from tests.test_gpu_dirichlet import _face_values, _smooth
+    D, I = tenoaa.BC_DIRICHLET, tenoaa.BC_INFLOW
+    shape, lo, hi = (37, 45), [D, S], [I, D]
+    U = _smooth(shape, 12)
+    faces = _face_values(U, shape, lo, hi, 1.4, 1, seed=21, order=10)
+    grid = tenoaa.make_grid(shape, [1.0 / n for n in shape], lo, hi,
+                            bc_values={k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in faces.items()})
+    Ud = torch.from_numpy(np.ascontiguousarray(U)).cuda()
+    R = _seed(Ud, 14)
+    sch = tenoaa.make_scheme(10, tenoaa.LLF, 0)
+    first = tenoaa.rhs_vjp(grid, sch, Ud, R)
+    for _ in range(3):
+        assert torch.equal(tenoaa.rhs_vjp(grid, sch, Ud, R), first)
