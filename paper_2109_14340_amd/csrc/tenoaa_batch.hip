@@ -9,7 +9,7 @@
 //                           UPDATE (flux difference and stage s of every cell;
 //                                   at s = 3 also the next step's wave speeds)
 //
-// Within a phase the items (tiles or 1024-cell blocks of any problem) are
+// Within a phase the items (tiles or 2048-cell blocks of any problem) are
 // handed out by an atomic counter, largest problems first; phases are
 // separated by a grid barrier (release fence, arrival count, acquire fence).
 // Every item is evaluated by the same device bodies as the per-grid kernels
@@ -42,7 +42,10 @@ namespace {
 #endif
 
 constexpr int BT = 256;         // threads per block
-constexpr int CELLS_ITEM = 1024;  // cells per update / wave-speed item
+#ifndef TENOAA_BATCH_CELLS_ITEM
+#define TENOAA_BATCH_CELLS_ITEM 2048
+#endif
+constexpr int CELLS_ITEM = TENOAA_BATCH_CELLS_ITEM;  // cells per update / wave-speed item
 constexpr int NBUCKET = 3;        // size buckets of the tile choice (by n_x)
 
 // Tile candidates (TT pencils x TN faces, 256 threads).
@@ -366,9 +369,11 @@ void batch_kernel(BatchArgs B) {
       if (first >= total) break;
       const int64_t last = (first + B.chunk < total) ? first + B.chunk : total;
       const uint64_t t_items = wall_clock64();
+      int p = -1;
       for (int64_t it = first; it < last; ++it) {
         if (it > first) __syncthreads();
-        const int p = find_problem(pre, B.nprob, it);
+        // the items of a chunk mostly belong to one problem: search only on leaving it
+        if (p < 0 || it >= pre[p + 1]) p = find_problem(pre, B.nprob, it);
         const int64_t k = it - pre[p];
         if (kind == 0) {
           speeds_item<BV>(B, arena, p, k);
