@@ -699,9 +699,8 @@ void sweep_vjp_kernel(AdjointArgs A) {
   };
   // adds Ub to where the tile cell at (ttc, nn) is read from: U_bar, or for a
   // halo cell (a neighbour piece's) the caller's halo-adjoint buffer.  The
-  // adds are atomic, at L2, so that the tiles of later launches and the ghost
-  // round below see them; their order is fixed as described at the top of
-  // this file.
+  // adds are atomic (performed at L2, where the tiles of later launches read
+  // them); their order is fixed as described at the top of this file.
   auto add_to_source = [&](int ttc, int nn, const double (&Ub)[NV]) {
     int64_t tc, l, layer;
     int gbc, side;
