@@ -185,7 +185,6 @@ __device__ __forceinline__ void sweep_item(const BatchArgs& B, char* arena, int 
   A.n[1] = P.n[1];
   A.n[2] = 1;
   A.splitting = B.splitting;
-  A.pad = 0;
   A.gamma = B.gamma;
   A.mu = nullptr;
   A.status = B.status + p;

@@ -249,7 +249,7 @@ struct Audit {
 // (flags and frozen are then taken from it).
 int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint8_t* frozen = nullptr,
            int only_dir = -1, double* fh_out = nullptr, int stage = 0, double* theta_out = nullptr,
-           const Audit* audit = nullptr) {
+           const Audit* audit = nullptr, bool pencil_major = false) {
   const tenoaa_grid* g = c.g;
   const int nv = g->ndim + 2;
   int64_t flag_off = 0;
@@ -267,6 +267,7 @@ int sweeps(const Ctx& c, const double* U, bool limit, uint8_t* flags, const uint
     a.frozen = frozen ? frozen + fo : nullptr;
     a.fh_out = fh_out;
     a.theta_out = theta_out;
+    a.rec_pencil_major = pencil_major ? 1 : 0;
     for (int k = 0; k < 3; ++k) a.n[k] = g->n[k];
     a.nf = faces_along(g, d);
     a.nft = faces_total(g, d);
@@ -324,7 +325,7 @@ int recorded_sweeps(const Ctx& c, const double* U, int st, const uint8_t* frozen
     uint8_t* flags = reinterpret_cast<uint8_t*>(c.ws + c.L.vjp[st][d]);
     double* fh = reinterpret_cast<double*>(c.ws + c.L.vjp[st][d] + c.L.vjp_fh_rel[d]);
     double* th = limit ? reinterpret_cast<double*>(c.ws + c.L.vjp[st][d] + c.L.vjp_th_rel[d]) : nullptr;
-    int rc = sweeps(c, U, limit, flags, frozen ? frozen + off : nullptr, d, fh, st, th);
+    int rc = sweeps(c, U, limit, flags, frozen ? frozen + off : nullptr, d, fh, st, th, nullptr, true);
     if (rc) return rc;
     off += (int64_t)(c.g->ndim + 2) * 2 * faces_total(c.g, d);
   }

@@ -33,7 +33,10 @@ struct SweepArgs {
   int64_t f_begin = 0;  // first face along the direction of this launch's tiles
   int bc_lo = 0, bc_hi = 0;
   int splitting = 0;
-  int pad = 0;
+  // 1: flags, fh_out and theta_out are indexed pencil by pencil (face f of
+  // pencil (t, b) at f + nf (t + n_A b)), the layout the reverse sweep reads
+  // along its waves; 0: in grid order, the layout of the C ABI's flag arrays
+  int rec_pencil_major = 0;
   double gamma = 0.0;
   const double* bcv[2] = {nullptr, nullptr};  // boundary (Dirichlet, inflow, halo) values of the low/high side, this evaluation's set, or null
   const double* mu = nullptr;  // device: limiter factors
@@ -74,9 +77,9 @@ struct AdjointArgs {
   const double* U = nullptr;       // state at which the right-hand side is differentiated
   const double* R = nullptr;       // seed: adjoint of dU/dt, layout of U
   double* Ubar = nullptr;          // accumulated in a fixed order (caller zeroes it)
-  const uint8_t* flags = nullptr;  // decisions of this direction's forward sweep at U, [nvar][2][nft]
-  const double* fh = nullptr;      // per-field fluxes of that sweep, [nvar][nft]
-  const double* theta = nullptr;   // the sweep's limiter factors per face, or null (no limiter)
+  const uint8_t* flags = nullptr;  // decisions of this direction's forward sweep at U, [nvar][2][nft], pencil by pencil
+  const double* fh = nullptr;      // per-field fluxes of that sweep, [nvar][nft], pencil by pencil
+  const double* theta = nullptr;   // the sweep's limiter factors per face (pencil by pencil), or null (no limiter)
   const double* bcv[2] = {nullptr, nullptr};  // boundary values of the low/high side (Dirichlet, inflow, halo), else null
   double* hbar[2] = {nullptr, nullptr};       // adjoints of the low/high halo cells (accumulated), or null
   int64_t nft = 0;

@@ -330,7 +330,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     const int64_t fstr[3] = {1, m[0], m[0] * m[1]};
     flin = f * fstr[DIR] + t * fstr[AX_A] + bcoord * fstr[AX_B];
   }
-  uint8_t* const flag_out = A.flags ? A.flags + flin : nullptr;
+  // the recording for the reverse sweep is pencil by pencil (the same as grid
+  // order along x)
+  const int64_t frec = A.rec_pencil_major ? f + A.nf * (t + nA * bcoord) : flin;
+  uint8_t* const flag_out = A.flags ? A.flags + frec : nullptr;
   const uint8_t* const frozen = A.frozen ? A.frozen + flin : nullptr;
 
   double Fh[NV];  // back-projected flux, local frame
@@ -455,7 +458,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
       flag_out[(int64_t)(s * 2 + 1) * A.nft] = flm;
     }
     const double fh = (!ROE || upwind == 0) ? hp + hm : (upwind == 1 ? hp : hm);
-    if (A.fh_out) A.fh_out[(int64_t)s * A.nft + flin] = fh;
+    if (A.fh_out) A.fh_out[(int64_t)s * A.nft + frec] = fh;
     // back-projection F = sum_s R[:, s] fh_s, accumulated over s in order
     double r1 = 0.0, re = 0.0;
     if (s == 0) {
@@ -555,7 +558,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     });
     unroll<NV>([&](auto c) { Fh[c] = (th_p < 1.0) ? FL[c] + th_p * (Fs[c] - FL[c]) : Fs[c]; });
     // for the adjoint: the flux is F_LF + theta (F_H - F_LF) with theta = theta_rho theta_p
-    if (A.theta_out) A.theta_out[flin] = th_r * th_p;
+    if (A.theta_out) A.theta_out[frec] = th_r * th_p;
   } else {
     (void)mu;
   }

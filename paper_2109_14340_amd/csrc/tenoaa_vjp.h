@@ -255,13 +255,9 @@ void sweep_vjp_kernel(AdjointArgs A) {
   constexpr int LSTEP = 1;
   const int ia = lbase + (G - 1) * LSTEP, ib = lbase + G * LSTEP;
 
-  int64_t flin = 0;
-  {
-    int64_t m[3] = {A.n[0], A.n[1], A.n[2]};
-    m[DIR] = A.nf;
-    const int64_t fstr[3] = {1, m[0], m[0] * m[1]};
-    flin = f * fstr[DIR] + t * fstr[AX_A] + bcoord * fstr[AX_B];
-  }
+  // the face's recorded decisions, fluxes and limiter factor, laid out
+  // pencil by pencil by the forward sweep (a wave reads consecutive faces)
+  const int64_t frec = f + A.nf * (t + nA * bcoord);
   if (active) {
     // seed of the face flux: dU_i = -(F_{i+1} - F_i)/dx gives
     // Fbar_f = (R_f - R_{f-1}) / dx over the cells that exist
@@ -289,7 +285,7 @@ void sweep_vjp_kernel(AdjointArgs A) {
     // F_LF = (F_a + F_b - a_L (W_b - W_a)) / 2 with a_L = max(|u_n| + c) of the
     // two cells (that cell frozen); F_H continues below with seed theta Fbar
     if (A.theta) {
-      const double th = A.theta[flin];
+      const double th = A.theta[frec];
       if (th < 1.0) {
         const double sA = fabs(sUn[ia]) + sC[ia], sB = fabs(sUn[ib]) + sC[ib];
         const bool onA = sA >= sB;
@@ -366,7 +362,7 @@ void sweep_vjp_kernel(AdjointArgs A) {
     unroll<NV>([&](auto ss) {
       constexpr int s = decltype(ss)::value;
       constexpr bool shear = (s >= 2 && s <= NV - 2);
-      const double fh = A.fh[(int64_t)s * A.nft + flin];
+      const double fh = A.fh[(int64_t)s * A.nft + frec];
       if constexpr (!shear) {
         const double r1 = (s == 0) ? un - cr : (s == 1 ? un : un + cr);
         const double re = (s == 0) ? Hr - un * cr : (s == 1 ? qq : Hr + un * cr);
@@ -417,8 +413,8 @@ void sweep_vjp_kernel(AdjointArgs A) {
     bool one_side[NV];
     unroll<NV>([&](auto ss) {
       constexpr int s = decltype(ss)::value;
-      const uint8_t bp = A.flags[(int64_t)(2 * s) * A.nft + flin];
-      const uint8_t bm = A.flags[(int64_t)(2 * s + 1) * A.nft + flin];
+      const uint8_t bp = A.flags[(int64_t)(2 * s) * A.nft + frec];
+      const uint8_t bm = A.flags[(int64_t)(2 * s + 1) * A.nft + frec];
       rowp[s] = weight_row<ORDER>(bp);
       rowm[s] = weight_row<ORDER>(bm);
       one_side[s] = GENERAL && A.splitting == TENOAA_ROE && (bp == 0 || bm == 0);
