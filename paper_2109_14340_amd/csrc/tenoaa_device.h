@@ -194,9 +194,28 @@ __device__ __forceinline__ double linear_flux(const double (&v)[W]) {
 // gets 1 if a test the reconstruction made lies within the relative distance
 // tol of its threshold (chi_p / C_T or chi_k / C_T within 1 +- tol, or the
 // cut-off exponent B within tol B of an integer while m > 0), else 0.
+// The TENO5 fallback's flux once its deltas are decided (Sec. 3.3): the
+// renormalised weights of the kept small stencils times their third-order
+// candidates.  Shared by teno_aa and replay_recon, outside teno_aa's
+// contracted decision arithmetic.
+template <int ORDER>
+__device__ __forceinline__ double fallback_flux(const double (&v)[ORDER], int dm) {
+  constexpr int I = ORDER / 2 - 1;
+  const double fm1 = v[I - 1], f0 = v[I], f1 = v[I + 1];
+  const double h0 = div6((-fm1 + 5.0 * f0) + 2.0 * f1);
+  const double h1 = div6((2.0 * f0 + 5.0 * f1) - v[I + 2]);
+  const double h2 = div6((2.0 * v[I - 2] - 7.0 * fm1) + 11.0 * f0);
+  return fma(WFALL.w[dm][2], h2, fma(WFALL.w[dm][1], h1, WFALL.w[dm][0] * h0));
+}
+
 template <int ORDER, bool AUDIT = false>
 __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& flag, uint8_t* near = nullptr,
                                           double tol = 0.0) {
+  // every operation written in this body is decision-only (the fluxes come
+  // from linear_flux and fallback_flux), so the compiler may fuse its
+  // multiply-adds: a decision then differs from the oracle's only within a
+  // few ulps of its threshold, inside the band the parity checks exclude
+#pragma clang fp contract(fast)
   constexpr int G = ORDER / 2;
   constexpr int I = G - 1;  // index of f_i
 
@@ -287,11 +306,7 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   if constexpr (AUDIT) *near |= (close(g0, cs) || close(g1, cs) || close(g2, cs)) ? 1 : 0;
   const int dm = (g0 >= cs ? 1 : 0) | (g1 >= cs ? 2 : 0) | (g2 >= cs ? 4 : 0);
   flag = (uint8_t)((dm << 2) | kbits);
-  const double fm1 = v[I - 1], f0 = v[I], f1 = v[I + 1];
-  const double h0 = div6((-fm1 + 5.0 * f0) + 2.0 * f1);
-  const double h1 = div6((2.0 * f0 + 5.0 * f1) - v[I + 2]);
-  const double h2 = div6((2.0 * v[I - 2] - 7.0 * fm1) + 11.0 * f0);
-  return fma(WFALL.w[dm][2], h2, fma(WFALL.w[dm][1], h1, WFALL.w[dm][0] * h0));
+  return fallback_flux<ORDER>(v, dm);
 }
 
 // The reconstruction a recorded decision byte selects, evaluated exactly as
@@ -299,7 +314,6 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
 template <int ORDER>
 __device__ __forceinline__ double replay_recon(const double (&v)[ORDER], uint8_t flag) {
   constexpr int G = ORDER / 2;
-  constexpr int I = G - 1;
   const int sel = flag & 3;
   if constexpr (ORDER == 12) {
     if (sel == 3 && (flag & 4)) return linear_flux<12, 0>(v);
@@ -309,12 +323,7 @@ __device__ __forceinline__ double replay_recon(const double (&v)[ORDER], uint8_t
   }
   if (sel == 2) return linear_flux<8, G - 4>(v);
   if (sel == 1) return linear_flux<6, G - 3>(v);
-  const int dm = (flag >> 2) & 7;
-  const double fm1 = v[I - 1], f0 = v[I], f1 = v[I + 1];
-  const double h0 = div6((-fm1 + 5.0 * f0) + 2.0 * f1);
-  const double h1 = div6((2.0 * f0 + 5.0 * f1) - v[I + 2]);
-  const double h2 = div6((2.0 * v[I - 2] - 7.0 * fm1) + 11.0 * f0);
-  return fma(WFALL.w[dm][2], h2, fma(WFALL.w[dm][1], h1, WFALL.w[dm][0] * h0));
+  return fallback_flux<ORDER>(v, (flag >> 2) & 7);
 }
 
 // Local frame of direction DIR: component 0 = rho, 1 = normal momentum,
