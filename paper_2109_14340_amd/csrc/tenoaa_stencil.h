@@ -336,33 +336,29 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
   uint8_t* const flag_out = A.flags ? A.flags + frec : nullptr;
   const uint8_t* const frozen = A.frozen ? A.frozen + flin : nullptr;
 
-  double Fh[NV];  // back-projected flux, local frame
-  unroll<NV>([&](auto c) { Fh[c] = 0.0; });
-#pragma unroll 1
-  for (int s = 0; s < NV; ++s) {
-    const bool shear = (s >= 2 && s <= NV - 2);
-    const bool acoustic = (s == 0 || s == NV - 1);
+  // One characteristic field s (a compile-time constant, so its eigenvector
+  // row, splitting speed and projection form are fixed in the code): the
+  // projection of the window, the split and the reconstructions of both
+  // sides.  Returns fh_s.
+  auto field = [&](auto sc) -> double {
+    constexpr int s = decltype(sc)::value;
+    constexpr bool shear = (s >= 2 && s <= NV - 2);
     // left eigenvector row s (local frame), the reading of the Roe eigenvectors
     double L[NV];
-    if (acoustic) {
+    if constexpr (s == 0 || s == NV - 1) {
       L[0] = (s == 0) ? 0.5 * (b2 + unc) : 0.5 * (b2 - unc);
       L[1] = (s == 0) ? 0.5 * (-b1 * un - ic) : 0.5 * (-b1 * un + ic);
       unroll<NDIM - 1>([&](auto k) { L[2 + k] = 0.5 * (-b1 * ut[k]); });
       L[NV - 1] = 0.5 * b1;
-    } else {
+    } else if constexpr (s == 1) {
       L[0] = 1.0 - b2;
       L[1] = b1 * un;
       unroll<NDIM - 1>([&](auto k) { L[2 + k] = b1 * ut[k]; });
       L[NV - 1] = -b1;
     }
-    double mut = 0.0;
-    int sl = 2;
-    if constexpr (NDIM == 3) {
-      mut = (s == 3) ? -ut[1] : -ut[0];
-      sl = s;
-    } else if constexpr (NDIM == 2) {
-      mut = -ut[0];
-    }
+    // shear field s: the tangential momentum of local slot s less u_t rho
+    [[maybe_unused]] double mut = 0.0;
+    if constexpr (shear) mut = -ut[s - 2];
     const double alpha = (s == 0) ? am : (s == NV - 1 ? ap : a0);
     // Roe flux with entropy fix: where the field's eigenvalue keeps one
     // strict sign at both cells of the face, the unsplit characteristic flux
@@ -374,7 +370,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
         const uint8_t bp = frozen[(int64_t)(s * 2 + 0) * A.nft], bm = frozen[(int64_t)(s * 2 + 1) * A.nft];
         upwind = bm == 0 ? 1 : (bp == 0 ? 2 : 0);
       } else {
-        const double ka = (s == 0) ? -1.0 : (s == NV - 1 ? 1.0 : 0.0);
+        constexpr double ka = (s == 0) ? -1.0 : (s == NV - 1 ? 1.0 : 0.0);
         const double la = sUn[ia] + ka * sC[ia], lb = sUn[ib] + ka * sC[ib];
         upwind = (la > 0.0 && lb > 0.0) ? 1 : ((la < 0.0 && lb < 0.0) ? 2 : 0);
       }
@@ -384,7 +380,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     unroll<W>([&](auto j) {
       const int li = lbase + j * LSTEP;
       double v, g;
-      if (!shear) {
+      if constexpr (!shear) {
         const double2 w0 = sWF[li];
         v = L[0] * w0.x;
         g = L[0] * w0.y;
@@ -394,8 +390,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
           g = fma(L[cc + 1], w.y, g);
         });
       } else {
+        // the row's other entries are zero and its entry at slot s is one
         const double2 w0 = sWF[li];
-        const double2 ws = sWF[sl * NCT + li];
+        const double2 ws = sWF[s * NCT + li];
         v = mut * w0.x + ws.x;
         g = mut * w0.y + ws.y;
       }
@@ -459,36 +456,41 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& A, char* lds, int64_
     }
     const double fh = (!ROE || upwind == 0) ? hp + hm : (upwind == 1 ? hp : hm);
     if (A.fh_out) A.fh_out[(int64_t)s * A.nft + frec] = fh;
-    // back-projection F = sum_s R[:, s] fh_s, accumulated over s in order
-    double r1 = 0.0, re = 0.0;
-    if (s == 0) {
-      r1 = un - cr;
-      re = Hr - un * cr;
-    } else if (s == NV - 1) {
-      r1 = un + cr;
-      re = Hr + un * cr;
-    } else if (s == 1) {
-      r1 = un;
-      re = qq;
-    } else {
-      if constexpr (NDIM == 3) re = (s == 3) ? ut[1] : ut[0];
-      else if constexpr (NDIM == 2) re = ut[0];
-    }
-    const double r0 = shear ? 0.0 : 1.0;
-    if (s == 0) {
-      Fh[0] = r0 * fh;
-      Fh[1] = r1 * fh;
-      unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = ut[k] * fh; });
-      Fh[NV - 1] = re * fh;
-    } else {
-      Fh[0] = fma(r0, fh, Fh[0]);
-      Fh[1] = fma(r1, fh, Fh[1]);
-      unroll<NDIM - 1>([&](auto k) {
-        const double rk = shear ? (s == 2 + (int)k ? 1.0 : 0.0) : ut[k];
-        Fh[2 + k] = fma(rk, fh, Fh[2 + k]);
-      });
-      Fh[NV - 1] = fma(re, fh, Fh[NV - 1]);
-    }
+    return fh;
+  };
+  // every field its own code; a scheduling barrier between two fields keeps
+  // their working sets from overlapping (register pressure)
+  double fhs[NV];
+  unroll<NV>([&](auto sc) {
+    fhs[sc] = field(sc);
+    __builtin_amdgcn_sched_barrier(0);
+  });
+
+  // back-projection F = sum_s R[:, s] fh_s, accumulated over s in order; the
+  // zero entries of a shear field's column add nothing (skipped) and its unit
+  // entry is an addition
+  double Fh[NV];  // back-projected flux, local frame
+  {
+    const double fa = fhs[0];
+    Fh[0] = fa;
+    Fh[1] = (un - cr) * fa;
+    unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = ut[k] * fa; });
+    Fh[NV - 1] = (Hr - un * cr) * fa;
+    const double fe = fhs[1];
+    Fh[0] = Fh[0] + fe;
+    Fh[1] = fma(un, fe, Fh[1]);
+    unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = fma(ut[k], fe, Fh[2 + k]); });
+    Fh[NV - 1] = fma(qq, fe, Fh[NV - 1]);
+    unroll<NDIM - 1>([&](auto k) {
+      const double fk = fhs[2 + k];
+      Fh[2 + k] = Fh[2 + k] + fk;
+      Fh[NV - 1] = fma(ut[k], fk, Fh[NV - 1]);
+    });
+    const double fz = fhs[NV - 1];
+    Fh[0] = Fh[0] + fz;
+    Fh[1] = fma(un + cr, fz, Fh[1]);
+    unroll<NDIM - 1>([&](auto k) { Fh[2 + k] = fma(ut[k], fz, Fh[2 + k]); });
+    Fh[NV - 1] = fma(Hr + un * cr, fz, Fh[NV - 1]);
   }
 
   if constexpr (LIMIT) {
