@@ -20,6 +20,10 @@ constexpr double C_R = 0.265;
 constexpr double ALPHA1 = 14.0;
 constexpr double ALPHA2 = 6.4;
 constexpr double CT_TABLE[8] = {1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12, 1e-13, 1e-14};
+// 1/C_T - 1 = 10^K - 1 (exact doubles), the bound of the large-stencil test
+// in the form S b^7 <= 1/C_T - 1 (teno_aa)
+constexpr double INV_CT_M1[8] = {9999999.0,      99999999.0,      999999999.0,      9999999999.0,
+                                 99999999999.0, 999999999999.0, 9999999999999.0, 99999999999999.0};
 // Sec. 4.1 / 4.2: linear schemes on S3, S4, S5, leftmost coefficient first.
 constexpr double LIN6[6] = {0.02852274270130377, -0.1714015614372447, 0.650378818735941,
                             0.6253788187359414, -0.1589015614372448, 0.02602274270130375};
@@ -246,6 +250,7 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   int K = (int)floor(B);
   K = K < 7 ? 7 : (K > 14 ? 14 : K);
   const double CT = CT_TABLE[K - 7];
+  const double TK = INV_CT_M1[K - 7];
   const uint8_t kbits = (uint8_t)((K - 7) << 5);
   // chi / C_T - 1 = (g - t) / t for the test g >= t
   [[maybe_unused]] auto close = [&](double g, double t) { return fabs(g - t) <= tol * t; };
@@ -263,40 +268,62 @@ __device__ __forceinline__ double teno_aa(const double (&v)[ORDER], uint8_t& fla
   const double g1 = gamma7(fma(C13, b1b * b1b, 0.25 * (b1a * b1a)));
   const double g2 = gamma7(fma(C13, b2b * b2b, 0.25 * (b2a * b2a)));
   const double S = (g0 + g1) + g2;
+  // Sec. 3.3's test of a large stencil, gamma_p >= C_T (S + gamma_p) with
+  // gamma_p = 1/b^7 (b = beta_p + eps), taken as S b^7 <= 1/C_T - 1: the
+  // same inequality without the reciprocal of b (decision-only; an overflow
+  // of S b^7 fails the test, as the exact ratio does)
+  auto passes = [&](double beta) {
+    const double b = beta + EPS;
+    const double b2 = b * b;
+    const double b4 = b2 * b2;
+    return S * ((b4 * b2) * b) <= TK;
+  };
 
   // Sec. 3.3: the groups (S0,S1,S2,Sp), largest p first; Sp is taken when
   // chi_p = gamma_p / (S + gamma_p) >= C_T.  Stencil Sp starts at v[G - p].
   if constexpr (ORDER == 12) {
-    const double gp = gamma7(sos_beta<12, 0>(v));
-    if constexpr (AUDIT) *near |= close(gp, CT * (S + gp)) ? 1 : 0;
-    if (gp >= CT * (S + gp)) {
+    const double bp = sos_beta<12, 0>(v);
+    if constexpr (AUDIT) {
+      const double gp = gamma7(bp);
+      *near |= close(gp, CT * (S + gp)) ? 1 : 0;
+    }
+    if (passes(bp)) {
       flag = (uint8_t)(7 | kbits);
       return linear_flux<12, 0>(v);
     }
   }
   if constexpr (ORDER >= 10) {
     constexpr int P = G - 5;
-    const double gp = gamma7(sos_beta<10, P>(v));
-    if constexpr (AUDIT) *near |= close(gp, CT * (S + gp)) ? 1 : 0;
-    if (gp >= CT * (S + gp)) {
+    const double bp = sos_beta<10, P>(v);
+    if constexpr (AUDIT) {
+      const double gp = gamma7(bp);
+      *near |= close(gp, CT * (S + gp)) ? 1 : 0;
+    }
+    if (passes(bp)) {
       flag = (uint8_t)(3 | kbits);
       return linear_flux<10, P>(v);
     }
   }
   {
     constexpr int P = G - 4;
-    const double gp = gamma7(sos_beta<8, P>(v));
-    if constexpr (AUDIT) *near |= close(gp, CT * (S + gp)) ? 1 : 0;
-    if (gp >= CT * (S + gp)) {
+    const double bp = sos_beta<8, P>(v);
+    if constexpr (AUDIT) {
+      const double gp = gamma7(bp);
+      *near |= close(gp, CT * (S + gp)) ? 1 : 0;
+    }
+    if (passes(bp)) {
       flag = (uint8_t)(2 | kbits);
       return linear_flux<8, P>(v);
     }
   }
   {
     constexpr int P = G - 3;
-    const double gp = gamma7(sos_beta<6, P>(v));
-    if constexpr (AUDIT) *near |= close(gp, CT * (S + gp)) ? 1 : 0;
-    if (gp >= CT * (S + gp)) {
+    const double bp = sos_beta<6, P>(v);
+    if constexpr (AUDIT) {
+      const double gp = gamma7(bp);
+      *near |= close(gp, CT * (S + gp)) ? 1 : 0;
+    }
+    if (passes(bp)) {
       flag = (uint8_t)(1 | kbits);
       return linear_flux<6, P>(v);
     }
